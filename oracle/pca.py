@@ -1,0 +1,169 @@
+"""Algorithm 4 (single-pass PCA) and Algorithm 1 (basic randomised SVD), plain FP64.
+
+Test infrastructure only (see the package docstring).  Notation follows the paper: A is m x n and
+row-major, Omega is n x l with l = t*b, G = A Omega (m x l), H = A^T G (n x l), Q (m x l) and
+B (l x n) are built one column block of width b at a time.
+"""
+from dataclasses import dataclass, field
+import numpy as np
+from scipy.linalg import solve_triangular
+
+
+@dataclass
+class PCAResult:
+    S: np.ndarray                 # k singular values, descending, zero-padded past the rank
+    V: np.ndarray                 # n x k right singular vectors (principal components)
+    U: np.ndarray                 # m x k left singular vectors (None when not requested)
+    rank: int                     # number of basis vectors kept (l unless the guard stopped early)
+    G: np.ndarray = None
+    H: np.ndarray = None
+    Q: np.ndarray = None
+    B: np.ndarray = None
+    R: list = field(default_factory=list)
+
+
+def _qr_nonneg(X):
+    """Economy QR without pivoting (the paper's qr(X,0), Sec. 2.2), normalised so diag(R) >= 0."""
+    Q, R = np.linalg.qr(X, mode="reduced")
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d, R * d[:, None]
+
+
+def sketch_pass(blocks, Omega):
+    """The single pass of Algorithm 4 (steps 3-8) and Eq. (10).
+
+    For each block a of consecutive rows: g = a Omega is appended to G, and H accumulates a^T g,
+    so that H = sum over rows of a_r^T g_r = A^T G.  Each block is converted to FP64 on arrival,
+    as the paper does with its single-precision files (Sec. 4.2).
+    """
+    Omega = np.asarray(Omega, dtype=np.float64)
+    n, l = Omega.shape
+    H = np.zeros((n, l))
+    G_parts = []
+    for a in blocks:
+        a = np.asarray(a, dtype=np.float64)
+        if a.ndim != 2 or a.shape[1] != n:
+            raise ValueError("every row block must have n columns")
+        g = a @ Omega
+        G_parts.append(g)
+        H += a.T @ g
+    G = np.vstack(G_parts) if G_parts else np.zeros((0, l))
+    return G, H
+
+
+def qb_from_sketch(G, H, Omega, b, tau=1e-10):
+    """The column-block loop of Algorithm 4 (steps 9-15) with the re-orthogonalisation of Sec. 3.2.
+
+    For i = 1..t, on columns c = (i-1)b+1 : ib:
+      Y_i = G(:,c) - Q (B Omega_i)                        (first iteration: Q, B empty, term dropped)
+      [Q_i, R_i] = qr(Y_i)
+      [Q_i, R~_i] = qr(Q_i - Q (Q^T Q_i))                 (Eq. 7)
+      R_i = R~_i R_i
+      B_i = R_i^{-T} (H(:,c)^T - Y_i^T Q B - Omega_i^T B^T B)   (Eq. 9)
+      Q = [Q, Q_i];  B = [B; B_i]
+    Rank guard (a reading; the paper assumes full-rank sketches, Sec. 3.1 proof): with r0 the first
+    diagonal entry of the first combined R, keep only the leading columns of a block whose combined
+    R diagonal exceeds tau*r0, and stop the loop at the first block that loses a column.
+    Returns (Q, B, rank, R_list).
+    """
+    G = np.asarray(G, dtype=np.float64)
+    H = np.asarray(H, dtype=np.float64)
+    Omega = np.asarray(Omega, dtype=np.float64)
+    m, l = G.shape
+    n = H.shape[0]
+    if l % b != 0:
+        raise ValueError("l must be a multiple of b")
+    t = l // b
+    Q = np.zeros((m, 0))
+    B = np.zeros((0, n))
+    R_list = []
+    r0 = None
+    for i in range(t):
+        c = np.arange(i * b, (i + 1) * b)
+        Omega_i = Omega[:, c]
+        Y = G[:, c] - Q @ (B @ Omega_i)
+        Qi, Ri = _qr_nonneg(Y)
+        Qi, Rt = _qr_nonneg(Qi - Q @ (Q.T @ Qi))
+        Ri = Rt @ Ri
+        if r0 is None:
+            r0 = Ri[0, 0]
+        d = np.abs(np.diag(Ri))
+        keep = 0
+        while keep < len(c) and d[keep] > tau * r0:
+            keep += 1
+        if keep < len(c):
+            c, Qi, Ri, Y = c[:keep], Qi[:, :keep], Ri[:keep, :keep], Y[:, :keep]
+        if keep > 0:
+            numer = H[:, c].T - (Y.T @ Q) @ B - (B @ Omega[:, c]).T @ B
+            Bi = solve_triangular(Ri.T, numer, lower=True)
+            Q = np.hstack([Q, Qi])
+            B = np.vstack([B, Bi])
+            R_list.append(Ri)
+        if keep < b:
+            break
+    return Q, B, Q.shape[1], R_list
+
+
+def apply_sign_convention(U, V):
+    """Flip each (u_j, v_j) pair so the largest-magnitude entry of v_j is positive.
+
+    The paper leaves singular-vector signs open; this reading breaks ties by the lowest index.
+    """
+    V = V.copy()
+    U = None if U is None else U.copy()
+    for j in range(V.shape[1]):
+        col = V[:, j]
+        if not np.any(col):
+            continue
+        p = int(np.argmax(np.abs(col)))
+        if col[p] < 0:
+            V[:, j] = -col
+            if U is not None:
+                U[:, j] = -U[:, j]
+    return U, V
+
+
+def svd_from_qb(Q, B, k, want_u=True):
+    """Steps 16-19 of Algorithm 4: [U~, S, V] = svd(B), U = Q U~, keep the first k.
+
+    Columns past the computed rank are returned as zeros.
+    """
+    m, r = Q.shape
+    n = B.shape[1]
+    S = np.zeros(k)
+    V = np.zeros((n, k))
+    U = np.zeros((m, k)) if want_u else None
+    if r > 0:
+        Ut, s, Vt = np.linalg.svd(B, full_matrices=False)
+        kk = min(k, len(s))
+        S[:kk] = s[:kk]
+        V[:, :kk] = Vt[:kk].T
+        if want_u:
+            U[:, :kk] = Q @ Ut[:, :kk]
+    U, V = apply_sign_convention(U, V)
+    return S, U, V
+
+
+def single_pass_pca(blocks, Omega, k, b, tau=1e-10, want_u=True, keep_state=False):
+    """Algorithm 4 end to end on an iterable of row blocks (the rows of A in order)."""
+    Omega = np.asarray(Omega, dtype=np.float64)
+    l = Omega.shape[1]
+    if not (1 <= k <= l):
+        raise ValueError("need 1 <= k <= l")
+    G, H = sketch_pass(blocks, Omega)
+    Q, B, rank, Rs = qb_from_sketch(G, H, Omega, b, tau)
+    S, U, V = svd_from_qb(Q, B, k, want_u)
+    res = PCAResult(S=S, V=V, U=U, rank=rank)
+    if keep_state:
+        res.G, res.H, res.Q, res.B, res.R = G, H, Q, B, Rs
+    return res
+
+
+def basic_randqb_svd(A, Omega, k, want_u=True):
+    """Algorithm 1 (two passes over A): Q = orth(A Omega), B = Q^T A, svd(B), U = Q U~."""
+    A = np.asarray(A, dtype=np.float64)
+    Q, _ = _qr_nonneg(A @ Omega)
+    B = Q.T @ A
+    S, U, V = svd_from_qb(Q, B, k, want_u)
+    return PCAResult(S=S, V=V, U=U, rank=Q.shape[1], Q=Q, B=B)
