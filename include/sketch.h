@@ -1,0 +1,169 @@
+/*
+ * sketch.h - C ABI of the MI355X single-pass PCA library.
+ *
+ * The library computes the truncated SVD / PCA of a dense m x n row-major matrix A that is seen
+ * once, in row blocks, following Algorithm 4 of Yu, Gu, Li, Liu and Li, "Single-Pass PCA of Large
+ * High-Dimensional Data" (IJCAI 2017):
+ *
+ *   sketch_init / sketch_reset   Omega = randn(n, l), G = [], H = 0           (Alg. 4, steps 1-3)
+ *   sketch_ingest_block          g = a Omega; G = [G; g]; H = H + a^T g       (Alg. 4, steps 4-8;
+ *                                                                              Eq. 10)
+ *   sketch_finalize              column-block loop with re-orthogonalisation  (Alg. 4, steps 9-15;
+ *                                (Eqs. 7-9), then [U~, S, V] = svd(B),         steps 16-19)
+ *                                U = Q U~, truncation to k
+ *
+ * Conventions
+ *   - Every call returns a sketch_status and never aborts or throws across the ABI.  On failure
+ *     sketch_last_error() returns a thread-local message describing the last error.
+ *   - "device pointer" means memory on the GPU the handle was created on (from hipMalloc or a
+ *     PyTorch CUDA tensor); "pinned host pointer" means memory from hipHostMalloc (or a PyTorch
+ *     pinned tensor).  Pageable host memory is rejected with SKETCH_E_INVAL.
+ *   - Matrices are row-major with an explicit leading dimension counted in elements.
+ *   - The library never allocates device memory: all device state lives in a caller-owned
+ *     workspace of sketch_workspace_size() bytes.  It owns one copy stream and a few events.
+ *   - Kernels run on the caller's HIP stream given at init.  A handle is not thread-safe;
+ *     distinct handles may be used concurrently.
+ *   - Any HIP runtime error makes the handle sticky in SKETCH_E_DEVICE; only sketch_destroy is
+ *     then valid.  A block holding a NaN or Inf makes it sticky in SKETCH_E_NONFINITE, reported
+ *     by the next call that synchronises (sketch_poll, sketch_finalize).
+ */
+#ifndef SKETCH_H
+#define SKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sketch_s* sketch_t;
+
+typedef enum {
+  SKETCH_OK = 0,
+  SKETCH_E_INVAL = 1,      /* bad argument or unsupported combination */
+  SKETCH_E_STATE = 2,      /* call not valid in the handle's state (e.g. ingest after finalize) */
+  SKETCH_E_NOMEM = 3,      /* workspace too small */
+  SKETCH_E_CAPACITY = 4,   /* more rows than m_capacity, or a block larger than max_block_rows */
+  SKETCH_E_NONFINITE = 5,  /* an ingested block held NaN or Inf (sticky) */
+  SKETCH_E_DEVICE = 6      /* a HIP runtime error (sticky) */
+} sketch_status;
+
+/* Element formats.  As a source format: the type of the rows passed to sketch_ingest_block.
+ * As a compute mode: the arithmetic of the two streaming products g = a Omega and a^T g.
+ *   F64        FP64 operands, FP64 accumulation (the paper's precision, Sec. 4.2).
+ *   F32        FP32 operands, FP32 accumulation within a block, FP64 accumulation of H.
+ *   BF16       a and Omega rounded to BF16 (RNE); g kept in FP32 and fed to a^T g as a BF16
+ *              hi + lo pair; FP32 accumulation within a block, FP64 accumulation of H.
+ *   BF16X2     a split as bf16(a) + bf16(a - bf16(a)); otherwise as BF16.
+ *   FP8_E4M3   a scaled by a power of two per row block (largest with amax * 2^e <= 448) and
+ *              rounded to OCP E4M3; Omega' = e4m3(32 fp32(Omega)) / 32; a^T g uses the same a'
+ *              with g as a BF16 hi + lo pair.
+ * In every mode G is stored in FP32 (FP64 in F64 mode) and everything after the pass (the
+ * column-block loop and the SVD of B) runs in FP64.  Omega' (Omega rounded to the operand format)
+ * is the matrix used by every step, and is what sketch_get_omega returns. */
+typedef enum {
+  SKETCH_F64 = 0,
+  SKETCH_F32 = 1,
+  SKETCH_BF16 = 2,
+  SKETCH_BF16X2 = 3,
+  SKETCH_FP8_E4M3 = 4
+} sketch_dtype;
+
+typedef struct {
+  int64_t n;               /* columns of A (>= 1) */
+  int64_t m_capacity;      /* most rows the handle will ingest in total (>= 1) */
+  int64_t max_block_rows;  /* largest nrows of one sketch_ingest_block call (>= 1) */
+  int32_t k;               /* number of singular triplets returned, 1 <= k <= l */
+  int32_t l;               /* sketch width; l = t*b "slightly larger than k" (Alg. 4 step 2),
+                              l <= n, l <= 128 */
+  int32_t b;               /* column block width of the finalize loop; l % b == 0, 1 <= b <= 32 */
+  int32_t compute;         /* sketch_dtype compute mode */
+  int32_t host_slots;      /* device staging slots for pinned-host sources: 0 (device sources
+                              only) or 2..4 (copies overlap compute on a side stream) */
+  int32_t host_src;        /* sketch_dtype of host rows when host_slots > 0: F32, F64 or BF16 */
+  int32_t want_u;          /* 1: finalize may return U (m x k) */
+  int32_t omega_from_seed; /* 1: Omega drawn on the device from `seed` (Philox-4x64-10 + Box-Muller,
+                              entry (r, c) from words 2(r l + c) and 2(r l + c) + 1 of the stream
+                              with key (seed, 0)); 0: supplied by sketch_set_omega */
+  uint64_t seed;
+} sketch_config;
+
+/* Device bytes the workspace must hold for `cfg`; 0 if cfg is invalid (see sketch_last_error). */
+size_t sketch_workspace_size(const sketch_config* cfg);
+
+/* Creates a handle whose state lives in `dev_ws` (device pointer, >= sketch_workspace_size bytes,
+ * 256-byte aligned, owned by the caller and kept alive until sketch_destroy).  `hip_stream` is the
+ * hipStream_t all kernels are launched on (NULL = the null stream).  With omega_from_seed = 1,
+ * Omega is generated here (Alg. 4 step 3); H is zeroed.  Enqueues work and returns at once. */
+sketch_status sketch_init(sketch_t* out, const sketch_config* cfg, void* dev_ws, size_t ws_bytes,
+                          void* hip_stream);
+
+/* Starts a new pass on the same handle and workspace: zero rows, H = 0, and a new Omega drawn
+ * from `seed` when the handle draws its own (Alg. 4 steps 1-3).  Valid in any non-sticky state. */
+sketch_status sketch_reset(sketch_t h, uint64_t seed);
+
+/* Supplies Omega (n x l, FP64, row-major with leading dimension ld >= l, device pointer) for a
+ * handle created with omega_from_seed = 0.  Must precede the first ingest.  The library rounds it
+ * to the operand format of the compute mode (Omega').  The caller's buffer may be freed after the
+ * call returns and the stream has passed it. */
+sketch_status sketch_set_omega(sketch_t h, const double* omega_dev, int64_t ld);
+
+/* Ingests the next nrows rows of A (Alg. 4 steps 5-7): `rows` points at an nrows x n row-major
+ * block with leading dimension ld >= n, of format `src_dtype`, either in device memory
+ * (src_is_device = 1; F64, F32 or BF16) or in pinned host memory (src_is_device = 0; requires
+ * host_slots > 0 and src_dtype == host_src).  Asynchronous: a host block must stay unchanged until
+ * sketch_poll reports its ticket done; a device block until the stream passes this point.
+ * Errors: E_INVAL (bad arguments, pageable host memory), E_CAPACITY (nrows > max_block_rows or
+ * the total exceeds m_capacity), E_STATE (after finalize or before Omega is set). */
+sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtype, int64_t nrows,
+                                  int64_t ld, int32_t src_is_device, uint64_t* ticket);
+
+/* *done = 1 once the host buffer of `ticket` may be reused (its copy to the device finished);
+ * device-source tickets are done when their kernels finished.  Non-blocking. */
+sketch_status sketch_poll(sketch_t h, uint64_t ticket, int32_t* done);
+
+/* Runs Alg. 4 steps 9-19 on the stream and waits for it.  Outputs (device pointers):
+ *   S_dev  k doubles, descending;
+ *   V_dev  n x k row-major, leading dimension ldv >= k (principal components);
+ *   U_dev  m x k row-major, ldu >= k, or NULL (requires want_u = 1 when non-NULL);
+ *   rank_out  number of basis vectors kept (l unless the rank guard stopped the loop early).
+ * Singular pairs are signed so the largest-magnitude entry of each v_j is positive (lowest index
+ * on ties).  Columns past min(k, rank) are zero.  Rank guard (a reading: the paper assumes a
+ * full-rank sketch): with r0 the first diagonal of the first combined R, a block keeps only its
+ * leading columns whose combined R diagonal exceeds 1e-10 r0, and the loop stops there.
+ * The handle then rejects ingest (E_STATE) until sketch_reset. */
+sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t ldu, double* V_dev,
+                              int64_t ldv, int32_t* rank_out);
+
+/* Copies Omega' (n x l, FP64, row-major, leading dimension ld >= l) into device memory. */
+sketch_status sketch_get_omega(sketch_t h, double* omega_dev, int64_t ld);
+
+/* Copies the pass state as FP64 into device memory: G (rows x l, row-major, ld = l) and
+ * H (n x l, row-major, ld = l); either pointer may be NULL.  *rows_out = rows ingested. */
+sketch_status sketch_debug_state(sketch_t h, double* G_dev, double* H_dev, int64_t* rows_out);
+
+/* Writes `count` raw 64-bit words of the Philox-4x64-10 stream with key (seed, 0), starting at
+ * word `first` (word w is lane w % 4 of the block at counter (w / 4, 0, 0, 0)), to device memory,
+ * on `hip_stream`, and waits for it.  Exposes the generator behind omega_from_seed for testing. */
+sketch_status sketch_philox_words(uint64_t seed, uint64_t first, int64_t count, uint64_t* out_dev,
+                                  void* hip_stream);
+
+/* Per-kernel timing of the pass (HIP events on the launch stream, taken around every launch of
+ * the two streaming products while enabled).  sketch_profile_read waits for the stream and
+ * returns, for kind 0 = g = a Omega (incl. its split reduction), 1 = H += a^T g, 2 = finalize:
+ * the number of launches and their summed milliseconds, then clears the counters. */
+sketch_status sketch_profile_enable(sketch_t h, int32_t on);
+sketch_status sketch_profile_read(sketch_t h, int32_t kind, int64_t* launches, double* total_ms);
+
+/* Releases the handle's stream, events and host bookkeeping (not the caller's workspace).
+ * Waits for outstanding work first. */
+sketch_status sketch_destroy(sketch_t h);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* sketch_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKETCH_H */

@@ -1,0 +1,272 @@
+"""MI355X single-pass PCA (Algorithm 4 of Yu et al., IJCAI 2017) behind a C ABI.
+
+Thin ctypes binding of ``include/sketch.h``: the functions below carry the C names and only
+marshal arguments; every step of the computation runs in the HIP library ``libsketch.so``.
+PyTorch provides device memory (workspace and outputs) and the HIP stream.
+
+The library must be built first (``python -m paper_1704_07669_amd.build``); loading fails loudly
+when it is missing -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsketch.so")
+
+# sketch_dtype
+F64, F32, BF16, BF16X2, FP8_E4M3 = 0, 1, 2, 3, 4
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x2": BF16X2, "fp8": FP8_E4M3}
+STATUS = {0: "SKETCH_OK", 1: "SKETCH_E_INVAL", 2: "SKETCH_E_STATE", 3: "SKETCH_E_NOMEM",
+          4: "SKETCH_E_CAPACITY", 5: "SKETCH_E_NONFINITE", 6: "SKETCH_E_DEVICE"}
+EXPORTED = [
+    "sketch_workspace_size", "sketch_init", "sketch_reset", "sketch_set_omega",
+    "sketch_ingest_block", "sketch_poll", "sketch_finalize", "sketch_get_omega",
+    "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
+    "sketch_destroy", "sketch_last_error",
+]
+
+
+class SketchError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sketch_config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("m_capacity", ctypes.c_int64), ("max_block_rows", ctypes.c_int64),
+        ("k", ctypes.c_int32), ("l", ctypes.c_int32), ("b", ctypes.c_int32),
+        ("compute", ctypes.c_int32), ("host_slots", ctypes.c_int32), ("host_src", ctypes.c_int32),
+        ("want_u", ctypes.c_int32), ("omega_from_seed", ctypes.c_int32), ("seed", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libsketch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run python -m paper_1704_07669_amd.build)")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                           ctypes.c_double)
+    cfgp = ctypes.POINTER(sketch_config)
+    sig = {
+        "sketch_workspace_size": (ctypes.c_size_t, [cfgp]),
+        "sketch_init": (I32, [ctypes.POINTER(P), cfgp, P, ctypes.c_size_t, P]),
+        "sketch_reset": (I32, [P, U64]),
+        "sketch_set_omega": (I32, [P, P, I64]),
+        "sketch_ingest_block": (I32, [P, P, I32, I64, I64, I32, ctypes.POINTER(U64)]),
+        "sketch_poll": (I32, [P, U64, ctypes.POINTER(I32)]),
+        "sketch_finalize": (I32, [P, P, P, I64, P, I64, ctypes.POINTER(I32)]),
+        "sketch_get_omega": (I32, [P, P, I64]),
+        "sketch_debug_state": (I32, [P, P, P, ctypes.POINTER(I64)]),
+        "sketch_philox_words": (I32, [U64, U64, I64, P, P]),
+        "sketch_profile_enable": (I32, [P, I32]),
+        "sketch_profile_read": (I32, [P, I32, ctypes.POINTER(I64), ctypes.POINTER(D)]),
+        "sketch_destroy": (I32, [P]),
+        "sketch_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != 0:
+        raise SketchError(st, _lib.sketch_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ C-named wrappers
+def sketch_workspace_size(cfg):
+    lib = load_library()
+    n = lib.sketch_workspace_size(ctypes.byref(cfg))
+    if n == 0:
+        raise SketchError(1, lib.sketch_last_error().decode())
+    return int(n)
+
+
+def sketch_init(cfg, workspace, stream=None):
+    lib = load_library()
+    h = ctypes.c_void_p()
+    _check(lib.sketch_init(ctypes.byref(h), ctypes.byref(cfg), _ptr(workspace),
+                           workspace.numel() * workspace.element_size(), _stream_handle(stream)))
+    return h
+
+
+def sketch_reset(h, seed):
+    _check(load_library().sketch_reset(h, seed))
+
+
+def sketch_set_omega(h, omega_dev):
+    _check(load_library().sketch_set_omega(h, _ptr(omega_dev), omega_dev.stride(0)))
+
+
+def sketch_ingest_block(h, rows, src_dtype, src_is_device):
+    tk = ctypes.c_uint64()
+    _check(load_library().sketch_ingest_block(h, _ptr(rows), src_dtype, rows.shape[0],
+                                              rows.stride(0), int(src_is_device),
+                                              ctypes.byref(tk)))
+    return tk.value
+
+
+def sketch_poll(h, ticket):
+    d = ctypes.c_int32()
+    _check(load_library().sketch_poll(h, ticket, ctypes.byref(d)))
+    return bool(d.value)
+
+
+def sketch_finalize(h, S, U, V):
+    r = ctypes.c_int32()
+    _check(load_library().sketch_finalize(h, _ptr(S), _ptr(U), 0 if U is None else U.stride(0),
+                                          _ptr(V), V.stride(0), ctypes.byref(r)))
+    return r.value
+
+
+def sketch_get_omega(h, out):
+    _check(load_library().sketch_get_omega(h, _ptr(out), out.stride(0)))
+
+
+def sketch_debug_state(h, G, H):
+    rows = ctypes.c_int64()
+    _check(load_library().sketch_debug_state(h, _ptr(G), _ptr(H), ctypes.byref(rows)))
+    return rows.value
+
+
+def sketch_philox_words(seed, first, count, out, stream=None):
+    _check(load_library().sketch_philox_words(seed, first, count, _ptr(out),
+                                              _stream_handle(stream)))
+
+
+def sketch_profile_enable(h, on=True):
+    _check(load_library().sketch_profile_enable(h, int(on)))
+
+
+def sketch_profile_read(h, kind):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(load_library().sketch_profile_read(h, kind, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def sketch_destroy(h):
+    _check(load_library().sketch_destroy(h))
+
+
+def sketch_last_error():
+    return load_library().sketch_last_error().decode()
+
+
+# ------------------------------------------------------------------ convenience object
+class Sketch:
+    """One single-pass PCA stream on the current CUDA (HIP) device.
+
+    ``compute`` is one of 'f64', 'f32', 'bf16', 'bf16x2', 'fp8'.  Omega is drawn on the device
+    from ``seed`` unless ``omega`` (an n x l float64 array/tensor) is given.
+    """
+
+    def __init__(self, n, m_capacity, max_block_rows, k, l, b=10, compute="f32", host_slots=0,
+                 host_src="f32", want_u=False, seed=0, omega=None, stream=None):
+        import torch
+        load_library()
+        self.cfg = sketch_config(
+            n=n, m_capacity=m_capacity, max_block_rows=max_block_rows, k=k, l=l, b=b,
+            compute=DTYPES[compute], host_slots=host_slots, host_src=DTYPES[host_src],
+            want_u=int(bool(want_u)), omega_from_seed=int(omega is None), seed=seed)
+        self.n, self.k, self.l = n, k, l
+        self.stream = stream
+        ws = sketch_workspace_size(self.cfg)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device="cuda")
+        self.h = sketch_init(self.cfg, self.workspace, stream)
+        self.closed = False
+        if omega is not None:
+            om = torch.as_tensor(np.asarray(omega, dtype=np.float64)).to("cuda")
+            sketch_set_omega(self.h, om.contiguous())
+            torch.cuda.synchronize()
+
+    _TORCH2DT = None
+
+    @staticmethod
+    def _src_code(t):
+        import torch
+        return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t.dtype]
+
+    def ingest(self, rows):
+        """Ingest a 2-D block: a CUDA tensor, or a pinned CPU tensor (host_slots > 0)."""
+        if rows.dim() != 2 or rows.shape[1] != self.n or rows.stride(1) != 1:
+            raise ValueError("rows must be a row-major nrows x n tensor")
+        return sketch_ingest_block(self.h, rows, self._src_code(rows), rows.is_cuda)
+
+    def poll(self, ticket):
+        return sketch_poll(self.h, ticket)
+
+    def finalize(self, want_u=None):
+        import torch
+        want_u = bool(self.cfg.want_u) if want_u is None else want_u
+        S = torch.empty(self.k, dtype=torch.float64, device="cuda")
+        V = torch.empty(self.n, self.k, dtype=torch.float64, device="cuda")
+        U = None
+        if want_u:
+            U = torch.empty(self.rows_capacity_used(), self.k, dtype=torch.float64, device="cuda")
+        rank = sketch_finalize(self.h, S, U, V)
+        return S, V, U, rank
+
+    def rows_capacity_used(self):
+        import torch
+        rows = ctypes.c_int64()
+        _check(load_library().sketch_debug_state(self.h, None, None, ctypes.byref(rows)))
+        return rows.value
+
+    def omega(self):
+        import torch
+        out = torch.empty(self.n, self.l, dtype=torch.float64, device="cuda")
+        sketch_get_omega(self.h, out)
+        return out
+
+    def state(self):
+        import torch
+        rows = self.rows_capacity_used()
+        G = torch.empty(rows, self.l, dtype=torch.float64, device="cuda")
+        H = torch.empty(self.n, self.l, dtype=torch.float64, device="cuda")
+        sketch_debug_state(self.h, G, H)
+        return G, H
+
+    def reset(self, seed=None):
+        sketch_reset(self.h, self.cfg.seed if seed is None else seed)
+
+    def profile(self, on=True):
+        sketch_profile_enable(self.h, on)
+
+    def profile_read(self, kind):
+        return sketch_profile_read(self.h, kind)
+
+    def close(self):
+        if not self.closed:
+            sketch_destroy(self.h)
+            self.closed = True
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

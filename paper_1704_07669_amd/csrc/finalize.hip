@@ -1,0 +1,966 @@
+// After the pass: the column-block loop of Algorithm 4 (steps 9-15, re-orthogonalised as in
+// Sec. 3.2, Eqs. 7-9) and the SVD of B with U = Q U~ (steps 16-19), all in FP64.
+//
+// Per iteration i (columns c = ib .. ib+b-1, p = ib earlier basis vectors):
+//   W  = B Omega_i                 (p x b; reduction over n)
+//   Y  = G(:,c) - Q W              (m x b)
+//   T  = Q^T Y                     (p x b; Y_i^T Q = T^T, needed by the numerator of Eq. 9)
+//   [Q_i, R_i] = qr(Y)             (tall-skinny QR, Householder on row chunks + reduction tree)
+//   C  = Q^T Q_i; Z = Q_i - Q C    (Eq. 7)
+//   [Q_i, R~_i] = qr(Z);  R_i = R~_i R_i
+//   rank guard on diag(R_i)
+//   N  = H(:,c) - B^T (T + W)      (= the transpose of H(:,c)^T - Y_i^T Q B - Omega_i^T B^T B)
+//   B_i^T = N R_i^{-1}             (row-wise triangular solve)
+// The two terms Y_i^T Q B and Omega_i^T B^T B of Eq. 9 share the factor B and are formed as one
+// product (T + W)^T B.  B is kept transposed (B^T, n x l) so that every tall operand is a
+// column-major array whose columns are contiguous.
+//
+// SVD of B: B^T = Q_B R_B by the same block Gram-Schmidt-with-re-orthogonalisation + TSQR scheme,
+// then a one-sided (Hestenes) Jacobi SVD of R_B^T in one workgroup: R_B^T J = W with orthogonal
+// columns, so B = (W S^-1) S (Q_B J)^T, i.e. U~ = W S^-1, V = Q_B J, U = Q U~.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace sk {
+namespace {
+
+constexpr double kGuardTau = 1e-10;
+constexpr int TPB = 256;
+
+inline int grid_for(int64_t work, int block = TPB, int cap = 65536) {
+  int64_t g = cdiv<int64_t>(work, block);
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+__device__ __forceinline__ bool skip_iter(const Ctrl* ctrl, int iter) {
+  return ctrl != nullptr && iter > ctrl->last_iter;
+}
+
+// Sum of `cnt` per-thread values across a 256-thread block; result broadcast in out[0..cnt).
+template <int CMAX>
+__device__ __forceinline__ void block_sum(double (&v)[CMAX], int cnt, double* red, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < CMAX; ++c) {
+    if (c < cnt) {
+      const double s = wave_sum(v[c]);
+      if (lane == 0) red[wave * CMAX + c] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < cnt) {
+    double s = 0;
+    for (int w = 0; w < TPB / 64; ++w) s += red[w * CMAX + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------------------
+// Reductions over rows: part[chunk][a][c] = sum_{r in chunk} X[a][r] Y[c][r]
+template <int QMAX>
+__global__ __launch_bounds__(TPB) void k_tn_partial(const double* __restrict__ X, int64_t ldx,
+                                                    const double* __restrict__ Y, int64_t ldy,
+                                                    int p, int q, int64_t rows, int RC,
+                                                    double* __restrict__ part,
+                                                    const Ctrl* __restrict__ ctrl, int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  extern __shared__ double ys[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * RC;
+  const int cnt = (int)min<int64_t>(RC, rows - r0);
+  for (int idx = threadIdx.x; idx < q * RC; idx += TPB) {
+    const int c = idx / RC, r = idx - c * RC;
+    ys[idx] = (r < cnt) ? Y[c * ldy + r0 + r] : 0.0;
+  }
+  __syncthreads();
+  for (int a = wave; a < p; a += TPB / 64) {
+    double acc[QMAX];
+#pragma unroll
+    for (int c = 0; c < QMAX; ++c) acc[c] = 0.0;
+    const double* xa = X + a * ldx + r0;
+    for (int r = lane; r < cnt; r += 64) {
+      const double x = xa[r];
+#pragma unroll
+      for (int c = 0; c < QMAX; ++c)
+        if (c < q) acc[c] = fma(x, ys[c * RC + r], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < QMAX; ++c) {
+      if (c < q) {
+        const double s = wave_sum(acc[c]);
+        if (lane == 0) part[((int64_t)blockIdx.x * p + a) * q + c] = s;
+      }
+    }
+  }
+}
+
+// out (p x q, row-major, leading dimension ldo) = sum over chunks in chunk order.
+__global__ void k_tn_final(const double* __restrict__ part, int nchunks, int p, int q,
+                           double* __restrict__ out, int ldo, const Ctrl* __restrict__ ctrl,
+                           int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= p * q) return;
+  double s = 0;
+  for (int ch = 0; ch < nchunks; ++ch) s += part[(int64_t)ch * p * q + idx];
+  out[(idx / q) * ldo + idx % q] = s;
+}
+
+// out[c][r] = base[c][r] + alpha * sum_a X[a][r] W[a][c]  (W row-major p x q, ldw); base may be
+// null (taken as 0) and may alias out.
+template <typename BT, int QMAX>
+__global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int64_t ldo,
+                                                   const BT* base, int64_t ldb,
+                                                   const double* __restrict__ X, int64_t ldx,
+                                                   int p, const double* __restrict__ W, int ldw,
+                                                   int q, int64_t rows, double alpha,
+                                                   const Ctrl* __restrict__ ctrl, int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  extern __shared__ double ws[];
+  for (int idx = threadIdx.x; idx < p * q; idx += TPB) ws[idx] = W[(idx / q) * ldw + idx % q];
+  __syncthreads();
+  for (int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * TPB) {
+    double acc[QMAX];
+#pragma unroll
+    for (int c = 0; c < QMAX; ++c) acc[c] = 0.0;
+    for (int a = 0; a < p; ++a) {
+      const double x = X[a * ldx + r];
+#pragma unroll
+      for (int c = 0; c < QMAX; ++c)
+        if (c < q) acc[c] = fma(x, ws[a * q + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < QMAX; ++c) {
+      if (c < q) {
+        const double bv = base ? (double)base[c * ldb + r] : 0.0;
+        out[c * ldo + r] = bv + alpha * acc[c];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Tall-skinny QR.  Level arrays are column-major (rows x b).  Each chunk of CR rows is factored by
+// Householder reflections (the LAPACK dlarfg convention) with RPT rows per thread held in
+// registers; its b x b R goes to the next level's stacked array.  The Q factor is then formed from
+// the root down by applying each chunk's reflectors to its b x b block of the level above.
+template <int BMAX, int RPT>
+__global__ __launch_bounds__(TPB) void k_house_factor(double* __restrict__ X, int64_t ldx,
+                                                      int64_t rows, int b, int CR,
+                                                      double* __restrict__ tau,
+                                                      double* __restrict__ Rnext, int64_t ldr,
+                                                      const Ctrl* __restrict__ ctrl, int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  __shared__ double red[(TPB / 64) * BMAX];
+  __shared__ double bc[BMAX + 4];
+  const int64_t r0 = (int64_t)blockIdx.x * CR;
+  const int cnt = (int)min<int64_t>(CR, rows - r0);
+  double x[RPT][BMAX];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int i = threadIdx.x + t * TPB;
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c) x[t][c] = (c < b && i < cnt) ? X[c * ldx + r0 + i] : 0.0;
+  }
+  for (int j = 0; j < b; ++j) {
+    // alpha = x_jj, xnorm^2 = sum_{i>j} x_ij^2
+    double v1[1] = {0.0};
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int i = threadIdx.x + t * TPB;
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c)
+        if (c == j) {
+          if (i > j) v1[0] = fma(x[t][c], x[t][c], v1[0]);
+          if (i == j) bc[BMAX] = x[t][c];
+        }
+    }
+    block_sum<1>(v1, 1, red, bc + BMAX + 1);
+    if (threadIdx.x == 0) {
+      const double alpha = bc[BMAX], xn2 = bc[BMAX + 1];
+      double t_, beta, scal;
+      if (xn2 == 0.0) {
+        t_ = 0.0; beta = alpha; scal = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        t_ = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      bc[BMAX + 2] = t_;
+      bc[BMAX + 3] = scal;
+      bc[BMAX + 1] = beta;
+      tau[(int64_t)blockIdx.x * b + j] = t_;
+    }
+    __syncthreads();
+    const double tj = bc[BMAX + 2], scal = bc[BMAX + 3], beta = bc[BMAX + 1];
+    // v_i = x_ij * scal (i > j), v_j = 1; the column becomes (beta at row j, v below)
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int i = threadIdx.x + t * TPB;
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c)
+        if (c == j) {
+          if (i > j) x[t][c] *= scal;
+          if (i == j) x[t][c] = beta;
+        }
+    }
+    if (tj != 0.0 && j + 1 < b) {
+      // w_c = x_jc + sum_{i>j} v_i x_ic for c > j;  x_ic -= tau v_i w_c
+      double w[BMAX];
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c) w[c] = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int i = threadIdx.x + t * TPB;
+        double vi = 0.0;
+#pragma unroll
+        for (int c = 0; c < BMAX; ++c)
+          if (c == j) vi = (i > j) ? x[t][c] : (i == j ? 1.0 : 0.0);
+#pragma unroll
+        for (int c = 0; c < BMAX; ++c)
+          if (c > j && c < b) w[c] = fma(vi, x[t][c], w[c]);
+      }
+      block_sum<BMAX>(w, b, red, bc);
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int i = threadIdx.x + t * TPB;
+        double vi = 0.0;
+#pragma unroll
+        for (int c = 0; c < BMAX; ++c)
+          if (c == j) vi = (i > j) ? x[t][c] : (i == j ? 1.0 : 0.0);
+#pragma unroll
+        for (int c = 0; c < BMAX; ++c)
+          if (c > j && c < b) x[t][c] -= tj * vi * bc[c];
+      }
+      __syncthreads();
+    }
+  }
+  // reflectors back in place (rows < cnt), R (upper triangle, zero below) to the next level
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int i = threadIdx.x + t * TPB;
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c) {
+      if (c < b) {
+        if (i < cnt) X[c * ldx + r0 + i] = x[t][c];
+        if (i < b) Rnext[c * ldr + (int64_t)blockIdx.x * b + i] = (i <= c) ? x[t][c] : 0.0;
+      }
+    }
+  }
+}
+
+// Explicit Q of each chunk: Y = H_0 H_1 ... H_{b-1} [Qabove(chunk rows); 0], written over the
+// chunk's reflectors.  At the root (Qabove == null) the start is D = diag(sign(R_jj)) with R the
+// root's stacked rows, so the final R = D R has a nonnegative diagonal; the root also writes that
+// R (row-major b x b) to Rout.
+template <int BMAX, int RPT>
+__global__ __launch_bounds__(TPB) void k_house_form(double* __restrict__ X, int64_t ldx,
+                                                    int64_t rows, int b, int CR,
+                                                    const double* __restrict__ tau,
+                                                    const double* __restrict__ Qabove,
+                                                    int64_t lda, const double* __restrict__ Rroot,
+                                                    int64_t ldr, double* __restrict__ Rout,
+                                                    const Ctrl* __restrict__ ctrl, int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  __shared__ double red[(TPB / 64) * BMAX];
+  __shared__ double bc[BMAX];
+  __shared__ double d[BMAX];
+  const int64_t r0 = (int64_t)blockIdx.x * CR;
+  const int cnt = (int)min<int64_t>(CR, rows - r0);
+  if (Qabove == nullptr && threadIdx.x < b) {
+    const double rjj = Rroot[threadIdx.x * ldr + threadIdx.x];
+    d[threadIdx.x] = (rjj < 0.0) ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  if (Qabove == nullptr && Rout != nullptr) {
+    for (int idx = threadIdx.x; idx < b * b; idx += TPB) {
+      const int i = idx / b, c = idx % b;
+      Rout[idx] = (c >= i) ? d[i] * Rroot[c * ldr + i] : 0.0;
+    }
+  }
+  double v[RPT][BMAX], y[RPT][BMAX];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int i = threadIdx.x + t * TPB;
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c) {
+      v[t][c] = (c < b && i < cnt) ? X[c * ldx + r0 + i] : 0.0;
+      double y0 = 0.0;
+      if (c < b && i < b) {
+        if (Qabove) y0 = Qabove[c * lda + (int64_t)blockIdx.x * b + i];
+        else y0 = (i == c) ? d[c] : 0.0;
+      }
+      y[t][c] = y0;
+    }
+  }
+  for (int j = b - 1; j >= 0; --j) {
+    const double tj = tau[(int64_t)blockIdx.x * b + j];
+    if (tj == 0.0) continue;
+    double w[BMAX];
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c) w[c] = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int i = threadIdx.x + t * TPB;
+      double vi = 0.0;
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c)
+        if (c == j) vi = (i > j) ? v[t][c] : (i == j ? 1.0 : 0.0);
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c)
+        if (c < b) w[c] = fma(vi, y[t][c], w[c]);
+    }
+    block_sum<BMAX>(w, b, red, bc);
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int i = threadIdx.x + t * TPB;
+      double vi = 0.0;
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c)
+        if (c == j) vi = (i > j) ? v[t][c] : (i == j ? 1.0 : 0.0);
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c)
+        if (c < b) y[t][c] -= tj * vi * bc[c];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int i = threadIdx.x + t * TPB;
+    if (i < cnt) {
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c)
+        if (c < b) X[c * ldx + r0 + i] = y[t][c];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Small b x b / p x b kernels (one workgroup).
+
+// R = R2 R1 (upper triangular), then the rank guard of the column-block loop.
+__global__ void k_guard(const double* __restrict__ R1, const double* __restrict__ R2,
+                        double* __restrict__ R, int b, int iter, int t, Ctrl* __restrict__ ctrl) {
+  if (skip_iter(ctrl, iter)) return;
+  for (int idx = threadIdx.x; idx < b * b; idx += blockDim.x) {
+    const int i = idx / b, c = idx % b;
+    double s = 0.0;
+    for (int q = i; q <= c; ++q) s = fma(R2[i * b + q], R1[q * b + c], s);
+    R[idx] = (c >= i) ? s : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (iter == 0) ctrl->r0 = R[0];
+    const double thr = kGuardTau * ctrl->r0;
+    int keep = 0;
+    while (keep < b && fabs(R[keep * b + keep]) > thr) ++keep;
+    if (keep < b) {
+      ctrl->last_iter = iter;
+      ctrl->keep_last = keep;
+      ctrl->l_eff = iter * b + keep;
+    } else {
+      ctrl->l_eff = (iter + 1) * b;
+      ctrl->keep_last = b;
+    }
+  }
+}
+
+// out = A + B (p x q, row-major with leading dimension q)
+__global__ void k_add_small(const double* __restrict__ A, const double* __restrict__ B,
+                            double* __restrict__ out, int count, const Ctrl* __restrict__ ctrl,
+                            int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) out[i] = A[i] + B[i];
+}
+
+// Bt(:, c0 + j) = (N R^{-1})(:, j) for j < keep (row-wise forward substitution), 0 for j >= keep;
+// Q columns c0 + keep .. c0 + b - 1 are zeroed by k_zero_cols.
+template <int BMAX>
+__global__ void k_trsm_rows(const double* __restrict__ N, int64_t ldn, const double* __restrict__ R,
+                            int b, int64_t rows, double* __restrict__ Bt, int64_t ldb, int c0,
+                            const Ctrl* __restrict__ ctrl, int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  const int keep = (iter == ctrl->last_iter) ? ctrl->keep_last : b;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double y[BMAX];
+#pragma unroll
+    for (int j = 0; j < BMAX; ++j) {
+      if (j < b) {
+        double s = N[j * ldn + r];
+#pragma unroll
+        for (int q = 0; q < BMAX; ++q)
+          if (q < j) s -= y[q] * R[q * b + j];
+        y[j] = (j < keep) ? s / R[j * b + j] : 0.0;
+        Bt[(c0 + j) * ldb + r] = y[j];
+      }
+    }
+  }
+}
+
+__global__ void k_zero_cols(double* __restrict__ Q, int64_t ldq, int64_t rows, int c0, int b,
+                            const Ctrl* __restrict__ ctrl, int iter) {
+  if (skip_iter(ctrl, iter) || iter != ctrl->last_iter) return;
+  const int keep = ctrl->keep_last;
+  const int64_t total = (int64_t)(b - keep) * rows;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(q / rows);
+    Q[(c0 + keep + c) * ldq + (q - (int64_t)c * rows)] = 0.0;
+  }
+}
+
+// R_B blocks of one panel (row-major R_B, leading dimension ldr):
+//   R_B[0:c0, panel] = C1 + C2 R1,  R_B[panel, panel] = R2 R1.
+__global__ void k_rb_assemble(const double* __restrict__ C1, const double* __restrict__ C2,
+                              const double* __restrict__ R1, const double* __restrict__ R2,
+                              double* __restrict__ RB, int ldr, int c0, int w) {
+  for (int idx = threadIdx.x; idx < (c0 + w) * w; idx += blockDim.x) {
+    const int i = idx / w, c = idx % w;
+    double s = 0.0;
+    if (i < c0) {
+      s = C1[i * w + c];
+      for (int q = 0; q <= c; ++q) s = fma(C2[i * w + q], R1[q * w + c], s);
+    } else {
+      const int ii = i - c0;
+      for (int q = ii; q <= c; ++q) s = fma(R2[ii * w + q], R1[q * w + c], s);
+    }
+    RB[i * ldr + c0 + c] = s;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// One-sided Jacobi on M = R_B^T (L x L, L = l_eff): columns of M are the rows of R_B.  Round-robin
+// ordering: in each of the N-1 rounds (N = L rounded up to even) the N/2 disjoint pairs are rotated
+// in parallel, one wave per pair.  Each rotation is logged as (p, q, c, s) so J can be rebuilt by
+// k_jacobi_apply.  Outputs: sig (descending), perm, W = M J (column perm[j] holds sigma_j u_j).
+constexpr int JMAX = 128;
+constexpr int JSWEEPS = 40;
+
+__device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
+  if (k == 0) { p = N - 1; q = r; }
+  else { p = (r + k) % (N - 1); q = (r - k + N - 1) % (N - 1); }
+  if (p > q) { const int t = p; p = q; q = t; }
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, int ldr, int L,
+                                                 double* __restrict__ W, int ldw,
+                                                 double4* __restrict__ log, int* __restrict__ info,
+                                                 double* __restrict__ sig, int* __restrict__ perm) {
+  extern __shared__ double M[];           // N columns of L entries
+  __shared__ int rotated;
+  __shared__ double nrm[JMAX];
+  const int N = (L + 1) & ~1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int idx = threadIdx.x; idx < N * L; idx += blockDim.x) {
+    const int col = idx / L, i = idx % L;
+    M[idx] = (col < L) ? RB[col * ldr + i] : 0.0;     // M(:, col) = R_B(col, :)^T
+  }
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < JSWEEPS && N > 1; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r) {
+      for (int k = wave; k < N / 2; k += nw) {
+        int p, q;
+        rr_pair(N, r, k, p, q);
+        double* mp = M + p * L;
+        double* mq = M + q * L;
+        double a = 0, bb = 0, g = 0;
+        for (int i = lane; i < L; i += 64) {
+          const double xp = mp[i], xq = mq[i];
+          a = fma(xp, xp, a); bb = fma(xq, xq, bb); g = fma(xp, xq, g);
+        }
+        a = wave_sum(a); bb = wave_sum(bb); g = wave_sum(g);
+        double c = 1.0, s = 0.0;
+        bool rot = (g != 0.0) && (fabs(g) > 1e-15 * sqrt(a * bb));
+        if (rot) {
+          const double zeta = (bb - a) / (2.0 * g);
+          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = c * t;
+          for (int i = lane; i < L; i += 64) {
+            const double xp = mp[i], xq = mq[i];
+            mp[i] = c * xp - s * xq;
+            mq[i] = s * xp + c * xq;
+          }
+          if (lane == 0) rotated = 1;
+        }
+        if (lane == 0)
+          log[((int64_t)sweep * (N - 1) + r) * (N / 2) + k] =
+              make_double4((double)p, (double)q, c, rot ? s : 0.0);
+      }
+      __syncthreads();
+    }
+    if (!rotated) { ++sweep; break; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) info[0] = sweep;
+  for (int col = threadIdx.x; col < L; col += blockDim.x) {
+    double s = 0;
+    for (int i = 0; i < L; ++i) s = fma(M[col * L + i], M[col * L + i], s);
+    nrm[col] = sqrt(s);
+  }
+  __syncthreads();
+  for (int col = threadIdx.x; col < L; col += blockDim.x) {
+    int rank = 0;
+    for (int o = 0; o < L; ++o)
+      rank += (nrm[o] > nrm[col]) || (nrm[o] == nrm[col] && o < col);
+    sig[rank] = nrm[col];
+    perm[rank] = col;
+  }
+  for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x) {
+    const int col = idx / L, i = idx % L;
+    W[i * ldw + col] = M[col * L + i];   // W row-major L x L
+  }
+}
+
+// J = product of the logged rotations, applied round by round to the rows of the identity.
+__global__ __launch_bounds__(1024) void k_jacobi_apply(const double4* __restrict__ log,
+                                                       const int* __restrict__ info, int L,
+                                                       double* __restrict__ J, int ldj) {
+  extern __shared__ double Js[];          // N x N row-major
+  const int N = (L + 1) & ~1;
+  for (int idx = threadIdx.x; idx < N * N; idx += blockDim.x)
+    Js[idx] = (idx / N == idx % N) ? 1.0 : 0.0;
+  __syncthreads();
+  const int sweeps = info[0];
+  const int half = N / 2;
+  for (int sr = 0; sr < sweeps * (N - 1); ++sr) {
+    const double4* lg = log + (int64_t)sr * half;
+    for (int item = threadIdx.x; item < N * half; item += blockDim.x) {
+      const int row = item / half, k = item % half;
+      const double4 e = lg[k];
+      if (e.w != 0.0) {
+        const int p = (int)e.x, q = (int)e.y;
+        const double xp = Js[row * N + p], xq = Js[row * N + q];
+        Js[row * N + p] = e.z * xp - e.w * xq;
+        Js[row * N + q] = e.w * xp + e.z * xq;
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x)
+    J[(idx / L) * ldj + idx % L] = Js[(idx / L) * N + idx % L];
+}
+
+// Gather the k leading right/left factors: Jk = J(:, perm[0:kk]), Wk = W(:, perm[0:kk]) / sig.
+__global__ void k_gather(const double* __restrict__ J, const double* __restrict__ W, int ld, int L,
+                         const int* __restrict__ perm, const double* __restrict__ sig, int kk,
+                         double* __restrict__ Jk, double* __restrict__ Wk) {
+  for (int idx = threadIdx.x; idx < L * kk; idx += blockDim.x) {
+    const int i = idx / kk, j = idx % kk;
+    const int col = perm[j];
+    Jk[idx] = J[i * ld + col];
+    Wk[idx] = sig[j] > 0.0 ? W[i * ld + col] / sig[j] : 0.0;
+  }
+}
+
+// Sign of each column j < kk of V (column-major, ld): + if its largest-magnitude entry (lowest
+// index on ties) is positive.  One workgroup per column.
+__global__ __launch_bounds__(TPB) void k_signs(const double* __restrict__ V, int64_t ldv,
+                                               int64_t n, double* __restrict__ sgn) {
+  __shared__ double bv[TPB];
+  __shared__ int64_t bi[TPB];
+  const int j = blockIdx.x;
+  double best = -1.0;
+  int64_t bidx = 0;
+  for (int64_t r = threadIdx.x; r < n; r += TPB) {
+    const double a = fabs(V[j * ldv + r]);
+    if (a > best) { best = a; bidx = r; }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int o = TPB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double a = bv[threadIdx.x + o];
+      const int64_t ia = bi[threadIdx.x + o];
+      if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ia < bi[threadIdx.x])) {
+        bv[threadIdx.x] = a;
+        bi[threadIdx.x] = ia;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sgn[j] = (V[j * ldv + bi[0]] < 0.0) ? -1.0 : 1.0;
+}
+
+// out = sign_j * (X Wk)(r, j) for j < kk, 0 for kk <= j < k; row-major (out[r*ld + j]) or, with
+// colmajor, out[j*ld + r].  sgn may be null (all +1).
+__global__ __launch_bounds__(TPB) void k_write_rows(const double* __restrict__ X, int64_t ldx,
+                                                    int L, const double* __restrict__ Wk, int kk,
+                                                    int k, const double* __restrict__ sgn,
+                                                    int64_t rows, double* __restrict__ out,
+                                                    int64_t ld, int colmajor) {
+  extern __shared__ double ws[];
+  for (int idx = threadIdx.x; idx < L * kk; idx += TPB) ws[idx] = Wk[idx];
+  __syncthreads();
+  for (int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * TPB) {
+    for (int j0 = 0; j0 < k; j0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+      for (int a = 0; a < L; ++a) {
+        const double x = X[a * ldx + r];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j0 + j < kk) acc[j] = fma(x, ws[a * kk + j0 + j], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (j0 + j < k) {
+          const double v = (j0 + j < kk) ? (sgn ? sgn[j0 + j] : 1.0) * acc[j] : 0.0;
+          if (colmajor) out[(int64_t)(j0 + j) * ld + r] = v;
+          else out[r * ld + j0 + j] = v;
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_write_s(const double* __restrict__ sig, int kk, int k, double* __restrict__ S) {
+  for (int j = threadIdx.x; j < k; j += blockDim.x) S[j] = (j < kk) ? sig[j] : 0.0;
+}
+
+__global__ void k_init_ctrl(Ctrl* ctrl, int t, int l) {
+  if (threadIdx.x == 0) {
+    const int nf = ctrl->nonfinite;
+    ctrl->r0 = 0.0;
+    ctrl->last_iter = t - 1;
+    ctrl->keep_last = 0;
+    ctrl->l_eff = l;
+    ctrl->nonfinite = nf;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Host orchestration.
+struct Ctx {
+  hipStream_t s;
+  hipError_t err = hipSuccess;
+  bool ok() const { return err == hipSuccess; }
+  void chk() { if (err == hipSuccess) err = hipGetLastError(); }
+};
+
+int tn_rows_per_chunk(int q) {
+  int rc = 8192 / (q < 1 ? 1 : q);
+  rc = rc > 2048 ? 2048 : rc;
+  return rc < 64 ? 64 : (rc / 64) * 64;
+}
+
+// out (p x q row-major, ldo) = X[:, 0:p]^T Y[:, 0:q] over `rows` rows.
+void tn(Ctx& cx, const double* X, int64_t ldx, const double* Y, int64_t ldy, int p, int q,
+        int64_t rows, double* part, double* out, int ldo, const Ctrl* ctrl, int iter) {
+  if (!cx.ok() || p == 0 || q == 0) return;
+  const int RC = tn_rows_per_chunk(q);
+  const int nch = (int)cdiv<int64_t>(rows, RC);
+  const size_t shm = (size_t)RC * q * sizeof(double);
+  if (q <= 8)
+    hipLaunchKernelGGL(k_tn_partial<8>, dim3(nch), dim3(TPB), shm, cx.s, X, ldx, Y, ldy, p, q,
+                       rows, RC, part, ctrl, iter);
+  else if (q <= 16)
+    hipLaunchKernelGGL(k_tn_partial<16>, dim3(nch), dim3(TPB), shm, cx.s, X, ldx, Y, ldy, p, q,
+                       rows, RC, part, ctrl, iter);
+  else
+    hipLaunchKernelGGL(k_tn_partial<32>, dim3(nch), dim3(TPB), shm, cx.s, X, ldx, Y, ldy, p, q,
+                       rows, RC, part, ctrl, iter);
+  cx.chk();
+  if (!cx.ok()) return;
+  hipLaunchKernelGGL(k_tn_final, dim3(cdiv(p * q, TPB)), dim3(TPB), 0, cx.s, part, nch, p, q, out,
+                     ldo, ctrl, iter);
+  cx.chk();
+}
+
+template <typename BT>
+void nn(Ctx& cx, double* out, int64_t ldo, const BT* base, int64_t ldb, const double* X,
+        int64_t ldx, int p, const double* W, int ldw, int q, int64_t rows, double alpha,
+        const Ctrl* ctrl, int iter) {
+  if (!cx.ok() || q == 0) return;
+  const size_t shm = (size_t)(p * q > 0 ? p * q : 1) * sizeof(double);
+  const dim3 g(grid_for(rows, TPB, 8192)), blk(TPB);
+  if (q <= 8)
+    hipLaunchKernelGGL((k_nn_update<BT, 8>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p, W,
+                       ldw, q, rows, alpha, ctrl, iter);
+  else if (q <= 16)
+    hipLaunchKernelGGL((k_nn_update<BT, 16>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p,
+                       W, ldw, q, rows, alpha, ctrl, iter);
+  else
+    hipLaunchKernelGGL((k_nn_update<BT, 32>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p,
+                       W, ldw, q, rows, alpha, ctrl, iter);
+  cx.chk();
+}
+
+struct Level {
+  double* X; int64_t ld; int64_t rows; int nch; int CR; double* tau;
+};
+
+template <int BMAX, int RPT>
+void tsqr_t(Ctx& cx, double* X, int64_t ldx, int64_t rows, int b, double* ws, double* Rout,
+            const Ctrl* ctrl, int iter) {
+  constexpr int CR0 = TPB * RPT;
+  Level lv[16];
+  int L = 0;
+  double* cur = ws;
+  lv[0] = {X, ldx, rows, 0, 0, nullptr};
+  for (;;) {
+    Level& v = lv[L];
+    v.nch = (int)cdiv<int64_t>(v.rows, CR0);
+    v.CR = (int)cdiv<int64_t>(v.rows, v.nch);
+    v.tau = cur;
+    cur += rup<int64_t>((int64_t)v.nch * b, 32);
+    // the next level holds the stacked R factors (also used for the root's raw R)
+    Level& nx = lv[L + 1];
+    nx.rows = (int64_t)v.nch * b;
+    nx.ld = nx.rows;
+    nx.X = cur;
+    cur += rup<int64_t>(nx.rows * b, 32);
+    if (v.nch == 1) break;
+    ++L;
+  }
+  // factor levels 0..L; level L is the root (one chunk) and writes its raw R into lv[L+1].X
+  for (int k = 0; k <= L && cx.ok(); ++k) {
+    hipLaunchKernelGGL((k_house_factor<BMAX, RPT>), dim3(lv[k].nch), dim3(TPB), 0, cx.s, lv[k].X,
+                       lv[k].ld, lv[k].rows, b, lv[k].CR, lv[k].tau, lv[k + 1].X, lv[k + 1].ld,
+                       ctrl, iter);
+    cx.chk();
+  }
+  // form Q from the root down
+  for (int k = L; k >= 0 && cx.ok(); --k) {
+    const bool root = (k == L);
+    hipLaunchKernelGGL((k_house_form<BMAX, RPT>), dim3(lv[k].nch), dim3(TPB), 0, cx.s, lv[k].X,
+                       lv[k].ld, lv[k].rows, b, lv[k].CR, lv[k].tau,
+                       root ? (const double*)nullptr : lv[k + 1].X, lv[k + 1].ld, lv[L + 1].X,
+                       lv[L + 1].ld, root ? Rout : (double*)nullptr, ctrl, iter);
+    cx.chk();
+  }
+}
+
+void tsqr(Ctx& cx, double* X, int64_t ldx, int64_t rows, int b, double* ws, double* Rout,
+          const Ctrl* ctrl, int iter) {
+  if (!cx.ok()) return;
+  if (b <= 8) tsqr_t<8, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  else if (b <= 16) tsqr_t<16, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  else tsqr_t<32, 2>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+}
+
+// Small-buffer layout (doubles), see finalize_small_elems.
+struct Small {
+  double *W, *T, *C, *Wn, *R1, *R2, *R, *RB, *C1, *C2, *Jm, *Wm, *sig, *Jk, *Wk, *sgn;
+  int* perm; int* info; double4* log;
+};
+Small carve_small(double* base, int l, int b) {
+  const int P = l * 32;   // p x b blocks with p <= l, b <= 32
+  Small sm;
+  double* c = base;
+  auto take = [&](int64_t cnt) { double* r = c; c += rup<int64_t>(cnt, 32); return r; };
+  sm.W = take(P); sm.T = take(P); sm.C = take(P); sm.Wn = take(P);
+  sm.R1 = take(32 * 32); sm.R2 = take(32 * 32); sm.R = take(32 * 32);
+  sm.RB = take((int64_t)l * l); sm.C1 = take(P); sm.C2 = take(P);
+  sm.Jm = take((int64_t)l * l); sm.Wm = take((int64_t)l * l); sm.sig = take(l);
+  sm.Jk = take((int64_t)l * l); sm.Wk = take((int64_t)l * l); sm.sgn = take(l);
+  sm.perm = reinterpret_cast<int*>(take(l));
+  sm.info = reinterpret_cast<int*>(take(4));
+  const int N = (l + 1) & ~1;
+  sm.log = reinterpret_cast<double4*>(take((int64_t)JSWEEPS * (N - 1 > 0 ? N - 1 : 1) * (N / 2 > 0 ? N / 2 : 1) * 4));
+  return sm;
+}
+
+}  // namespace
+
+hipError_t finalize_prepare() {
+  const int big = JMAX * JMAX * (int)sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_jacobi_apply,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_write_rows,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  return e;
+}
+
+size_t finalize_small_elems(int l, int b) {
+  (void)b;
+  const int N = (l + 1) & ~1;
+  const int64_t P = (int64_t)l * 32;
+  int64_t e = 6 * rup<int64_t>(P, 32) + 3 * 1024 + 5 * rup<int64_t>((int64_t)l * l, 32) +
+              3 * rup<int64_t>(l, 32) + 32 +
+              rup<int64_t>((int64_t)JSWEEPS * (N - 1 > 0 ? N - 1 : 1) * (N / 2 > 0 ? N / 2 : 1) * 4, 32);
+  return (size_t)e + 1024;
+}
+
+size_t tsqr_workspace_elems(int64_t rows, int b) {
+  const int RPT = (b <= 16) ? 4 : 2;
+  const int64_t CR0 = TPB * RPT;
+  int64_t total = 0, r = rows;
+  for (int guard = 0; guard < 16; ++guard) {
+    const int64_t nch = cdiv<int64_t>(r, CR0);
+    total += rup<int64_t>(nch * b, 32) + rup<int64_t>(nch * b * b, 32);
+    if (nch == 1) break;
+    r = nch * b;
+  }
+  return (size_t)total + 64;
+}
+
+size_t reduce_workspace_elems(int64_t rows, int p, int q) {
+  // worst case over q in [1, 32]: chunks * p * q
+  int64_t worst = 0;
+  for (int qq = 1; qq <= 32; ++qq) {
+    const int64_t nch = cdiv<int64_t>(rows, tn_rows_per_chunk(qq));
+    worst = nch * p * qq > worst ? nch * p * qq : worst;
+  }
+  return (size_t)worst + 64;
+}
+
+hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
+  Ctx cx{stream};
+  const int b = f.b, l = f.l, t = l / b;
+  const int64_t m = f.m, n = f.n;
+  Small sm = carve_small(f.small, l, b);
+  Ctrl* ctrl = f.ctrl;
+
+  hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l);
+  cx.chk();
+
+  // ---------------- column-block loop (Alg. 4 steps 9-15)
+  for (int i = 0; i < t && cx.ok(); ++i) {
+    const int c0 = i * b, p = c0;
+    double* Qi = f.Q + (int64_t)c0 * f.ldq;
+    // W = B Omega_i  (B^T is n x p)
+    tn(cx, f.Bt, f.ldb, f.om64 + (int64_t)c0 * f.ldo, f.ldo, p, b, n, f.red_ws, sm.W, b, ctrl, i);
+    // Y = G(:, c) - Q W, formed in the basis slot of Q_i
+    if (f.mode == M_F64)
+      nn<double>(cx, Qi, f.ldq, (const double*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
+                 sm.W, b, b, m, -1.0, ctrl, i);
+    else
+      nn<float>(cx, Qi, f.ldq, (const float*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
+                sm.W, b, b, m, -1.0, ctrl, i);
+    // T = Q^T Y
+    tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.T, b, ctrl, i);
+    // [Q_i, R_i] = qr(Y), in place
+    tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R1, ctrl, i);
+    // C = Q^T Q_i; Q_i <- Q_i - Q C; [Q_i, R~_i] = qr(Q_i)
+    tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
+    nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+    tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R2, ctrl, i);
+    if (!cx.ok()) break;
+    // R_i = R~_i R_i and the rank guard
+    hipLaunchKernelGGL(k_guard, dim3(1), dim3(256), 0, stream, sm.R1, sm.R2, sm.R, b, i, t, ctrl);
+    cx.chk();
+    hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((int64_t)b * m)), dim3(TPB), 0, stream, f.Q,
+                       f.ldq, m, c0, b, ctrl, i);
+    cx.chk();
+    // N = H(:, c) - B^T (T + W);  B_i^T = N R_i^{-1}
+    if (p > 0) {
+      hipLaunchKernelGGL(k_add_small, dim3(1), dim3(256), 0, stream, sm.T, sm.W, sm.Wn, p * b,
+                         ctrl, i);
+      cx.chk();
+    }
+    nn<double>(cx, f.Wn, f.ldb, f.H + (int64_t)c0 * f.ldh, f.ldh, f.Bt, f.ldb, p, sm.Wn, b, b, n,
+               -1.0, ctrl, i);
+    if (!cx.ok()) break;
+    if (b <= 8)
+      hipLaunchKernelGGL(k_trsm_rows<8>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
+                         sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
+    else if (b <= 16)
+      hipLaunchKernelGGL(k_trsm_rows<16>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
+                         sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
+    else
+      hipLaunchKernelGGL(k_trsm_rows<32>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
+                         sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
+    cx.chk();
+  }
+  if (!cx.ok()) return cx.err;
+
+  // the rank decided on the device sizes the rest
+  Ctrl hc;
+  cx.err = hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
+  if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+  if (!cx.ok()) return cx.err;
+  const int L = hc.l_eff;
+  const int kk = (f.k < L) ? f.k : L;
+
+  if (L > 0) {
+    // ---------------- B^T = Q_B R_B (panels of width b, re-orthogonalised)
+    cx.err = launch_fill_f64(sm.RB, (int64_t)L * L, 0.0, stream);
+    for (int c0 = 0; c0 < L && cx.ok(); c0 += b) {
+      const int w = (L - c0 < b) ? (L - c0) : b;
+      double* Qp = f.Qb + (int64_t)c0 * f.ldb;
+      const double* Bp = f.Bt + (int64_t)c0 * f.ldb;
+      tn(cx, f.Qb, f.ldb, Bp, f.ldb, c0, w, n, f.red_ws, sm.C1, w, nullptr, 0);
+      nn<double>(cx, Qp, f.ldb, Bp, f.ldb, f.Qb, f.ldb, c0, sm.C1, w, w, n, -1.0, nullptr, 0);
+      tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R1, nullptr, 0);
+      tn(cx, f.Qb, f.ldb, Qp, f.ldb, c0, w, n, f.red_ws, sm.C2, w, nullptr, 0);
+      nn<double>(cx, Qp, f.ldb, Qp, f.ldb, f.Qb, f.ldb, c0, sm.C2, w, w, n, -1.0, nullptr, 0);
+      tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R2, nullptr, 0);
+      if (!cx.ok()) break;
+      hipLaunchKernelGGL(k_rb_assemble, dim3(1), dim3(256), 0, stream, sm.C1, sm.C2, sm.R1, sm.R2,
+                         sm.RB, L, c0, w);
+      cx.chk();
+    }
+    if (!cx.ok()) return cx.err;
+    // ---------------- Jacobi SVD of R_B^T
+    const int N = (L + 1) & ~1;
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), (size_t)N * L * sizeof(double), stream,
+                       sm.RB, L, L, sm.Wm, L, sm.log, sm.info, sm.sig, sm.perm);
+    cx.chk();
+    if (!cx.ok()) return cx.err;
+    hipLaunchKernelGGL(k_jacobi_apply, dim3(1), dim3(1024), (size_t)N * N * sizeof(double), stream,
+                       sm.log, sm.info, L, sm.Jm, L);
+    cx.chk();
+    if (!cx.ok()) return cx.err;
+    hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, stream, sm.Jm, sm.Wm, L, L, sm.perm,
+                       sm.sig, kk, sm.Jk, sm.Wk);
+    cx.chk();
+    // V (column-major temp in the H storage) = Q_B Jk, signs, then the row-major outputs
+    double* Vt = const_cast<double*>(f.H);
+    hipLaunchKernelGGL(k_write_rows, dim3(grid_for(n, TPB, 8192)), dim3(TPB),
+                       (size_t)L * kk * sizeof(double), stream, f.Qb, f.ldb, L, sm.Jk, kk, kk,
+                       (const double*)nullptr, n, Vt, f.ldh, 1);
+    cx.chk();
+    if (!cx.ok()) return cx.err;
+    hipLaunchKernelGGL(k_signs, dim3(kk), dim3(TPB), 0, stream, Vt, f.ldh, n, sm.sgn);
+    cx.chk();
+    if (!cx.ok()) return cx.err;
+    // V = Vt with signs: reuse k_write_rows with X = Vt and Wk = identity would cost a pass; write
+    // directly from Q_B instead.
+    hipLaunchKernelGGL(k_write_rows, dim3(grid_for(n, TPB, 8192)), dim3(TPB),
+                       (size_t)L * kk * sizeof(double), stream, f.Qb, f.ldb, L, sm.Jk, kk, f.k,
+                       sm.sgn, n, f.V, f.ldv, 0);
+    cx.chk();
+    if (f.U && cx.ok()) {
+      hipLaunchKernelGGL(k_write_rows, dim3(grid_for(m, TPB, 8192)), dim3(TPB),
+                         (size_t)L * kk * sizeof(double), stream, f.Q, f.ldq, L, sm.Wk, kk, f.k,
+                         sm.sgn, m, f.U, f.ldu, 0);
+      cx.chk();
+    }
+    if (!cx.ok()) return cx.err;
+    hipLaunchKernelGGL(k_write_s, dim3(1), dim3(256), 0, stream, sm.sig, kk, f.k, f.S);
+    cx.chk();
+  } else {
+    // rank 0: all outputs zero
+    double zero_s = 0.0;
+    (void)zero_s;
+    cx.err = launch_fill_f64(f.S, f.k, 0.0, stream);
+    for (int64_t r = 0; r < 1 && cx.ok(); ++r) {
+      hipLaunchKernelGGL(k_write_rows, dim3(grid_for(n, TPB, 8192)), dim3(TPB), 8, stream, f.Qb,
+                         f.ldb, 0, sm.Jk, 0, f.k, sm.sgn, n, f.V, f.ldv, 0);
+      cx.chk();
+      if (f.U && cx.ok()) {
+        hipLaunchKernelGGL(k_write_rows, dim3(grid_for(m, TPB, 8192)), dim3(TPB), 8, stream, f.Q,
+                           f.ldq, 0, sm.Wk, 0, f.k, sm.sgn, m, f.U, f.ldu, 0);
+        cx.chk();
+      }
+    }
+  }
+  if (!cx.ok()) return cx.err;
+  return hipStreamSynchronize(stream);
+}
+
+}  // namespace sk

@@ -1,0 +1,89 @@
+// Host-side launchers of the device kernels (one translation unit per kernel family).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "common.hpp"
+
+namespace sk {
+
+// ---------------------------------------------------------------- test matrix Omega (Alg. 4 step 3)
+hipError_t launch_omega_philox(uint64_t seed, int64_t n, int l, double* om64, int64_t ldo,
+                               hipStream_t s);
+hipError_t launch_omega_user(const double* src, int64_t ld, int64_t n, int l, double* om64,
+                             int64_t ldo, hipStream_t s);
+// Rounds Omega (column-major, l columns of length n, ld = NP) to the operand format of `mode`,
+// writing the operand copy `omc` (LP x NP, zero padded) and replacing om64 by Omega' in FP64.
+hipError_t launch_omega_quantize(int mode, int64_t n, int64_t NP, int l, int LP, double* om64,
+                                 void* omc, hipStream_t s);
+hipError_t launch_philox_words(uint64_t seed, uint64_t first, int64_t count, uint64_t* out,
+                               hipStream_t s);
+
+// ---------------------------------------------------------------- streaming pass (Alg. 4 steps 5-7)
+struct PassArgs {
+  int mode;            // Mode
+  int src;             // sketch_dtype of the rows actually read by the kernels (F64/F32/BF16,
+                       // or FP8 for pre-quantised staging)
+  const void* A;       // nrows x n row-major block
+  int64_t lda;         // elements
+  int nrows;
+  int64_t n;
+  const void* omc;     // Omega' operand copy, LP x NP column-major
+  int64_t NP;
+  int LP;              // l rounded up to 16
+  int NT;              // LP / 16
+  void* P1;            // split partials of g = a Omega: splits x LP x ldp
+  int64_t ldp;
+  int splits;
+  int64_t kchunk;      // columns per split (multiple of 512)
+  void* G;             // G, LP x ldg column-major (FP64 in F64 mode, FP32 otherwise)
+  int64_t ldg;
+  int64_t g_row0;      // first row of this block in G
+  double* H;           // H, LP x ldh column-major, FP64
+  int64_t ldh;
+  const int* fp8_exp;  // device exponent e of the block scale 2^e (FP8 mode), else null
+  Ctrl* ctrl;
+};
+int gemm1_row_tile(int mode);
+hipError_t launch_gemm1(const PassArgs& a, hipStream_t s);
+hipError_t launch_reduce1(const PassArgs& a, hipStream_t s);
+hipError_t launch_gemm2(const PassArgs& a, hipStream_t s);
+// FP8 mode: amax of the block, then a' = e4m3(a 2^e) into `q` (nrows x ldq bytes).
+hipError_t launch_fp8_quantize(const float* A, int64_t lda, int nrows, int64_t n, uint32_t* amax,
+                               uint8_t* q, int64_t ldq, int* exp_out, hipStream_t s);
+
+// ---------------------------------------------------------------- small helpers
+hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
+// rows x cols block of a row-major matrix with leading dimension ld
+hipError_t launch_fill_rows(double* p, int64_t rows, int cols, int64_t ld, double v,
+                            hipStream_t s);
+hipError_t launch_copy_state(int mode, const void* G, int64_t ldg, int64_t rows, const double* H,
+                             int64_t ldh, int64_t n, int l, double* Gout, double* Hout,
+                             hipStream_t s);
+hipError_t launch_copy_omega_out(const double* om64, int64_t ldo, int64_t n, int l, double* out,
+                                 int64_t ld, hipStream_t s);
+
+// ---------------------------------------------------------------- finalize (Alg. 4 steps 9-19)
+struct FinalizeArgs {
+  int mode;
+  int64_t m, n;
+  int k, l, b, LP;
+  const void* G; int64_t ldg;        // m-side, column-major
+  const double* H; int64_t ldh;      // n-side, column-major
+  const double* om64; int64_t ldo;   // Omega' (FP64), n-side
+  double* Q; int64_t ldq;            // m x l basis
+  double* Bt; double* Qb; int64_t ldb;   // B^T and the Q factor of B^T, n-side
+  double* Wn;                        // n x b work (ld = ldb)
+  double* tsqr_ws; int64_t tsqr_ws_elems;
+  double* red_ws; int64_t red_ws_elems;
+  double* small;                     // small matrices, see finalize.hip
+  Ctrl* ctrl;
+  double* S; double* U; int64_t ldu; double* V; int64_t ldv;
+};
+hipError_t finalize_prepare();
+size_t finalize_small_elems(int l, int b);
+size_t tsqr_workspace_elems(int64_t rows, int b);
+size_t reduce_workspace_elems(int64_t rows, int p, int q);
+hipError_t run_finalize(const FinalizeArgs& f, hipStream_t s);
+
+}  // namespace sk

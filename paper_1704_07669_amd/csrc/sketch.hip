@@ -1,0 +1,591 @@
+// Runtime and C ABI of the single-pass PCA library (see include/sketch.h).
+//
+// Device state lives in the caller's workspace, carved here.  All kernels run on the caller's
+// stream; pinned-host blocks are copied on a library-owned side stream into a ring of device
+// staging slots, with events ordering copy -> compute and compute -> reuse of the slot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sketch.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace sk;
+
+namespace {
+
+thread_local std::string g_err;
+
+sketch_status fail(sketch_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+constexpr int kRing = 16;          // per-ticket completion events
+constexpr int64_t kAlign = 256;    // workspace carve alignment (bytes)
+constexpr int kNpAlign = 512;      // n padding: multiple of every k-chunk of g = a Omega
+constexpr int kMaxSplits = 64;
+
+int src_size(int dt) {
+  switch (dt) {
+    case SKETCH_F64: return 8;
+    case SKETCH_F32: return 4;
+    case SKETCH_BF16: return 2;
+    default: return 0;
+  }
+}
+
+bool mode_accepts(int mode, int src) {
+  switch (mode) {
+    case SKETCH_F64: return src == SKETCH_F64 || src == SKETCH_F32;
+    case SKETCH_F32: return src == SKETCH_F32;
+    case SKETCH_BF16: return src == SKETCH_F32 || src == SKETCH_BF16;
+    case SKETCH_BF16X2: return src == SKETCH_F32;
+    case SKETCH_FP8_E4M3: return src == SKETCH_F32;
+    default: return false;
+  }
+}
+
+int op_size(int mode) {
+  switch (mode) {
+    case SKETCH_F64: return 8;
+    case SKETCH_F32: return 4;
+    case SKETCH_BF16:
+    case SKETCH_BF16X2: return 2;
+    default: return 1;
+  }
+}
+
+struct Layout {
+  int LP, NT, t, splits_max;
+  int64_t NP, MCAP, RBP, LDST, NQ;
+  int64_t off_ctrl, off_fp8, off_om64, off_omc, off_G, off_H, off_P1, off_stage, off_fp8q,
+      off_Q, off_Bt, off_Qb, off_Wn, off_tsqr, off_red, off_small, total;
+  int64_t stage_slot_bytes;
+  int64_t tsqr_elems, red_elems;
+};
+
+const char* validate(const sketch_config* c) {
+  if (!c) return "config is NULL";
+  if (c->n < 1) return "n must be >= 1";
+  if (c->m_capacity < 1) return "m_capacity must be >= 1";
+  if (c->max_block_rows < 1) return "max_block_rows must be >= 1";
+  if (c->max_block_rows > (int64_t)1 << 30) return "max_block_rows too large";
+  if (c->l < 1 || c->l > 128) return "l must be in [1, 128]";
+  if (c->k < 1 || c->k > c->l) return "k must be in [1, l]";
+  if (c->b < 1 || c->b > 32 || c->l % c->b != 0) return "b must be in [1, 32] and divide l";
+  if (c->l > c->n) return "l must be <= n";
+  if (c->compute < SKETCH_F64 || c->compute > SKETCH_FP8_E4M3) return "unknown compute mode";
+  if (c->host_slots != 0 && (c->host_slots < 2 || c->host_slots > 4))
+    return "host_slots must be 0 or 2..4";
+  if (c->host_slots > 0 && !mode_accepts(c->compute, c->host_src))
+    return "host_src not supported by the compute mode";
+  if (c->want_u != 0 && c->want_u != 1) return "want_u must be 0 or 1";
+  if (c->omega_from_seed != 0 && c->omega_from_seed != 1) return "omega_from_seed must be 0 or 1";
+  return nullptr;
+}
+
+Layout plan(const sketch_config* c) {
+  Layout L{};
+  L.LP = (int)rup<int64_t>(c->l, 16);
+  L.NT = L.LP / 16;
+  L.t = c->l / c->b;
+  L.NP = rup<int64_t>(c->n, kNpAlign);
+  L.MCAP = rup<int64_t>(c->m_capacity, 64);
+  L.RBP = rup<int64_t>(c->max_block_rows, 16);
+  L.splits_max = (int)std::min<int64_t>(kMaxSplits, L.NP / kNpAlign);
+  L.LDST = rup<int64_t>(c->n, 64);
+  L.NQ = rup<int64_t>(c->n, kNpAlign);
+  const int gsz = (c->compute == SKETCH_F64) ? 8 : 4;
+  L.stage_slot_bytes =
+      c->host_slots > 0 ? rup<int64_t>(c->max_block_rows * L.LDST * src_size(c->host_src), kAlign)
+                        : 0;
+  const int64_t rows_max = std::max<int64_t>(L.MCAP, L.NP);
+  L.tsqr_elems = (int64_t)tsqr_workspace_elems(rows_max, c->b);
+  L.red_elems = (int64_t)reduce_workspace_elems(rows_max, c->l, c->b);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { const int64_t r = off; off += rup<int64_t>(bytes, kAlign); return r; };
+  L.off_ctrl = take(sizeof(Ctrl));
+  L.off_fp8 = take(64);
+  L.off_om64 = take((int64_t)L.LP * L.NP * 8);
+  L.off_omc = take((int64_t)L.LP * L.NP * op_size(c->compute));
+  L.off_G = take((int64_t)L.LP * L.MCAP * gsz);
+  L.off_H = take((int64_t)L.LP * L.NP * 8);
+  L.off_P1 = take((int64_t)L.splits_max * L.LP * L.RBP * gsz);
+  L.off_stage = take(L.stage_slot_bytes * c->host_slots);
+  L.off_fp8q = take(c->compute == SKETCH_FP8_E4M3 ? c->max_block_rows * L.NQ : 0);
+  L.off_Q = take((int64_t)L.LP * L.MCAP * 8);
+  L.off_Bt = take((int64_t)L.LP * L.NP * 8);
+  L.off_Qb = take((int64_t)L.LP * L.NP * 8);
+  L.off_Wn = take((int64_t)32 * L.NP * 8);
+  L.off_tsqr = take(L.tsqr_elems * 8);
+  L.off_red = take(L.red_elems * 8);
+  L.off_small = take((int64_t)finalize_small_elems(c->l, c->b) * 8);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct sketch_s {
+  sketch_config cfg;
+  Layout lay;
+  uint8_t* ws = nullptr;
+  hipStream_t stream = nullptr;
+  hipStream_t copy = nullptr;
+  int device = 0;
+  // state
+  int64_t rows = 0;
+  int phase = 0;                    // 0: needs Omega, 1: ingesting, 2: finalized
+  sketch_status sticky = SKETCH_OK;
+  uint64_t next_ticket = 1;
+  hipEvent_t done_ev[kRing] = {};
+  hipEvent_t copy_ev[kRing] = {};
+  uint64_t ring_ticket[kRing] = {};
+  bool ring_host[kRing] = {};
+  hipEvent_t slot_consumed[4] = {};
+  bool slot_used[4] = {};
+  int next_slot = 0;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_free;
+  struct Rec { hipEvent_t a, b, c; int kind; };
+  std::vector<Rec> recs;
+  int64_t prof_n[3] = {0, 0, 0};
+  double prof_ms[3] = {0, 0, 0};
+
+  template <typename T> T* at(int64_t off) { return reinterpret_cast<T*>(ws + off); }
+  Ctrl* ctrl() { return at<Ctrl>(lay.off_ctrl); }
+
+  sketch_status dev_fail(hipError_t e, const char* what) {
+    sticky = SKETCH_E_DEVICE;
+    return fail(SKETCH_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  }
+  hipEvent_t take_event() {
+    if (!ev_free.empty()) { hipEvent_t e = ev_free.back(); ev_free.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+namespace {
+
+sketch_status check_handle(sketch_t h) {
+  if (!h) return fail(SKETCH_E_INVAL, "handle is NULL");
+  if (h->sticky != SKETCH_OK)
+    return fail(h->sticky, "handle is in a sticky error state (%d)", (int)h->sticky);
+  return SKETCH_OK;
+}
+
+sketch_status make_omega_ready(sketch_t h) {
+  const Layout& L = h->lay;
+  hipError_t e = launch_omega_quantize(h->cfg.compute, h->cfg.n, L.NP, h->cfg.l, L.LP,
+                                       h->at<double>(L.off_om64), h->ws + L.off_omc, h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "omega quantize");
+  return SKETCH_OK;
+}
+
+sketch_status start_pass(sketch_t h) {
+  const Layout& L = h->lay;
+  hipError_t e = launch_fill_f64(h->at<double>(L.off_H), (int64_t)L.LP * L.NP, 0.0, h->stream);
+  if (e == hipSuccess)
+    e = launch_fill_u32(reinterpret_cast<uint32_t*>(h->ctrl()), sizeof(Ctrl) / 4, 0u, h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "reset state");
+  h->rows = 0;
+  if (h->cfg.omega_from_seed) {
+    e = launch_omega_philox(h->cfg.seed, h->cfg.n, h->cfg.l, h->at<double>(L.off_om64), L.NP,
+                            h->stream);
+    if (e != hipSuccess) return h->dev_fail(e, "omega generation");
+    sketch_status st = make_omega_ready(h);
+    if (st != SKETCH_OK) return st;
+    h->phase = 1;
+  } else {
+    h->phase = (h->phase == 0) ? 0 : 1;   // a supplied Omega' stays valid across resets
+  }
+  return SKETCH_OK;
+}
+
+bool is_pinned_host(const void* p) {
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof(at));
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeHost;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sketch_last_error(void) { return g_err.c_str(); }
+
+size_t sketch_workspace_size(const sketch_config* cfg) {
+  if (const char* why = validate(cfg)) {
+    fail(SKETCH_E_INVAL, "%s", why);
+    return 0;
+  }
+  return (size_t)plan(cfg).total;
+}
+
+sketch_status sketch_init(sketch_t* out, const sketch_config* cfg, void* dev_ws, size_t ws_bytes,
+                          void* hip_stream) {
+  if (!out) return fail(SKETCH_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (const char* why = validate(cfg)) return fail(SKETCH_E_INVAL, "%s", why);
+  const Layout L = plan(cfg);
+  if (!dev_ws) return fail(SKETCH_E_INVAL, "workspace is NULL");
+  if (((uintptr_t)dev_ws) % kAlign) return fail(SKETCH_E_INVAL, "workspace must be 256-byte aligned");
+  if ((int64_t)ws_bytes < L.total)
+    return fail(SKETCH_E_NOMEM, "workspace holds %zu bytes, %lld needed", ws_bytes,
+                (long long)L.total);
+  static bool prepared = false;
+  if (!prepared) {
+    hipError_t e = finalize_prepare();
+    if (e != hipSuccess) return fail(SKETCH_E_DEVICE, "kernel attributes: %s", hipGetErrorString(e));
+    prepared = true;
+  }
+  sketch_s* h = new sketch_s();
+  h->cfg = *cfg;
+  h->lay = L;
+  h->ws = (uint8_t*)dev_ws;
+  h->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess && cfg->host_slots > 0)
+    e = hipStreamCreateWithFlags(&h->copy, hipStreamNonBlocking);
+  for (int i = 0; i < kRing && e == hipSuccess; ++i) {
+    e = hipEventCreateWithFlags(&h->done_ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->copy_ev[i], hipEventDisableTiming);
+  }
+  for (int i = 0; i < cfg->host_slots && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&h->slot_consumed[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    sketch_destroy(h);
+    return fail(SKETCH_E_DEVICE, "stream/event creation: %s", hipGetErrorString(e));
+  }
+  sketch_status st = start_pass(h);
+  if (st != SKETCH_OK) {
+    sketch_destroy(h);
+    return st;
+  }
+  *out = h;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_reset(sketch_t h, uint64_t seed) {
+  if (sketch_status st = check_handle(h)) return st;
+  h->cfg.seed = seed;
+  return start_pass(h);
+}
+
+sketch_status sketch_set_omega(sketch_t h, const double* omega_dev, int64_t ld) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (h->cfg.omega_from_seed) return fail(SKETCH_E_STATE, "handle draws its own Omega");
+  if (h->rows > 0 || h->phase == 2) return fail(SKETCH_E_STATE, "Omega must precede the first ingest");
+  if (!omega_dev || ld < h->cfg.l) return fail(SKETCH_E_INVAL, "bad Omega pointer or ld");
+  const Layout& L = h->lay;
+  hipError_t e = launch_fill_f64(h->at<double>(L.off_om64), (int64_t)L.LP * L.NP, 0.0, h->stream);
+  if (e == hipSuccess)
+    e = launch_omega_user(omega_dev, ld, h->cfg.n, h->cfg.l, h->at<double>(L.off_om64), L.NP,
+                          h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "set omega");
+  sketch_status st = make_omega_ready(h);
+  if (st != SKETCH_OK) return st;
+  h->phase = 1;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtype, int64_t nrows,
+                                  int64_t ld, int32_t src_is_device, uint64_t* ticket) {
+  if (sketch_status st = check_handle(h)) return st;
+  const sketch_config& c = h->cfg;
+  const Layout& L = h->lay;
+  if (h->phase == 0) return fail(SKETCH_E_STATE, "Omega has not been supplied");
+  if (h->phase == 2) return fail(SKETCH_E_STATE, "ingest after finalize (call sketch_reset)");
+  if (!rows) return fail(SKETCH_E_INVAL, "rows is NULL");
+  if (nrows < 1) return fail(SKETCH_E_INVAL, "nrows must be >= 1");
+  if (ld < c.n) return fail(SKETCH_E_INVAL, "ld must be >= n");
+  if (src_is_device != 0 && src_is_device != 1) return fail(SKETCH_E_INVAL, "src_is_device must be 0 or 1");
+  if (!mode_accepts(c.compute, src_dtype))
+    return fail(SKETCH_E_INVAL, "source format %d not supported by compute mode %d", src_dtype,
+                c.compute);
+  if (nrows > c.max_block_rows)
+    return fail(SKETCH_E_CAPACITY, "block of %lld rows exceeds max_block_rows %lld",
+                (long long)nrows, (long long)c.max_block_rows);
+  if (h->rows + nrows > c.m_capacity)
+    return fail(SKETCH_E_CAPACITY, "m_capacity %lld exceeded", (long long)c.m_capacity);
+  const int es = src_size(src_dtype);
+  const void* A = rows;
+  int64_t lda = ld;
+  const uint64_t tk = h->next_ticket;
+  const int ring = (int)(tk % kRing);
+  hipError_t e = hipSuccess;
+  int slot = -1;
+  if (!src_is_device) {
+    if (c.host_slots == 0) return fail(SKETCH_E_INVAL, "handle has no host staging slots");
+    if (src_dtype != c.host_src) return fail(SKETCH_E_INVAL, "src_dtype differs from host_src");
+    if (!is_pinned_host(rows)) return fail(SKETCH_E_INVAL, "host rows must be pinned (hipHostMalloc)");
+    slot = h->next_slot;
+    h->next_slot = (h->next_slot + 1) % c.host_slots;
+    uint8_t* dst = h->ws + L.off_stage + (int64_t)slot * L.stage_slot_bytes;
+    if (h->slot_used[slot]) e = hipStreamWaitEvent(h->copy, h->slot_consumed[slot], 0);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(dst, L.LDST * es, rows, ld * es, c.n * es, nrows,
+                           hipMemcpyHostToDevice, h->copy);
+    if (e == hipSuccess) e = hipEventRecord(h->copy_ev[ring], h->copy);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->copy_ev[ring], 0);
+    if (e != hipSuccess) return h->dev_fail(e, "host block copy");
+    A = dst;
+    lda = L.LDST;
+  }
+
+  PassArgs a{};
+  a.mode = c.compute;
+  a.src = src_dtype;
+  a.A = A;
+  a.lda = lda;
+  a.nrows = (int)nrows;
+  a.n = c.n;
+  a.omc = h->ws + L.off_omc;
+  a.NP = L.NP;
+  a.LP = L.LP;
+  a.NT = L.NT;
+  a.P1 = h->ws + L.off_P1;
+  a.ldp = L.RBP;
+  a.G = h->ws + L.off_G;
+  a.ldg = L.MCAP;
+  a.g_row0 = h->rows;
+  a.H = h->at<double>(L.off_H);
+  a.ldh = L.NP;
+  a.fp8_exp = nullptr;
+  a.ctrl = h->ctrl();
+  if (c.compute == SKETCH_FP8_E4M3) {
+    uint32_t* amax = h->at<uint32_t>(L.off_fp8);
+    int* ex = reinterpret_cast<int*>(amax + 4);
+    uint8_t* q = h->ws + L.off_fp8q;
+    e = launch_fp8_quantize((const float*)A, lda, (int)nrows, c.n, amax, q, L.NQ, ex, h->stream);
+    if (e != hipSuccess) return h->dev_fail(e, "fp8 quantize");
+    a.A = q;
+    a.lda = L.NQ;
+    a.src = 4;
+    a.fp8_exp = ex;
+  }
+  // k splits of g = a Omega: enough workgroups to fill the chip
+  const int64_t row_tiles = cdiv<int64_t>(nrows, gemm1_row_tile(c.compute));
+  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(L.splits_max, cdiv<int64_t>(1024, row_tiles)));
+  a.kchunk = rup<int64_t>(cdiv<int64_t>(c.n, splits), kNpAlign);
+  a.splits = (int)cdiv<int64_t>(c.n, a.kchunk);
+
+  sketch_s::Rec rec{};
+  if (h->prof) {
+    rec.a = h->take_event(); rec.b = h->take_event(); rec.c = h->take_event(); rec.kind = 0;
+    if (!rec.a || !rec.b || !rec.c) return h->dev_fail(hipErrorOutOfMemory, "profiling events");
+    e = hipEventRecord(rec.a, h->stream);
+  }
+  if (e == hipSuccess) e = launch_gemm1(a, h->stream);
+  if (e == hipSuccess) e = launch_reduce1(a, h->stream);
+  if (e == hipSuccess && h->prof) e = hipEventRecord(rec.b, h->stream);
+  if (e == hipSuccess) e = launch_gemm2(a, h->stream);
+  if (e == hipSuccess && h->prof) e = hipEventRecord(rec.c, h->stream);
+  if (e == hipSuccess) e = hipEventRecord(h->done_ev[ring], h->stream);
+  if (e == hipSuccess && slot >= 0) {
+    e = hipEventRecord(h->slot_consumed[slot], h->stream);
+    h->slot_used[slot] = true;
+  }
+  if (e != hipSuccess) return h->dev_fail(e, "pass kernels");
+  if (h->prof) h->recs.push_back(rec);
+  h->ring_ticket[ring] = tk;
+  h->ring_host[ring] = (slot >= 0);
+  h->next_ticket = tk + 1;
+  h->rows += nrows;
+  if (ticket) *ticket = tk;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_poll(sketch_t h, uint64_t ticket, int32_t* done) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (!done) return fail(SKETCH_E_INVAL, "done is NULL");
+  if (ticket == 0 || ticket >= h->next_ticket) return fail(SKETCH_E_INVAL, "unknown ticket");
+  const int ring = (int)(ticket % kRing);
+  hipEvent_t ev;
+  if (h->ring_ticket[ring] == ticket)
+    ev = h->ring_host[ring] ? h->copy_ev[ring] : h->done_ev[ring];
+  else
+    ev = h->done_ev[ring];   // a later ticket reused the slot; its completion implies ours
+  hipError_t e = hipEventQuery(ev);
+  if (e == hipSuccess) { *done = 1; return SKETCH_OK; }
+  if (e == hipErrorNotReady) { *done = 0; return SKETCH_OK; }
+  return h->dev_fail(e, "poll");
+}
+
+sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t ldu,
+                              double* V_dev, int64_t ldv, int32_t* rank_out) {
+  if (sketch_status st = check_handle(h)) return st;
+  const sketch_config& c = h->cfg;
+  const Layout& L = h->lay;
+  if (h->phase != 1) return fail(SKETCH_E_STATE, h->phase == 2 ? "already finalized" : "Omega has not been supplied");
+  if (!S_dev || !V_dev) return fail(SKETCH_E_INVAL, "S and V are required");
+  if (ldv < c.k) return fail(SKETCH_E_INVAL, "ldv must be >= k");
+  if (U_dev && !c.want_u) return fail(SKETCH_E_INVAL, "U requested but want_u = 0");
+  if (U_dev && ldu < c.k) return fail(SKETCH_E_INVAL, "ldu must be >= k");
+  hipError_t e = hipSuccess;
+  hipEvent_t fa = nullptr, fb = nullptr;
+  if (h->prof) {
+    fa = h->take_event(); fb = h->take_event();
+    e = hipEventRecord(fa, h->stream);
+  }
+  if (h->rows == 0) {
+    if (e == hipSuccess) e = launch_fill_f64(S_dev, c.k, 0.0, h->stream);
+    if (e == hipSuccess) e = launch_fill_rows(V_dev, c.n, c.k, ldv, 0.0, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->dev_fail(e, "finalize");
+    if (rank_out) *rank_out = 0;
+    h->phase = 2;
+    return SKETCH_OK;
+  }
+  FinalizeArgs f{};
+  f.mode = c.compute;
+  f.m = h->rows;
+  f.n = c.n;
+  f.k = c.k;
+  f.l = c.l;
+  f.b = c.b;
+  f.LP = L.LP;
+  f.G = h->ws + L.off_G;
+  f.ldg = L.MCAP;
+  f.H = h->at<double>(L.off_H);
+  f.ldh = L.NP;
+  f.om64 = h->at<double>(L.off_om64);
+  f.ldo = L.NP;
+  f.Q = h->at<double>(L.off_Q);
+  f.ldq = L.MCAP;
+  f.Bt = h->at<double>(L.off_Bt);
+  f.Qb = h->at<double>(L.off_Qb);
+  f.ldb = L.NP;
+  f.Wn = h->at<double>(L.off_Wn);
+  f.tsqr_ws = h->at<double>(L.off_tsqr);
+  f.tsqr_ws_elems = L.tsqr_elems;
+  f.red_ws = h->at<double>(L.off_red);
+  f.red_ws_elems = L.red_elems;
+  f.small = h->at<double>(L.off_small);
+  f.ctrl = h->ctrl();
+  f.S = S_dev;
+  f.U = U_dev;
+  f.ldu = ldu;
+  f.V = V_dev;
+  f.ldv = ldv;
+  if (e == hipSuccess) e = run_finalize(f, h->stream);
+  if (e == hipSuccess && h->prof) e = hipEventRecord(fb, h->stream);
+  Ctrl hc;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hc, h->ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "finalize");
+  if (h->prof) h->recs.push_back({fa, fb, nullptr, 2});
+  h->phase = 2;
+  if (hc.nonfinite) {
+    h->sticky = SKETCH_E_NONFINITE;
+    return fail(SKETCH_E_NONFINITE, "an ingested block held NaN or Inf");
+  }
+  if (rank_out) *rank_out = hc.l_eff;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_get_omega(sketch_t h, double* omega_dev, int64_t ld) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (h->phase == 0) return fail(SKETCH_E_STATE, "Omega has not been supplied");
+  if (!omega_dev || ld < h->cfg.l) return fail(SKETCH_E_INVAL, "bad output pointer or ld");
+  hipError_t e = launch_copy_omega_out(h->at<double>(h->lay.off_om64), h->lay.NP, h->cfg.n,
+                                       h->cfg.l, omega_dev, ld, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "get omega");
+  return SKETCH_OK;
+}
+
+sketch_status sketch_debug_state(sketch_t h, double* G_dev, double* H_dev, int64_t* rows_out) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (h->phase == 2) return fail(SKETCH_E_STATE, "state is consumed by finalize");
+  hipError_t e = launch_copy_state(h->cfg.compute, h->ws + h->lay.off_G, h->lay.MCAP, h->rows,
+                                   h->at<double>(h->lay.off_H), h->lay.NP, h->cfg.n, h->cfg.l,
+                                   G_dev, H_dev, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "debug state");
+  if (rows_out) *rows_out = h->rows;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_philox_words(uint64_t seed, uint64_t first, int64_t count, uint64_t* out_dev,
+                                  void* hip_stream) {
+  if (count < 0 || (count > 0 && !out_dev)) return fail(SKETCH_E_INVAL, "bad output");
+  if (count == 0) return SKETCH_OK;
+  hipError_t e = launch_philox_words(seed, first, count, out_dev, (hipStream_t)hip_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(SKETCH_E_DEVICE, "philox: %s", hipGetErrorString(e));
+  return SKETCH_OK;
+}
+
+sketch_status sketch_profile_enable(sketch_t h, int32_t on) {
+  if (sketch_status st = check_handle(h)) return st;
+  h->prof = (on != 0);
+  return SKETCH_OK;
+}
+
+sketch_status sketch_profile_read(sketch_t h, int32_t kind, int64_t* launches, double* total_ms) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (kind < 0 || kind > 2 || !launches || !total_ms) return fail(SKETCH_E_INVAL, "bad arguments");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "profile sync");
+  for (auto& r : h->recs) {
+    float ms = 0.f;
+    if (r.kind == 0) {
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) { h->prof_ms[0] += ms; h->prof_n[0]++; }
+      if (hipEventElapsedTime(&ms, r.b, r.c) == hipSuccess) { h->prof_ms[1] += ms; h->prof_n[1]++; }
+      h->ev_free.push_back(r.c);
+    } else {
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) { h->prof_ms[2] += ms; h->prof_n[2]++; }
+    }
+    h->ev_free.push_back(r.a);
+    h->ev_free.push_back(r.b);
+  }
+  h->recs.clear();
+  *launches = h->prof_n[kind];
+  *total_ms = h->prof_ms[kind];
+  h->prof_n[kind] = 0;
+  h->prof_ms[kind] = 0.0;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_destroy(sketch_t h) {
+  if (!h) return fail(SKETCH_E_INVAL, "handle is NULL");
+  (void)hipStreamSynchronize(h->stream);
+  if (h->copy) { (void)hipStreamSynchronize(h->copy); (void)hipStreamDestroy(h->copy); }
+  for (int i = 0; i < kRing; ++i) {
+    if (h->done_ev[i]) (void)hipEventDestroy(h->done_ev[i]);
+    if (h->copy_ev[i]) (void)hipEventDestroy(h->copy_ev[i]);
+  }
+  for (int i = 0; i < 4; ++i)
+    if (h->slot_consumed[i]) (void)hipEventDestroy(h->slot_consumed[i]);
+  for (auto& r : h->recs) {
+    if (r.a) (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
+    if (r.c) (void)hipEventDestroy(r.c);
+  }
+  for (auto ev : h->ev_free) (void)hipEventDestroy(ev);
+  delete h;
+  return SKETCH_OK;
+}
+
+}  // extern "C"
