@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Single-GPU benchmark of the single-pass PCA hot path (Algorithm 4) on MI355X.
+
+Workload (FP32-resident): A is 100000 x 20000 FP32 (8.0 GB) resident in HBM, sigma_j = 1/j for
+j <= 200 then 1e-4, with N(0, 1e-4) noise on sigma; k = 50, l = 100, b = 10; 25 row blocks of 4096
+rows (the last 1696).  A is generated on the GPU from a Kronecker-structured SVD whose spectrum is
+exactly known.  One step = one whole pass of the hot path: a new Omega from a seed (step 3), all
+row blocks ingested (steps 4-8), and the finalize (steps 9-19) returning S, V.
+
+The JSON line reports the headline mode (BF16 by default) and, under "compare", the FP32 mode,
+each as FP32-equivalent ingest GB/s (4 m n bytes per step / step time).  Accuracy of each mode is
+measured against the FP64 reference on the same stored A and the same Omega' (relative sigma_k
+error; the gate is 1e-3).  The reference also provides the CPU baseline, timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "A-ingest GB/s + % roofline, BF16 vs FP32 @ rel σ_k err≤1e-3; p99 block lat"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "fp8": 5000.0, "f64": 78.6}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="bf16", choices=["f32", "bf16", "bf16x2", "fp8", "f64"])
+    ap.add_argument("--compare", default="f32", help="second mode reported alongside ('' = none)")
+    ap.add_argument("--m", type=int, default=100000)
+    ap.add_argument("--n", type=int, default=20000)
+    ap.add_argument("--kron", default="500,200,100,200", help="m1,m2,n1,n2 with m=m1*m2, n=n1*n2")
+    ap.add_argument("--k", type=int, default=50)
+    ap.add_argument("--l", type=int, default=100)
+    ap.add_argument("--b", type=int, default=10)
+    ap.add_argument("--block", type=int, default=4096)
+    ap.add_argument("--check", default="full", choices=["full", "none"],
+                    help="FP64 reference accuracy check on the whole workload")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="budget of the CPU-baseline sample (0 = skip)")
+    ap.add_argument("--profile-steps", type=int, default=2)
+    return ap.parse_args()
+
+
+def make_matrix(args, torch):
+    import synth
+    m1, m2, n1, n2 = (int(x) for x in args.kron.split(","))
+    assert m1 * m2 == args.m and n1 * n2 == args.n, "--kron must factor m and n"
+    sig = synth.noisy_spectrum(synth.inv_floor_spectrum(args.n, knee=200, floor=1e-4), 1e-4, 1002)
+    K = synth.KronMatrix(m1, m2, n1, n2, sig, 1002)
+    A = torch.empty(args.m, args.n, dtype=torch.float32, device="cuda")
+    for r0 in range(0, args.m, 2048):
+        c = min(2048, args.m - r0)
+        K.rows_torch(r0, c, "cuda", out=A[r0:r0 + c])
+    torch.cuda.synchronize()
+    return A, K
+
+
+def run_step(sk_obj, A, block, seed):
+    sk_obj.reset(seed)
+    m = A.shape[0]
+    for r0 in range(0, m, block):
+        sk_obj.ingest(A[r0:r0 + block])
+    return sk_obj.finalize(want_u=False)
+
+
+def bench_mode(mode, A, args, torch, sk):
+    m, n = A.shape
+    obj = sk.Sketch(n, m, args.block, args.k, args.l, args.b, compute=mode, seed=2002)
+    for _ in range(args.warmup):
+        run_step(obj, A, args.block, 2002)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S, V, _, rank = run_step(obj, A, args.block, 2002)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / max(1, args.steps)
+    # per-kernel HIP-event timing (events on the launch stream around every launch)
+    obj.profile(True)
+    lat = []
+    for _ in range(args.profile_steps):
+        run_step(obj, A, args.block, 2002)
+    n1, t_g1 = obj.profile_read(0)
+    n2, t_g2 = obj.profile_read(1)
+    nf, t_fin = obj.profile_read(2)
+    obj.profile(False)
+    nblocks = (m + args.block - 1) // args.block
+    res = dict(mode=mode, ms_per_step=ms_step, value=4.0 * m * n / (ms_step * 1e-3) / 1e9,
+               rank=rank, S=S.cpu().numpy(), V=V.cpu().numpy(),
+               gemm1_ms=t_g1 / max(1, n1), gemm2_ms=t_g2 / max(1, n2),
+               finalize_ms=t_fin / max(1, nf), launches=(n1, n2, nf), nblocks=nblocks)
+    obj.close()
+    return res
+
+
+def block_latency(A, args, torch, sk, mode):
+    """Per-block ingest latency (enqueue to completion of that block's kernels), one block at a
+    time, on the resident workload."""
+    m, n = A.shape
+    obj = sk.Sketch(n, m, args.block, args.k, args.l, args.b, compute=mode, seed=7)
+    lat = []
+    for r0 in range(0, m, args.block):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obj.ingest(A[r0:r0 + args.block])
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    obj.close()
+    full = [x for i, x in enumerate(lat) if (i + 1) * args.block <= m] or lat
+    return float(np.percentile(full, 50)), float(np.percentile(full, 99))
+
+
+def roofline(res, m, n, l, mode):
+    """Dominant streaming kernel against its roof: HBM for the BF16/FP8 paths (algorithmic bytes
+    = the block's FP32 bytes, read once per launch), the matrix-core peak for FP32/FP64
+    (algorithmic flops = 2 l per element of the block, per launch)."""
+    dom, t = ("g = a Omega", res["gemm1_ms"]) if res["gemm1_ms"] >= res["gemm2_ms"] else \
+        ("H += a^T g", res["gemm2_ms"])
+    elems_per_launch = m * n / res["nblocks"]
+    if mode in ("f32", "f64"):
+        ach = 2.0 * l * elems_per_launch / (t * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFLOPS[mode]
+        out = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak)
+    else:
+        ach = 4.0 * elems_per_launch / (t * 1e-3) / 1e9
+        out = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS)
+    out["kernel"] = dom
+    out["traffic"] = traffic_for(dom, mode)
+    return out
+
+
+def traffic_for(kernel, mode):
+    """Counter-derived HBM bytes per launch recorded in profiles/traffic.json, valid only while the
+    kernel source is unchanged (its SHA-256 is stored next to the figure)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1704_07669_amd", "csrc", "pass.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+        ent = rec.get(f"{kernel}|{mode}")
+        if ent and ent.get("pass_hip_sha256") == h:
+            return ent["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
+def accuracy(A_host, K, res_modes, args):
+    """Relative sigma errors of each mode against the FP64 reference on the stored A with the same
+    Omega' (regenerated by the reference's own Philox/Box-Muller and rounding)."""
+    import oracle
+    m = A_host.shape[0]
+    Om = oracle.gaussian_omega_philox(args.n, args.l, 2002)
+    out = {}
+    for res in res_modes:
+        mode = res["mode"]
+        Omq = oracle.quantize_omega(Om, mode)
+        t0 = time.perf_counter()
+        blocks = (A_host[r0:r0 + args.block] for r0 in range(0, m, args.block))
+        ref = oracle.single_pass_pca(blocks, Omq, args.k, args.b, want_u=False)
+        t_ref = time.perf_counter() - t0
+        e = oracle.rel_sigma_error(res["S"], ref.S)
+        out[mode] = dict(rel_sigma_k_err=float(e[args.k - 1]), max_rel_sigma_err=float(e.max()),
+                         sin_theta_V=float(oracle.sin_theta_max(ref.V, res["V"])),
+                         rel_sigma_k_err_vs_known=float(abs(res["S"][args.k - 1] - K.sigma[args.k - 1])
+                                                        / K.sigma[args.k - 1]),
+                         reference_seconds=t_ref, gate_1e3=bool(e[args.k - 1] <= 1e-3))
+    return out
+
+
+def cpu_baseline(A_host, args):
+    """The FP64 reference as it stands, timed on the host on a bounded sample: the pass over the
+    leading row blocks until the time budget is spent, then the finalize on that sample's sketch;
+    both are scaled linearly in m to the whole workload."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 0) for d in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    m = A_host.shape[0]
+    Om = oracle.gaussian_omega_philox(args.n, args.l, 2002)
+    budget = args.cpu_seconds
+    t0 = time.perf_counter()
+    import numpy as _np
+    H = _np.zeros((args.n, args.l))
+    Gs, rows = [], 0
+    while rows < m and time.perf_counter() - t0 < budget * 0.7:
+        a = _np.asarray(A_host[rows:rows + args.block], dtype=_np.float64)
+        g = a @ Om
+        Gs.append(g)
+        H += a.T @ g
+        rows += a.shape[0]
+    t_pass = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    Q, B, r, _ = oracle.qb_from_sketch(_np.vstack(Gs), H, Om, args.b)
+    oracle.svd_from_qb(Q, B, args.k, want_u=False)
+    t_fin = time.perf_counter() - t1
+    scale = m / rows
+    t_est = (t_pass + t_fin) * scale
+    return dict(value=4.0 * m * args.n / t_est / 1e9, unit="GB/s", cores=int(cores), kind="oracle",
+                sample=f"FP64 reference pass over the first {rows} of {m} rows ({rows // args.block}"
+                       f" blocks, {t_pass:.1f} s) plus its finalize ({t_fin:.1f} s), scaled by "
+                       f"m/{rows} to the whole workload")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_1704_07669_amd as sk
+    sk.load_library()
+    torch.cuda.set_device(0)
+    print(f"[bench] generating A {args.m}x{args.n} FP32 on the GPU", file=sys.stderr, flush=True)
+    A, K = make_matrix(args, torch)
+    modes = [args.mode] + ([args.compare] if args.compare and args.compare != args.mode else [])
+    results = []
+    for mode in modes:
+        print(f"[bench] mode {mode}: {args.warmup} warmup + {args.steps} timed steps",
+              file=sys.stderr, flush=True)
+        results.append(bench_mode(mode, A, args, torch, sk))
+        print(f"[bench] mode {mode}: {results[-1]['ms_per_step']:.3f} ms/step", file=sys.stderr,
+              flush=True)
+    p50, p99 = block_latency(A, args, torch, sk, args.mode)
+    head = results[0]
+    acc, cpu = {}, None
+    if args.check == "full" or args.cpu_seconds > 0:
+        print("[bench] copying A to the host for the reference", file=sys.stderr, flush=True)
+        A_host = A.cpu().numpy()
+        del A
+        torch.cuda.empty_cache()
+        if args.check == "full":
+            print("[bench] FP64 reference accuracy check", file=sys.stderr, flush=True)
+            acc = accuracy(A_host, K, results, args)
+        if args.cpu_seconds > 0:
+            print("[bench] CPU baseline (reference on a bounded sample)", file=sys.stderr,
+                  flush=True)
+            cpu = cpu_baseline(A_host, args)
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head["mode"],
+        "data": "synthetic",
+        "config": {"workload": f"fp32-resident {args.m}x{args.n}, k={args.k}, l={args.l}, "
+                               f"b={args.b}, {args.block}-row blocks",
+                   "m": args.m, "n": args.n, "k": args.k, "l": args.l, "b": args.b,
+                   "block_rows": args.block, "global_batch": args.m, "parallelism": "none"},
+        "roofline": roofline(head, args.m, args.n, args.l, head["mode"]),
+        "cpu_baseline": cpu,
+        "per_step_ms": {"g = a Omega": head["gemm1_ms"] * head["nblocks"],
+                        "H += a^T g": head["gemm2_ms"] * head["nblocks"],
+                        "finalize": head["finalize_ms"]},
+        "pass_only_gbps": 4.0 * args.m * args.n / ((head["gemm1_ms"] + head["gemm2_ms"]) *
+                                                   head["nblocks"] * 1e-3) / 1e9,
+        "block_latency_ms": {"p50": p50, "p99": p99, "rows": args.block},
+        "accuracy": acc.get(head["mode"]),
+        "compare": [
+            {"dtype": r["mode"], "value": r["value"], "ms_per_step": r["ms_per_step"],
+             "roofline": roofline(r, args.m, args.n, args.l, r["mode"]),
+             "per_step_ms": {"g = a Omega": r["gemm1_ms"] * r["nblocks"],
+                             "H += a^T g": r["gemm2_ms"] * r["nblocks"],
+                             "finalize": r["finalize_ms"]},
+             "accuracy": acc.get(r["mode"])} for r in results[1:]],
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

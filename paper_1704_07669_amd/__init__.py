@@ -52,6 +52,9 @@ def load_library(path=None):
     if _lib is not None:
         return _lib
     path = path or LIB_PATH
+    # PyTorch ships its own HIP runtime with the same soname as /opt/rocm's; loading torch first
+    # makes this library bind to that one runtime instead of pulling in a second copy.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run python -m paper_1704_07669_amd.build)")

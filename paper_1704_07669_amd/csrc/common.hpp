@@ -26,8 +26,26 @@ template <> __device__ __forceinline__ int acc_row<double>(int g, int i) { retur
 __device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// Wait states between the last matrix-core instruction of a chain and the first VALU read of its
+// accumulators.  On gfx950 the FP64 16x16x4 instruction runs at half the rate of gfx942's, and the
+// compiler's hazard padding (18 wait states) is too short for it: without this drain the last
+// accumulator element can be read before it is written (observed on hardware for a single
+// dependent FP64 chain).  The scheduling barriers keep the padding between the two.
+__device__ __forceinline__ void mfma_drain() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 __device__ __forceinline__ f64x4 mma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// FP64 product followed by the drain, so no read of its accumulator (including the copies the
+// compiler places at loop edges) can come early.
+__device__ __forceinline__ f64x4 mma_f64_drained(double a, double b, f64x4 c) {
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  mfma_drain();
+  return c;
 }
 __device__ __forceinline__ f32x4 mma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -51,15 +69,43 @@ __device__ __forceinline__ float fp8_to_f32(uint32_t v) {
   return s ? -r : r;
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane sums without LDS round trips: DPP moves inside each 16-lane row (quad_perm [1,0,3,2]
+// and [2,3,0,1], then row_half_mirror and row_mirror, which pair each lane with one whose partial
+// covers the other half of its 8- and 16-lane group), then readlane of the four row totals.
+namespace dpp {
+constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+template <int CTRL> __device__ __forceinline__ float mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double mov(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ float lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane(double v, int l) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+}  // namespace dpp
+
+// Sum over each 16-lane row; every lane of the row gets its row's total.
+template <typename T> __device__ __forceinline__ T row16_sum(T v) {
+  v += dpp::mov<dpp::kXor1>(v);
+  v += dpp::mov<dpp::kXor2>(v);
+  v += dpp::mov<dpp::kHalfMirror>(v);
+  v += dpp::mov<dpp::kMirror>(v);
   return v;
 }
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Sum over the whole 64-lane wave (all lanes active); every lane gets the total.
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+  v = row16_sum(v);
+  return (dpp::lane(v, 0) + dpp::lane(v, 16)) + (dpp::lane(v, 32) + dpp::lane(v, 48));
 }
 
 template <typename T> __host__ __device__ constexpr T cdiv(T a, T b) { return (a + b - 1) / b; }

@@ -57,54 +57,138 @@ __device__ __forceinline__ void block_sum(double (&v)[CMAX], int cnt, double* re
 }
 
 // ------------------------------------------------------------------------------------------------
-// Reductions over rows: part[chunk][a][c] = sum_{r in chunk} X[a][r] Y[c][r]
-template <int QMAX>
-__global__ __launch_bounds__(TPB) void k_tn_partial(const double* __restrict__ X, int64_t ldx,
-                                                    const double* __restrict__ Y, int64_t ldy,
-                                                    int p, int q, int64_t rows, int RC,
-                                                    double* __restrict__ part,
-                                                    const Ctrl* __restrict__ ctrl, int iter) {
-  if (skip_iter(ctrl, iter)) return;
-  extern __shared__ double ys[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * RC;
-  const int cnt = (int)min<int64_t>(RC, rows - r0);
-  for (int idx = threadIdx.x; idx < q * RC; idx += TPB) {
-    const int c = idx / RC, r = idx - c * RC;
-    ys[idx] = (r < cnt) ? Y[c * ldy + r0 + r] : 0.0;
-  }
-  __syncthreads();
-  for (int a = wave; a < p; a += TPB / 64) {
-    double acc[QMAX];
+// Reductions over rows on the FP64 matrix cores: part[chunk][a][c] = sum_{r in chunk} X[a][r] Y[c][r].
+// The MFMA k index is the row: lane L supplies rows r0 + 4(L/16) .. +3 of column a = 16 mt + L%16
+// of X and of column c = 16 nt + L%16 of Y (32 contiguous bytes each), one 16x16x4 MFMA per row.
+// The waves of a workgroup take interleaved 16-row steps (next step's operands fetched first) and
+// are summed in wave order through LDS.
+template <int MT, int NQ>
+__device__ __forceinline__ void tn_fetch(const double* __restrict__ X, int64_t ldx,
+                                         const double* __restrict__ Y, int64_t ldy, int p, int q,
+                                         int64_t rr, int64_t r_end, int r16, bool full,
+                                         double (&xa)[MT][4], double (&yb)[NQ][4]) {
 #pragma unroll
-    for (int c = 0; c < QMAX; ++c) acc[c] = 0.0;
-    const double* xa = X + a * ldx + r0;
-    for (int r = lane; r < cnt; r += 64) {
-      const double x = xa[r];
+  for (int mt = 0; mt < MT; ++mt) {
+    const int a = mt * 16 + r16;
+    const double* px = X + (int64_t)(a < p ? a : 0) * ldx + rr;
+    if (full) {
+      const f64x4 v = *reinterpret_cast<const f64x4*>(px);
 #pragma unroll
-      for (int c = 0; c < QMAX; ++c)
-        if (c < q) acc[c] = fma(x, ys[c * RC + r], acc[c]);
+      for (int j = 0; j < 4; ++j) xa[mt][j] = (a < p) ? v[j] : 0.0;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xa[mt][j] = (a < p && rr + j < r_end) ? px[j] : 0.0;
     }
+  }
 #pragma unroll
-    for (int c = 0; c < QMAX; ++c) {
-      if (c < q) {
-        const double s = wave_sum(acc[c]);
-        if (lane == 0) part[((int64_t)blockIdx.x * p + a) * q + c] = s;
-      }
+  for (int nt = 0; nt < NQ; ++nt) {
+    const int c = nt * 16 + r16;
+    const double* py = Y + (int64_t)(c < q ? c : 0) * ldy + rr;
+    if (full) {
+      const f64x4 v = *reinterpret_cast<const f64x4*>(py);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yb[nt][j] = (c < q) ? v[j] : 0.0;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yb[nt][j] = (c < q && rr + j < r_end) ? py[j] : 0.0;
     }
   }
 }
 
-// out (p x q, row-major, leading dimension ldo) = sum over chunks in chunk order.
-__global__ void k_tn_final(const double* __restrict__ part, int nchunks, int p, int q,
-                           double* __restrict__ out, int ldo, const Ctrl* __restrict__ ctrl,
-                           int iter) {
+template <int MT, int NQ>
+__global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, int64_t ldx,
+                                                 const double* __restrict__ Y, int64_t ldy, int p,
+                                                 int q, int64_t rows, int RCH,
+                                                 double* __restrict__ part,
+                                                 const Ctrl* __restrict__ ctrl, int iter) {
   if (skip_iter(ctrl, iter)) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= p * q) return;
-  double s = 0;
-  for (int ch = 0; ch < nchunks; ++ch) s += part[(int64_t)ch * p * q + idx];
-  out[(idx / q) * ldo + idx % q] = s;
+  __shared__ double red[(TPB / 64 - 1) * MT * NQ * 4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
+  const int64_t r_begin = (int64_t)blockIdx.x * RCH;
+  const int64_t r_end = min<int64_t>(rows, r_begin + RCH);
+  const bool aligned = ((ldx | ldy) % 4) == 0;
+  f64x4 acc[MT][NQ];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NQ; ++nt) acc[mt][nt] = f64x4{0, 0, 0, 0};
+  double xa0[MT][4], yb0[NQ][4], xa1[MT][4], yb1[NQ][4];
+  constexpr int STEP = (TPB / 64) * 16;
+  int64_t r0 = r_begin + wave * 16;
+  if (r0 < r_end)
+    tn_fetch<MT, NQ>(X, ldx, Y, ldy, p, q, r0 + 4 * g, r_end, r16, aligned && r0 + 16 <= r_end,
+                     xa0, yb0);
+  for (; r0 < r_end; r0 += 2 * STEP) {
+    const int64_t r1 = r0 + STEP, r2 = r0 + 2 * STEP;
+    if (r1 < r_end)
+      tn_fetch<MT, NQ>(X, ldx, Y, ldy, p, q, r1 + 4 * g, r_end, r16, aligned && r1 + 16 <= r_end,
+                       xa1, yb1);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NQ; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[mt][nt] = mma_f64(xa0[mt][j], yb0[nt][j], acc[mt][nt]);
+    mfma_drain();
+    if (r2 < r_end)
+      tn_fetch<MT, NQ>(X, ldx, Y, ldy, p, q, r2 + 4 * g, r_end, r16, aligned && r2 + 16 <= r_end,
+                       xa0, yb0);
+    if (r1 < r_end) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NQ; ++nt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[mt][nt] = mma_f64(xa1[mt][j], yb1[nt][j], acc[mt][nt]);
+      mfma_drain();
+    }
+  }
+  mfma_drain();
+  if (wave > 0) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NQ; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          red[((((wave - 1) * MT + mt) * NQ + nt) * 4 + i) * 64 + lane] = acc[mt][nt][i];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NQ; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double s = acc[mt][nt][i];
+          for (int w = 1; w < TPB / 64; ++w) s += red[((((w - 1) * MT + mt) * NQ + nt) * 4 + i) * 64 + lane];
+          const int a = mt * 16 + acc_row<double>(g, i), c = nt * 16 + r16;
+          if (a < p && c < q) part[((int64_t)blockIdx.x * p + a) * q + c] = s;
+        }
+  }
+}
+
+// out (p x q, row-major, leading dimension ldo) = sum over chunks in chunk order; one workgroup per
+// row a: thread t adds chunks t, t + 256, ..., then the 256 partial sums are added in a fixed tree.
+__global__ __launch_bounds__(TPB) void k_tn_final(const double* __restrict__ part, int nchunks,
+                                                  int p, int q, double* __restrict__ out, int ldo,
+                                                  const Ctrl* __restrict__ ctrl, int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  __shared__ double sm[TPB];
+  const int a = blockIdx.x;
+  for (int c = 0; c < q; ++c) {
+    double s = 0;
+    for (int ch = threadIdx.x; ch < nchunks; ch += TPB) s += part[((int64_t)ch * p + a) * q + c];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = TPB / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[a * ldo + c] = sm[0];
+    __syncthreads();
+  }
 }
 
 // out[c][r] = base[c][r] + alpha * sum_a X[a][r] W[a][c]  (W row-major p x q, ldw); base may be
@@ -154,7 +238,8 @@ __global__ __launch_bounds__(TPB) void k_house_factor(double* __restrict__ X, in
                                                       const Ctrl* __restrict__ ctrl, int iter) {
   if (skip_iter(ctrl, iter)) return;
   __shared__ double red[(TPB / 64) * BMAX];
-  __shared__ double bc[BMAX + 4];
+  __shared__ double sc[BMAX];       // s_c = sum_{i>j} x_ij x_ic   (c >= j)
+  __shared__ double rowj[BMAX];     // x_jc, the current pivot row
   const int64_t r0 = (int64_t)blockIdx.x * CR;
   const int cnt = (int)min<int64_t>(CR, rows - r0);
   double x[RPT][BMAX];
@@ -164,78 +249,57 @@ __global__ __launch_bounds__(TPB) void k_house_factor(double* __restrict__ X, in
 #pragma unroll
     for (int c = 0; c < BMAX; ++c) x[t][c] = (c < b && i < cnt) ? X[c * ldx + r0 + i] : 0.0;
   }
+  // One block reduction per column: with s_c = sum_{i>j} x_ij x_ic, the reflector of column j
+  // (LAPACK dlarfg: beta = -sign(alpha) sqrt(alpha^2 + s_j), tau = (beta - alpha) / beta,
+  // v_i = x_ij / (alpha - beta)) gives w_c = v^T x_c = x_jc + s_c / (alpha - beta) directly.
   for (int j = 0; j < b; ++j) {
-    // alpha = x_jj, xnorm^2 = sum_{i>j} x_ij^2
-    double v1[1] = {0.0};
+    double part[BMAX];
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c) part[c] = 0.0;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int i = threadIdx.x + t * TPB;
+      double xij = 0.0;
 #pragma unroll
       for (int c = 0; c < BMAX; ++c)
-        if (c == j) {
-          if (i > j) v1[0] = fma(x[t][c], x[t][c], v1[0]);
-          if (i == j) bc[BMAX] = x[t][c];
-        }
-    }
-    block_sum<1>(v1, 1, red, bc + BMAX + 1);
-    if (threadIdx.x == 0) {
-      const double alpha = bc[BMAX], xn2 = bc[BMAX + 1];
-      double t_, beta, scal;
-      if (xn2 == 0.0) {
-        t_ = 0.0; beta = alpha; scal = 0.0;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        t_ = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
+        if (c == j) xij = x[t][c];
+      if (i > j) {
+#pragma unroll
+        for (int c = 0; c < BMAX; ++c)
+          if (c >= j && c < b) part[c] = fma(xij, x[t][c], part[c]);
       }
-      bc[BMAX + 2] = t_;
-      bc[BMAX + 3] = scal;
-      bc[BMAX + 1] = beta;
-      tau[(int64_t)blockIdx.x * b + j] = t_;
+      if (i == j) {
+#pragma unroll
+        for (int c = 0; c < BMAX; ++c) rowj[c] = x[t][c];
+      }
     }
-    __syncthreads();
-    const double tj = bc[BMAX + 2], scal = bc[BMAX + 3], beta = bc[BMAX + 1];
-    // v_i = x_ij * scal (i > j), v_j = 1; the column becomes (beta at row j, v below)
+    block_sum<BMAX>(part, b, red, sc);
+    const double alpha = rowj[j], xn2 = sc[j];
+    double tj, beta, scal;
+    if (xn2 == 0.0) {
+      tj = 0.0; beta = alpha; scal = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tj = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (threadIdx.x == 0) tau[(int64_t)blockIdx.x * b + j] = tj;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int i = threadIdx.x + t * TPB;
+      double vi = 0.0;
 #pragma unroll
       for (int c = 0; c < BMAX; ++c)
-        if (c == j) {
-          if (i > j) x[t][c] *= scal;
-          if (i == j) x[t][c] = beta;
+        if (c == j) vi = (i > j) ? x[t][c] * scal : (i == j ? 1.0 : 0.0);
+      if (i >= j) {
+#pragma unroll
+        for (int c = 0; c < BMAX; ++c) {
+          if (c > j && c < b) x[t][c] -= tj * vi * (rowj[c] + scal * sc[c]);
+          if (c == j) x[t][c] = (i > j) ? vi : beta;
         }
-    }
-    if (tj != 0.0 && j + 1 < b) {
-      // w_c = x_jc + sum_{i>j} v_i x_ic for c > j;  x_ic -= tau v_i w_c
-      double w[BMAX];
-#pragma unroll
-      for (int c = 0; c < BMAX; ++c) w[c] = 0.0;
-#pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const int i = threadIdx.x + t * TPB;
-        double vi = 0.0;
-#pragma unroll
-        for (int c = 0; c < BMAX; ++c)
-          if (c == j) vi = (i > j) ? x[t][c] : (i == j ? 1.0 : 0.0);
-#pragma unroll
-        for (int c = 0; c < BMAX; ++c)
-          if (c > j && c < b) w[c] = fma(vi, x[t][c], w[c]);
       }
-      block_sum<BMAX>(w, b, red, bc);
-#pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const int i = threadIdx.x + t * TPB;
-        double vi = 0.0;
-#pragma unroll
-        for (int c = 0; c < BMAX; ++c)
-          if (c == j) vi = (i > j) ? x[t][c] : (i == j ? 1.0 : 0.0);
-#pragma unroll
-        for (int c = 0; c < BMAX; ++c)
-          if (c > j && c < b) x[t][c] -= tj * vi * bc[c];
-      }
-      __syncthreads();
     }
+    __syncthreads();   // rowj / sc are rewritten by the next column
   }
   // reflectors back in place (rows < cnt), R (upper triangle, zero below) to the next level
 #pragma unroll
@@ -438,6 +502,7 @@ __global__ void k_rb_assemble(const double* __restrict__ C1, const double* __res
 // k_jacobi_apply.  Outputs: sig (descending), perm, W = M J (column perm[j] holds sigma_j u_j).
 constexpr int JMAX = 128;
 constexpr int JSWEEPS = 40;
+constexpr int kJacobiLds = 160 * 1024 - 256;   // dynamic LDS of the fused Jacobi kernel
 
 __device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
   if (k == 0) { p = N - 1; q = r; }
@@ -445,51 +510,90 @@ __device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
   if (p > q) { const int t = p; p = q; q = t; }
 }
 
+// With fuse_j, J (N x N, column-major) lives in LDS after M and each rotation is applied to it
+// at once; otherwise the rotations are logged for k_jacobi_apply.  Each 16-lane row holds the L
+// (<= 128) entries of its pair's columns as 8 registers per lane.
 __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, int ldr, int L,
                                                  double* __restrict__ W, int ldw,
                                                  double4* __restrict__ log, int* __restrict__ info,
-                                                 double* __restrict__ sig, int* __restrict__ perm) {
-  extern __shared__ double M[];           // N columns of L entries
+                                                 double* __restrict__ sig, int* __restrict__ perm,
+                                                 double* __restrict__ Jout, int fuse_j) {
+  extern __shared__ double M[];           // N columns of L entries, then J when fused
   __shared__ int rotated;
-  __shared__ double nrm[JMAX];
   const int N = (L + 1) & ~1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* Jl = M + N * L;
+  const double tol = (double)L * 2.220446049250313e-16;
+  constexpr int EPL = JMAX / 16;          // entries per lane of a column
+  const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15, ngrp = blockDim.x >> 4;
   for (int idx = threadIdx.x; idx < N * L; idx += blockDim.x) {
     const int col = idx / L, i = idx % L;
     M[idx] = (col < L) ? RB[col * ldr + i] : 0.0;     // M(:, col) = R_B(col, :)^T
   }
+  if (fuse_j)
+    for (int idx = threadIdx.x; idx < N * N; idx += blockDim.x)
+      Jl[idx] = (idx / N == idx % N) ? 1.0 : 0.0;
   __syncthreads();
   int sweep = 0;
   for (; sweep < JSWEEPS && N > 1; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
-      for (int k = wave; k < N / 2; k += nw) {
+      for (int k = grp; k < N / 2; k += ngrp) {
         int p, q;
         rr_pair(N, r, k, p, q);
         double* mp = M + p * L;
         double* mq = M + q * L;
-        double a = 0, bb = 0, g = 0;
-        for (int i = lane; i < L; i += 64) {
-          const double xp = mp[i], xq = mq[i];
-          a = fma(xp, xp, a); bb = fma(xq, xq, bb); g = fma(xp, xq, g);
+        double xp[EPL], xq[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const int i = gl + 16 * e;
+          xp[e] = (i < L) ? mp[i] : 0.0;
+          xq[e] = (i < L) ? mq[i] : 0.0;
         }
-        a = wave_sum(a); bb = wave_sum(bb); g = wave_sum(g);
+        double a = 0, bb = 0, g = 0;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          a = fma(xp[e], xp[e], a); bb = fma(xq[e], xq[e], bb); g = fma(xp[e], xq[e], g);
+        }
+        a = row16_sum(a); bb = row16_sum(bb); g = row16_sum(g);
         double c = 1.0, s = 0.0;
-        bool rot = (g != 0.0) && (fabs(g) > 1e-15 * sqrt(a * bb));
+        // rotate unless the pair is orthogonal to working precision (L eps relative)
+        const bool rot = (g != 0.0) && (fabs(g) > tol * sqrt(a * bb));
         if (rot) {
           const double zeta = (bb - a) / (2.0 * g);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + t * t);
           s = c * t;
-          for (int i = lane; i < L; i += 64) {
-            const double xp = mp[i], xq = mq[i];
-            mp[i] = c * xp - s * xq;
-            mq[i] = s * xp + c * xq;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            const int i = gl + 16 * e;
+            if (i < L) {
+              mp[i] = c * xp[e] - s * xq[e];
+              mq[i] = s * xp[e] + c * xq[e];
+            }
           }
-          if (lane == 0) rotated = 1;
+          if (fuse_j) {
+            double* jp = Jl + p * N;
+            double* jq = Jl + q * N;
+            double yp[EPL], yq[EPL];
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+              const int i = gl + 16 * e;
+              yp[e] = (i < N) ? jp[i] : 0.0;
+              yq[e] = (i < N) ? jq[i] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+              const int i = gl + 16 * e;
+              if (i < N) {
+                jp[i] = c * yp[e] - s * yq[e];
+                jq[i] = s * yp[e] + c * yq[e];
+              }
+            }
+          }
+          if (gl == 0) rotated = 1;
         }
-        if (lane == 0)
+        if (!fuse_j && gl == 0)
           log[((int64_t)sweep * (N - 1) + r) * (N / 2) + k] =
               make_double4((double)p, (double)q, c, rot ? s : 0.0);
       }
@@ -499,6 +603,8 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, 
     __syncthreads();
   }
   if (threadIdx.x == 0) info[0] = sweep;
+  // column norms into the (now free) log-independent scratch at the end of W's rows
+  double* nrm = Jout + (int64_t)L * ldw;   // L scratch doubles past J (see carve_small)
   for (int col = threadIdx.x; col < L; col += blockDim.x) {
     double s = 0;
     for (int i = 0; i < L; ++i) s = fma(M[col * L + i], M[col * L + i], s);
@@ -515,25 +621,32 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, 
   for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x) {
     const int col = idx / L, i = idx % L;
     W[i * ldw + col] = M[col * L + i];   // W row-major L x L
+    if (fuse_j) Jout[i * ldw + col] = Jl[col * N + i];
   }
 }
 
-// J = product of the logged rotations, applied round by round to the rows of the identity.
+// J = product of the logged rotations, applied round by round to the rows of the identity; the
+// next round's rotations are fetched into LDS while the current round is applied.
 __global__ __launch_bounds__(1024) void k_jacobi_apply(const double4* __restrict__ log,
                                                        const int* __restrict__ info, int L,
                                                        double* __restrict__ J, int ldj) {
   extern __shared__ double Js[];          // N x N row-major
+  __shared__ double4 lg[2][JMAX / 2];
   const int N = (L + 1) & ~1;
+  const int half = N / 2;
   for (int idx = threadIdx.x; idx < N * N; idx += blockDim.x)
     Js[idx] = (idx / N == idx % N) ? 1.0 : 0.0;
+  const int rounds = info[0] * (N - 1);
+  if (rounds > 0 && threadIdx.x < half) lg[0][threadIdx.x] = log[threadIdx.x];
   __syncthreads();
-  const int sweeps = info[0];
-  const int half = N / 2;
-  for (int sr = 0; sr < sweeps * (N - 1); ++sr) {
-    const double4* lg = log + (int64_t)sr * half;
+  for (int sr = 0; sr < rounds; ++sr) {
+    const int cur = sr & 1;
+    double4 nxt = make_double4(0, 0, 0, 0);
+    const bool pre = (sr + 1 < rounds) && (threadIdx.x < half);
+    if (pre) nxt = log[(int64_t)(sr + 1) * half + threadIdx.x];   // lands while this round runs
     for (int item = threadIdx.x; item < N * half; item += blockDim.x) {
       const int row = item / half, k = item % half;
-      const double4 e = lg[k];
+      const double4 e = lg[cur][k];
       if (e.w != 0.0) {
         const int p = (int)e.x, q = (int)e.y;
         const double xp = Js[row * N + p], xq = Js[row * N + q];
@@ -541,6 +654,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_apply(const double4* __restrict
         Js[row * N + q] = e.w * xp + e.z * xq;
       }
     }
+    if (pre) lg[cur ^ 1][threadIdx.x] = nxt;
     __syncthreads();
   }
   for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x)
@@ -647,32 +761,40 @@ struct Ctx {
   void chk() { if (err == hipSuccess) err = hipGetLastError(); }
 };
 
-int tn_rows_per_chunk(int q) {
-  int rc = 8192 / (q < 1 ? 1 : q);
-  rc = rc > 2048 ? 2048 : rc;
-  return rc < 64 ? 64 : (rc / 64) * 64;
+constexpr int kTnRows = 512;     // rows per workgroup of the row reductions
+
+template <int MT>
+void tn_launch(Ctx& cx, int nq, dim3 grid, const double* X, int64_t ldx, const double* Y,
+               int64_t ldy, int p, int q, int64_t rows, double* part, const Ctrl* ctrl, int iter) {
+  if (nq == 1)
+    hipLaunchKernelGGL((k_tn_mfma<MT, 1>), grid, dim3(TPB), 0, cx.s, X, ldx, Y, ldy, p, q, rows,
+                       kTnRows, part, ctrl, iter);
+  else
+    hipLaunchKernelGGL((k_tn_mfma<MT, 2>), grid, dim3(TPB), 0, cx.s, X, ldx, Y, ldy, p, q, rows,
+                       kTnRows, part, ctrl, iter);
 }
 
-// out (p x q row-major, ldo) = X[:, 0:p]^T Y[:, 0:q] over `rows` rows.
+// out (p x q row-major, ldo) = X[:, 0:p]^T Y[:, 0:q] over `rows` rows (p <= 128, q <= 32).
 void tn(Ctx& cx, const double* X, int64_t ldx, const double* Y, int64_t ldy, int p, int q,
         int64_t rows, double* part, double* out, int ldo, const Ctrl* ctrl, int iter) {
   if (!cx.ok() || p == 0 || q == 0) return;
-  const int RC = tn_rows_per_chunk(q);
-  const int nch = (int)cdiv<int64_t>(rows, RC);
-  const size_t shm = (size_t)RC * q * sizeof(double);
-  if (q <= 8)
-    hipLaunchKernelGGL(k_tn_partial<8>, dim3(nch), dim3(TPB), shm, cx.s, X, ldx, Y, ldy, p, q,
-                       rows, RC, part, ctrl, iter);
-  else if (q <= 16)
-    hipLaunchKernelGGL(k_tn_partial<16>, dim3(nch), dim3(TPB), shm, cx.s, X, ldx, Y, ldy, p, q,
-                       rows, RC, part, ctrl, iter);
-  else
-    hipLaunchKernelGGL(k_tn_partial<32>, dim3(nch), dim3(TPB), shm, cx.s, X, ldx, Y, ldy, p, q,
-                       rows, RC, part, ctrl, iter);
+  const int nch = (int)cdiv<int64_t>(rows, kTnRows);
+  const int mt = cdiv(p, 16), nq = cdiv(q, 16);
+  const dim3 grid(nch);
+  switch (mt) {
+    case 1: tn_launch<1>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+    case 2: tn_launch<2>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+    case 3: tn_launch<3>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+    case 4: tn_launch<4>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+    case 5: tn_launch<5>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+    case 6: tn_launch<6>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+    case 7: tn_launch<7>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+    default: tn_launch<8>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+  }
   cx.chk();
   if (!cx.ok()) return;
-  hipLaunchKernelGGL(k_tn_final, dim3(cdiv(p * q, TPB)), dim3(TPB), 0, cx.s, part, nch, p, q, out,
-                     ldo, ctrl, iter);
+  hipLaunchKernelGGL(k_tn_final, dim3(p), dim3(TPB), 0, cx.s, part, nch, p, q, out, ldo, ctrl,
+                     iter);
   cx.chk();
 }
 
@@ -761,7 +883,7 @@ Small carve_small(double* base, int l, int b) {
   sm.W = take(P); sm.T = take(P); sm.C = take(P); sm.Wn = take(P);
   sm.R1 = take(32 * 32); sm.R2 = take(32 * 32); sm.R = take(32 * 32);
   sm.RB = take((int64_t)l * l); sm.C1 = take(P); sm.C2 = take(P);
-  sm.Jm = take((int64_t)l * l); sm.Wm = take((int64_t)l * l); sm.sig = take(l);
+  sm.Jm = take((int64_t)l * l + l); sm.Wm = take((int64_t)l * l); sm.sig = take(l);
   sm.Jk = take((int64_t)l * l); sm.Wk = take((int64_t)l * l); sm.sgn = take(l);
   sm.perm = reinterpret_cast<int*>(take(l));
   sm.info = reinterpret_cast<int*>(take(4));
@@ -775,7 +897,7 @@ Small carve_small(double* base, int l, int b) {
 hipError_t finalize_prepare() {
   const int big = JMAX * JMAX * (int)sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_jacobi,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, big);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiLds);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_jacobi_apply,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
@@ -789,7 +911,7 @@ size_t finalize_small_elems(int l, int b) {
   (void)b;
   const int N = (l + 1) & ~1;
   const int64_t P = (int64_t)l * 32;
-  int64_t e = 6 * rup<int64_t>(P, 32) + 3 * 1024 + 5 * rup<int64_t>((int64_t)l * l, 32) +
+  int64_t e = 6 * rup<int64_t>(P, 32) + 3 * 1024 + 5 * rup<int64_t>((int64_t)l * l + l, 32) +
               3 * rup<int64_t>(l, 32) + 32 +
               rup<int64_t>((int64_t)JSWEEPS * (N - 1 > 0 ? N - 1 : 1) * (N / 2 > 0 ? N / 2 : 1) * 4, 32);
   return (size_t)e + 1024;
@@ -809,13 +931,7 @@ size_t tsqr_workspace_elems(int64_t rows, int b) {
 }
 
 size_t reduce_workspace_elems(int64_t rows, int p, int q) {
-  // worst case over q in [1, 32]: chunks * p * q
-  int64_t worst = 0;
-  for (int qq = 1; qq <= 32; ++qq) {
-    const int64_t nch = cdiv<int64_t>(rows, tn_rows_per_chunk(qq));
-    worst = nch * p * qq > worst ? nch * p * qq : worst;
-  }
-  return (size_t)worst + 64;
+  return (size_t)(cdiv<int64_t>(rows, kTnRows) * p * 32) + 64;
 }
 
 hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
@@ -907,14 +1023,19 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
     if (!cx.ok()) return cx.err;
     // ---------------- Jacobi SVD of R_B^T
     const int N = (L + 1) & ~1;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), (size_t)N * L * sizeof(double), stream,
-                       sm.RB, L, L, sm.Wm, L, sm.log, sm.info, sm.sig, sm.perm);
+    const size_t jshm = (size_t)N * (L + N) * sizeof(double);
+    const int fuse = jshm <= (size_t)kJacobiLds;
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024),
+                       fuse ? jshm : (size_t)N * L * sizeof(double), stream, sm.RB, L, L, sm.Wm, L,
+                       sm.log, sm.info, sm.sig, sm.perm, sm.Jm, fuse);
     cx.chk();
     if (!cx.ok()) return cx.err;
-    hipLaunchKernelGGL(k_jacobi_apply, dim3(1), dim3(1024), (size_t)N * N * sizeof(double), stream,
-                       sm.log, sm.info, L, sm.Jm, L);
-    cx.chk();
-    if (!cx.ok()) return cx.err;
+    if (!fuse) {
+      hipLaunchKernelGGL(k_jacobi_apply, dim3(1), dim3(1024), (size_t)N * N * sizeof(double),
+                         stream, sm.log, sm.info, L, sm.Jm, L);
+      cx.chk();
+      if (!cx.ok()) return cx.err;
+    }
     hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, stream, sm.Jm, sm.Wm, L, L, sm.perm,
                        sm.sig, kk, sm.Jk, sm.Wk);
     cx.chk();

@@ -33,6 +33,8 @@ struct PassArgs {
   int NT;              // LP / 16
   void* P1;            // split partials of g = a Omega: splits x LP x ldp
   int64_t ldp;
+  void* Gop;           // block-local operand copy of g for a^T g: LP x ldp (FP64 / FP32), or two
+                       // LP x ldp BF16 arrays (hi, lo) in the BF16-operand modes
   int splits;
   int64_t kchunk;      // columns per split (multiple of 512)
   void* G;             // G, LP x ldg column-major (FP64 in F64 mode, FP32 otherwise)

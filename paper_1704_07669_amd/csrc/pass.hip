@@ -11,6 +11,8 @@
 // every matrix-core operand a run of consecutive k values per lane:
 //   g = a Omega : k = column of a; A operand = a rows, B operand = Omega' columns (staged in LDS).
 //   a^T g       : k = row of a;    A operand = G columns (the transposed G), B operand = a columns.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -51,25 +53,6 @@ template <> struct Frag<M_FP8> { i32x8 v; };
 template <typename Src> __device__ __forceinline__ float src_to_f32(Src x) { return (float)x; }
 template <> __device__ __forceinline__ float src_to_f32<__bf16>(__bf16 x) { return from_bf16(x); }
 template <> __device__ __forceinline__ float src_to_f32<uint8_t>(uint8_t x) { return fp8_to_f32(x); }
-
-// V consecutive elements of one row of a, starting at column k (zeros outside the block).
-// Vector loads need a 16-byte aligned block base and row pitch (vec_ok, uniform per launch).
-template <typename Src, int V>
-__device__ __forceinline__ void load_run(const Src* __restrict__ A, int64_t lda, int row, int nrows,
-                                         int64_t k, int64_t n, bool vec_ok, Src (&buf)[V]) {
-  static_assert((V * sizeof(Src)) % 16 == 0, "runs are whole 16-byte vectors");
-  if (vec_ok && row < nrows && k + V <= n) {
-    const u32x4* p = reinterpret_cast<const u32x4*>(A + (int64_t)row * lda + k);
-    u32x4 tmp[V * sizeof(Src) / 16];
-#pragma unroll
-    for (int i = 0; i < (int)(V * sizeof(Src) / 16); ++i) tmp[i] = p[i];
-    __builtin_memcpy(buf, tmp, sizeof(buf));
-  } else {
-#pragma unroll
-    for (int e = 0; e < V; ++e)
-      buf[e] = (row < nrows && k + e < n) ? A[(int64_t)row * lda + k + e] : Src(0);
-  }
-}
 
 template <int MODE, typename Src, int V> struct MakeA;
 template <typename Src> struct MakeA<M_F64, Src, 4> {
@@ -138,7 +121,7 @@ __device__ __forceinline__ typename BFrag<MODE>::type lds_frag(const uint8_t* p)
 
 __device__ __forceinline__ f64x4 mma(const Frag<M_F64>& a, const Frag<M_F64>& b, f64x4 c) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) c = mma_f64(a.v[j], b.v[j], c);
+  for (int j = 0; j < 4; ++j) c = mma_f64_drained(a.v[j], b.v[j], c);
   return c;
 }
 __device__ __forceinline__ f32x4 mma(const Frag<M_F32>& a, const Frag<M_F32>& b, f32x4 c) {
@@ -160,7 +143,49 @@ __device__ __forceinline__ f32x4 mma(const Frag<M_FP8>& a, const Frag<M_FP8>& b,
 // ---------------------------------------------------------------- g = a Omega, split over k
 // Grid: x = row tiles of ROW_TILE rows, y = k splits of `kchunk` columns.  Each wave owns 16*RSUB
 // rows and all NT sketch-column tiles; the k-chunk of Omega' (NT*16 columns x KC) is staged in
-// LDS once per workgroup and shared by its waves.
+// LDS once per workgroup and shared by its waves.  Row loads are issued one super-step ahead of
+// the matrix-core work (two register buffers).  A wave whose rows and super-step lie inside the
+// block takes unconditional 16-byte loads; only tails take per-element masked loads.
+template <typename Src, int V, int RS>
+__device__ __forceinline__ void fetch_rows(const Src* __restrict__ A, int64_t lda, int row0,
+                                           int r16, int nrows, int64_t kbase, int g, int64_t n,
+                                           bool rows_full, Src (&buf)[RS][V]) {
+  const int64_t k = kbase + V * g;
+  if (rows_full && kbase + 4 * V <= n) {
+#pragma unroll
+    for (int rs = 0; rs < RS; ++rs) {
+      const u32x4* p = reinterpret_cast<const u32x4*>(A + (int64_t)(row0 + rs * 16 + r16) * lda + k);
+      u32x4 tmp[V * sizeof(Src) / 16];
+#pragma unroll
+      for (int i = 0; i < (int)(V * sizeof(Src) / 16); ++i) tmp[i] = p[i];
+      __builtin_memcpy(buf[rs], tmp, sizeof(buf[rs]));
+    }
+  } else {
+#pragma unroll
+    for (int rs = 0; rs < RS; ++rs) {
+      const int row = row0 + rs * 16 + r16;
+#pragma unroll
+      for (int e = 0; e < V; ++e)
+        buf[rs][e] = (row < nrows && k + e < n) ? A[(int64_t)row * lda + k + e] : Src(0);
+    }
+  }
+}
+
+template <typename Src, int MODE, int NT, int RS>
+__device__ __forceinline__ void gemm1_step(const Src (&buf)[RS][PT<MODE>::V1], const uint8_t* lds,
+                                           int row_bytes, int koff_bytes, int r16,
+                                           typename PT<MODE>::accv (&acc)[RS][NT]) {
+  Frag<MODE> a[RS];
+#pragma unroll
+  for (int rs = 0; rs < RS; ++rs) a[rs] = MakeA<MODE, Src, PT<MODE>::V1>::f(buf[rs]);
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const auto b = lds_frag<MODE>(lds + (nt * 16 + r16) * row_bytes + koff_bytes);
+#pragma unroll
+    for (int rs = 0; rs < RS; ++rs) acc[rs][nt] = mma(a[rs], b, acc[rs][nt]);
+  }
+}
+
 template <typename Src, int MODE, int NT>
 __global__ __launch_bounds__(WAVES * 64) void k_gemm1(
     const Src* __restrict__ A, int64_t lda, int nrows, int64_t n,
@@ -176,7 +201,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(
   __shared__ __attribute__((aligned(16))) uint8_t lds[NT * 16 * ROW_BYTES];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
-  const int row_base = blockIdx.x * ROW_TILE + wave * 16 * RSUB;
+  const int row0 = blockIdx.x * ROW_TILE + wave * 16 * RSUB;
+  const bool rows_full = vec_ok && (row0 + 16 * RSUB <= nrows);
   const int64_t k_begin = (int64_t)blockIdx.y * kchunk;
   const int64_t k_end = min(n, k_begin + kchunk);
 
@@ -186,6 +212,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[rs][nt] = accv{0, 0, 0, 0};
 
+  Src b0[RSUB][V], b1[RSUB][V];
   for (int64_t kc = k_begin; kc < k_end; kc += KC) {
     __syncthreads();
     for (int p = tid; p < NT * 16 * PIECES; p += WAVES * 64) {
@@ -194,27 +221,22 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(
           reinterpret_cast<const uint8_t*>(omc + (int64_t)c * NP + kc) + pc * 16);
       *reinterpret_cast<u32x4*>(lds + c * ROW_BYTES + pc * 16) = v;
     }
+    fetch_rows<Src, V, RSUB>(A, lda, row0, r16, nrows, kc, g, n, rows_full, b0);
     __syncthreads();
     const int kspan = (int)min<int64_t>(KC, k_end - kc);
-    for (int ks = 0; ks < kspan; ks += KSS) {
-      const int64_t k = kc + ks + V * g;
-      Frag<MODE> a[RSUB];
-#pragma unroll
-      for (int rs = 0; rs < RSUB; ++rs) {
-        Src buf[V];
-        load_run<Src, V>(A, lda, row_base + rs * 16 + r16, nrows, k, n, vec_ok != 0, buf);
-        a[rs] = MakeA<MODE, Src, V>::f(buf);
-      }
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const auto b = lds_frag<MODE>(lds + (nt * 16 + r16) * ROW_BYTES +
-                                      (ks + V * g) * (int)sizeof(op_t));
-#pragma unroll
-        for (int rs = 0; rs < RSUB; ++rs) acc[rs][nt] = mma(a[rs], b, acc[rs][nt]);
-      }
+    for (int ks = 0; ks < kspan; ks += 2 * KSS) {
+      const bool has1 = ks + KSS < kspan;
+      if (has1) fetch_rows<Src, V, RSUB>(A, lda, row0, r16, nrows, kc + ks + KSS, g, n, rows_full, b1);
+      gemm1_step<Src, MODE, NT, RSUB>(b0, lds, ROW_BYTES, (ks + V * g) * (int)sizeof(op_t), r16, acc);
+      if (ks + 2 * KSS < kspan)
+        fetch_rows<Src, V, RSUB>(A, lda, row0, r16, nrows, kc + ks + 2 * KSS, g, n, rows_full, b0);
+      if (has1)
+        gemm1_step<Src, MODE, NT, RSUB>(b1, lds, ROW_BYTES, (ks + KSS + V * g) * (int)sizeof(op_t),
+                                        r16, acc);
     }
   }
 
+  mfma_drain();
   const int64_t pbase = (int64_t)blockIdx.y * LP;
 #pragma unroll
   for (int rs = 0; rs < RSUB; ++rs)
@@ -222,15 +244,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = row_base + rs * 16 + acc_row<acc_t>(g, i);
+        const int row = row0 + rs * 16 + acc_row<acc_t>(g, i);
         if (row < nrows) P[(pbase + nt * 16 + r16) * ldp + row] = acc[rs][nt][i];
       }
 }
 
-// G rows of this block = sum of the k-split partials in split order, times the FP8 scale.
-template <typename acc_t>
+// G rows of this block = sum of the k-split partials in split order, times the FP8 scale.  Also
+// writes the block-local operand copy read by a^T g: FP64 / FP32 as is, or, in the BF16-operand
+// modes, the pair hi = bf16(g), lo = bf16(g - hi) (two LP x ldp BF16 arrays).
+template <typename acc_t, bool HILO>
 __global__ void k_reduce1(const acc_t* __restrict__ P, int64_t ldp, int splits, int LP, int nrows,
-                          acc_t* __restrict__ G, int64_t ldg, int64_t g_row0,
+                          acc_t* __restrict__ G, int64_t ldg, int64_t g_row0, void* __restrict__ gop,
                           const int* __restrict__ fp8_exp, Ctrl* __restrict__ ctrl) {
   const acc_t scale = fp8_exp ? (acc_t)ldexp(1.0, -(*fp8_exp) - 5) : (acc_t)1;
   const int64_t total = (int64_t)LP * nrows;
@@ -244,14 +268,20 @@ __global__ void k_reduce1(const acc_t* __restrict__ P, int64_t ldp, int splits, 
     s *= scale;
     bad |= !isfinite(s);
     G[(int64_t)c * ldg + g_row0 + r] = s;
+    if constexpr (HILO) {
+      __bf16* hi = reinterpret_cast<__bf16*>(gop);
+      __bf16* lo = hi + (int64_t)LP * ldp;
+      const __bf16 h = to_bf16((float)s);
+      hi[(int64_t)c * ldp + r] = h;
+      lo[(int64_t)c * ldp + r] = to_bf16((float)s - from_bf16(h));
+    } else {
+      reinterpret_cast<acc_t*>(gop)[(int64_t)c * ldp + r] = s;
+    }
   }
   if (bad) ctrl->nonfinite = 1;
 }
 
 // ---------------------------------------------------------------- H += a^T g
-template <int MODE> struct GT { using type = float; };
-template <> struct GT<M_F64> { using type = double; };
-
 template <int MODE> struct GFrag;
 template <> struct GFrag<M_F64> { double v[4]; };
 template <> struct GFrag<M_F32> { float v[4]; };
@@ -267,7 +297,7 @@ template <> struct AFrag2<M_BF16X2> { bf16x8 hi, lo; };
 
 __device__ __forceinline__ f64x4 mma2(const GFrag<M_F64>& gq, const AFrag2<M_F64>& a, f64x4 c) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) c = mma_f64(gq.v[e], a.v[e], c);
+  for (int e = 0; e < 4; ++e) c = mma_f64_drained(gq.v[e], a.v[e], c);
   return c;
 }
 __device__ __forceinline__ f32x4 mma2(const GFrag<M_F32>& gq, const AFrag2<M_F32>& a, f32x4 c) {
@@ -288,20 +318,6 @@ __device__ __forceinline__ f32x4 mma2(const GFrag<M_BF16>& gq, const AFrag2<M_BF
   c = mma_bf16(gq.hi, a.hi, c);
   c = mma_bf16(gq.lo, a.hi, c);
   return mma_bf16(gq.hi, a.lo, c);
-}
-
-// VC consecutive columns of one row of a (zeros outside the block).
-template <typename Src, int VC>
-__device__ __forceinline__ void load_cols(const Src* __restrict__ A, int64_t lda, int row,
-                                          int nrows, int64_t col, int64_t n, bool vec_ok,
-                                          Src (&buf)[VC]) {
-  if (vec_ok && row < nrows && col + VC <= n) {
-    __builtin_memcpy(buf, A + (int64_t)row * lda + col, sizeof(buf));
-  } else {
-#pragma unroll
-    for (int j = 0; j < VC; ++j)
-      buf[j] = (row < nrows && col + j < n) ? A[(int64_t)row * lda + col + j] : Src(0);
-  }
 }
 
 template <int MODE, typename Src, int V2, int VC>
@@ -325,40 +341,99 @@ __device__ __forceinline__ AFrag2<MODE> make_a2(const Src (&a)[V2][VC], int j) {
   return r;
 }
 
-template <int MODE, int V2>
-__device__ __forceinline__ GFrag<MODE> load_gfrag(const typename GT<MODE>::type* __restrict__ gp,
-                                                  int r0, int nrows, bool aligned) {
-  using gt = typename GT<MODE>::type;
-  gt v[V2];
-  if (aligned && r0 + V2 <= nrows) {
-    __builtin_memcpy(v, gp, sizeof(v));
-  } else {
-#pragma unroll
-    for (int e = 0; e < V2; ++e) v[e] = (r0 + e < nrows) ? gp[e] : gt(0);
-  }
-  GFrag<MODE> f;
-  if constexpr (MODE == M_F64 || MODE == M_F32) {
-#pragma unroll
-    for (int e = 0; e < V2; ++e) f.v[e] = v[e];
-  } else {
+// V2 rows x VC columns of a (rows kr + V2*g + e, columns col .. col+VC-1).
+template <typename Src, int V2, int VC>
+__device__ __forceinline__ void fetch_cols(const Src* __restrict__ A, int64_t lda, int kr, int g,
+                                           int nrows, int64_t col, int64_t n, bool cols_full,
+                                           Src (&a)[V2][VC]) {
+  const int r0 = kr + V2 * g;
+  if (cols_full && kr + 4 * V2 <= nrows) {
 #pragma unroll
     for (int e = 0; e < V2; ++e) {
-      const __bf16 h = to_bf16(v[e]);
-      f.hi[e] = h;
-      f.lo[e] = to_bf16(v[e] - from_bf16(h));
+      const Src* p = A + (int64_t)(r0 + e) * lda + col;
+      if constexpr (VC * sizeof(Src) == 16) {
+        const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+        __builtin_memcpy(a[e], &v, 16);
+      } else if constexpr (VC * sizeof(Src) == 8) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        __builtin_memcpy(a[e], &v, 8);
+      } else {
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+        __builtin_memcpy(a[e], &v, 4);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < V2; ++e)
+#pragma unroll
+      for (int j = 0; j < VC; ++j)
+        a[e][j] = (r0 + e < nrows && col + j < n) ? A[(int64_t)(r0 + e) * lda + col + j] : Src(0);
+  }
+}
+
+// G fragment of column m: V2 consecutive block rows r0 .. r0+V2-1 of the block-local operand copy
+// (rows past the block are zero).
+template <int MODE, int V2>
+__device__ __forceinline__ GFrag<MODE> fetch_g(const void* __restrict__ gop, int64_t ldp, int LP,
+                                               int m, int r0, int nrows) {
+  GFrag<MODE> f;
+  if constexpr (MODE == M_F64 || MODE == M_F32) {
+    using gt = typename std::conditional<MODE == M_F64, double, float>::type;
+    const gt* p = reinterpret_cast<const gt*>(gop) + (int64_t)m * ldp + r0;
+    if (r0 + V2 <= nrows) {
+      __builtin_memcpy(f.v, p, sizeof(f.v));
+    } else {
+#pragma unroll
+      for (int e = 0; e < V2; ++e) f.v[e] = (r0 + e < nrows) ? p[e] : gt(0);
+    }
+  } else {
+    const __bf16* hi = reinterpret_cast<const __bf16*>(gop) + (int64_t)m * ldp + r0;
+    const __bf16* lo = hi + (int64_t)LP * ldp;
+    if (r0 + V2 <= nrows) {
+      const u32x4 vh = *reinterpret_cast<const u32x4*>(hi);
+      const u32x4 vl = *reinterpret_cast<const u32x4*>(lo);
+      __builtin_memcpy(&f.hi, &vh, 16);
+      __builtin_memcpy(&f.lo, &vl, 16);
+    } else {
+#pragma unroll
+      for (int e = 0; e < V2; ++e) {
+        f.hi[e] = (r0 + e < nrows) ? hi[e] : (__bf16)0.0f;
+        f.lo[e] = (r0 + e < nrows) ? lo[e] : (__bf16)0.0f;
+      }
     }
   }
   return f;
 }
 
+template <int MODE, int NT>
+__device__ __forceinline__ void fetch_gall(const void* __restrict__ gop, int64_t ldp, int LP,
+                                           int r16, int r0, int nrows, GFrag<MODE> (&gq)[NT]) {
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) gq[mt] = fetch_g<MODE, PT<MODE>::V2>(gop, ldp, LP, mt * 16 + r16, r0, nrows);
+}
+
+template <typename Src, int MODE, int NT>
+__device__ __forceinline__ void gemm2_step(const Src (&a)[PT<MODE>::V2][PT<MODE>::VC],
+                                           const GFrag<MODE> (&gq)[NT],
+                                           typename PT<MODE>::accv (&acc)[NT][PT<MODE>::VC]) {
+  constexpr int V2 = PT<MODE>::V2, VC = PT<MODE>::VC;
+  AFrag2<MODE> af[VC];
+#pragma unroll
+  for (int j = 0; j < VC; ++j) af[j] = make_a2<MODE, Src, V2, VC>(a, j);
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+    for (int j = 0; j < VC; ++j) acc[mt][j] = mma2(gq[mt], af[j], acc[mt][j]);
+}
+
 // Grid: x = strips of 16*VC columns of a.  The WAVES waves of a workgroup take interleaved
-// super-steps of 4*V2 rows; their partial sums are added in wave order through LDS and the FP64
-// sum is added into the workgroup's own rows of H.
+// super-steps of 4*V2 rows (loads issued one super-step ahead); their partial sums are added in
+// wave order through LDS and the FP64 sum is added into the workgroup's own rows of H.
 template <typename Src, int MODE, int NT>
 __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
-    const Src* __restrict__ A, int64_t lda, int nrows, int64_t n,
-    const typename GT<MODE>::type* __restrict__ G, int64_t ldg, int64_t g_row0,
-    double* __restrict__ H, int64_t ldh, const int* __restrict__ fp8_exp, int vec_ok) {
+    const Src* __restrict__ A, int64_t lda, int nrows, int64_t n, const void* __restrict__ gop,
+    int64_t ldp, int LP, double* __restrict__ H, int64_t ldh, const int* __restrict__ fp8_exp,
+    int vec_ok) {
   using T = PT<MODE>;
   using acc_t = typename T::acc_t;
   using accv = typename T::accv;
@@ -366,8 +441,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
   __shared__ acc_t red[(WAVES - 1) * VC * 4 * 64];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
-  const int64_t col = (int64_t)blockIdx.x * 16 * VC + VC * r16;
-  const bool galigned = ((g_row0 % V2) == 0) && ((ldg % V2) == 0);
+  const int64_t c0 = (int64_t)blockIdx.x * 16 * VC;
+  const int64_t col = c0 + VC * r16;
+  const bool cols_full = vec_ok && (c0 + 16 * VC <= n);
 
   accv acc[NT][VC];
 #pragma unroll
@@ -375,24 +451,30 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
 #pragma unroll
     for (int j = 0; j < VC; ++j) acc[mt][j] = accv{0, 0, 0, 0};
 
-  for (int kr = wave * KR; kr < nrows; kr += WAVES * KR) {
-    Src a[V2][VC];
-#pragma unroll
-    for (int e = 0; e < V2; ++e)
-      load_cols<Src, VC>(A, lda, kr + V2 * g + e, nrows, col, n, vec_ok != 0, a[e]);
-    AFrag2<MODE> af[VC];
-#pragma unroll
-    for (int j = 0; j < VC; ++j) af[j] = make_a2<MODE, Src, V2, VC>(a, j);
-    const int r0 = kr + V2 * g;
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      const auto gq = load_gfrag<MODE, V2>(G + (int64_t)(mt * 16 + r16) * ldg + g_row0 + r0, r0,
-                                           nrows, galigned);
-#pragma unroll
-      for (int j = 0; j < VC; ++j) acc[mt][j] = mma2(gq, af[j], acc[mt][j]);
+  // A and G of the next super-step are fetched before the matrix-core work of the current one
+  Src a0[V2][VC], a1[V2][VC];
+  GFrag<MODE> g0[NT], g1[NT];
+  constexpr int STRIDE = WAVES * KR;
+  int kr = wave * KR;
+  if (kr < nrows) {
+    fetch_cols<Src, V2, VC>(A, lda, kr, g, nrows, col, n, cols_full, a0);
+    fetch_gall<MODE, NT>(gop, ldp, LP, r16, kr + V2 * g, nrows, g0);
+  }
+  for (; kr < nrows; kr += 2 * STRIDE) {
+    const bool has1 = kr + STRIDE < nrows;
+    if (has1) {
+      fetch_cols<Src, V2, VC>(A, lda, kr + STRIDE, g, nrows, col, n, cols_full, a1);
+      fetch_gall<MODE, NT>(gop, ldp, LP, r16, kr + STRIDE + V2 * g, nrows, g1);
     }
+    gemm2_step<Src, MODE, NT>(a0, g0, acc);
+    if (kr + 2 * STRIDE < nrows) {
+      fetch_cols<Src, V2, VC>(A, lda, kr + 2 * STRIDE, g, nrows, col, n, cols_full, a0);
+      fetch_gall<MODE, NT>(gop, ldp, LP, r16, kr + 2 * STRIDE + V2 * g, nrows, g0);
+    }
+    if (has1) gemm2_step<Src, MODE, NT>(a1, g1, acc);
   }
 
+  mfma_drain();
   const double scale = fp8_exp ? ldexp(1.0, -(*fp8_exp)) : 1.0;
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
@@ -492,13 +574,10 @@ template <typename Src, int MODE, int NT>
 hipError_t gemm2_t(const PassArgs& a, hipStream_t s) {
   const dim3 grid(cdiv<int64_t>(a.n, 16 * PT<MODE>::VC));
   hipLaunchKernelGGL((k_gemm2<Src, MODE, NT>), grid, dim3(WAVES * 64), 0, s, (const Src*)a.A,
-                     a.lda, a.nrows, a.n, (const typename GT<MODE>::type*)a.G, a.ldg, a.g_row0,
-                     a.H, a.ldh, a.fp8_exp, vec_ok(a, sizeof(Src)));
+                     a.lda, a.nrows, a.n, (const void*)a.Gop, a.ldp, a.LP, a.H, a.ldh, a.fp8_exp,
+                     vec_ok(a, sizeof(Src)));
   return hipGetLastError();
 }
-
-template <template <typename, int, int> class F, typename Src, int MODE>
-struct NTDispatch;
 
 #define SK_NT_SWITCH(FN, SRC, MODE)                              \
   switch (a.NT) {                                                \
@@ -548,11 +627,17 @@ hipError_t launch_gemm2(const PassArgs& a, hipStream_t s) { SK_MODE_SWITCH(gemm2
 hipError_t launch_reduce1(const PassArgs& a, hipStream_t s) {
   const dim3 grid(grid_for((int64_t)a.LP * a.nrows)), block(256);
   if (a.mode == M_F64) {
-    hipLaunchKernelGGL(k_reduce1<double>, grid, block, 0, s, (const double*)a.P1, a.ldp, a.splits,
-                       a.LP, a.nrows, (double*)a.G, a.ldg, a.g_row0, a.fp8_exp, a.ctrl);
+    hipLaunchKernelGGL((k_reduce1<double, false>), grid, block, 0, s, (const double*)a.P1, a.ldp,
+                       a.splits, a.LP, a.nrows, (double*)a.G, a.ldg, a.g_row0, a.Gop, a.fp8_exp,
+                       a.ctrl);
+  } else if (a.mode == M_F32) {
+    hipLaunchKernelGGL((k_reduce1<float, false>), grid, block, 0, s, (const float*)a.P1, a.ldp,
+                       a.splits, a.LP, a.nrows, (float*)a.G, a.ldg, a.g_row0, a.Gop, a.fp8_exp,
+                       a.ctrl);
   } else {
-    hipLaunchKernelGGL(k_reduce1<float>, grid, block, 0, s, (const float*)a.P1, a.ldp, a.splits,
-                       a.LP, a.nrows, (float*)a.G, a.ldg, a.g_row0, a.fp8_exp, a.ctrl);
+    hipLaunchKernelGGL((k_reduce1<float, true>), grid, block, 0, s, (const float*)a.P1, a.ldp,
+                       a.splits, a.LP, a.nrows, (float*)a.G, a.ldg, a.g_row0, a.Gop, a.fp8_exp,
+                       a.ctrl);
   }
   return hipGetLastError();
 }

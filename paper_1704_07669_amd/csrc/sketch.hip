@@ -70,7 +70,7 @@ int op_size(int mode) {
 struct Layout {
   int LP, NT, t, splits_max;
   int64_t NP, MCAP, RBP, LDST, NQ;
-  int64_t off_ctrl, off_fp8, off_om64, off_omc, off_G, off_H, off_P1, off_stage, off_fp8q,
+  int64_t off_ctrl, off_fp8, off_om64, off_omc, off_G, off_H, off_P1, off_Gop, off_stage, off_fp8q,
       off_Q, off_Bt, off_Qb, off_Wn, off_tsqr, off_red, off_small, total;
   int64_t stage_slot_bytes;
   int64_t tsqr_elems, red_elems;
@@ -123,6 +123,7 @@ Layout plan(const sketch_config* c) {
   L.off_G = take((int64_t)L.LP * L.MCAP * gsz);
   L.off_H = take((int64_t)L.LP * L.NP * 8);
   L.off_P1 = take((int64_t)L.splits_max * L.LP * L.RBP * gsz);
+  L.off_Gop = take((int64_t)L.LP * L.RBP * gsz);
   L.off_stage = take(L.stage_slot_bytes * c->host_slots);
   L.off_fp8q = take(c->compute == SKETCH_FP8_E4M3 ? c->max_block_rows * L.NQ : 0);
   L.off_Q = take((int64_t)L.LP * L.MCAP * 8);
@@ -366,6 +367,7 @@ sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtyp
   a.NT = L.NT;
   a.P1 = h->ws + L.off_P1;
   a.ldp = L.RBP;
+  a.Gop = h->ws + L.off_Gop;
   a.G = h->ws + L.off_G;
   a.ldg = L.MCAP;
   a.g_row0 = h->rows;
@@ -386,7 +388,7 @@ sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtyp
   }
   // k splits of g = a Omega: enough workgroups to fill the chip
   const int64_t row_tiles = cdiv<int64_t>(nrows, gemm1_row_tile(c.compute));
-  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(L.splits_max, cdiv<int64_t>(1024, row_tiles)));
+  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(L.splits_max, cdiv<int64_t>(512, row_tiles)));
   a.kchunk = rup<int64_t>(cdiv<int64_t>(c.n, splits), kNpAlign);
   a.splits = (int)cdiv<int64_t>(c.n, a.kchunk);
 

@@ -97,9 +97,12 @@ def test_plain_fp64_workload(gpu_lib):
 
 
 @pytest.mark.parametrize("l,b,k", [(100, 10, 50), (100, 20, 50), (32, 32, 32), (30, 5, 30),
-                                   (16, 1, 8)])
+                                   (16, 1, 8), (16, 2, 8), (32, 8, 16), (30, 15, 30), (60, 5, 30),
+                                   (24, 6, 24), (128, 16, 64)])
 def test_widths_and_block_sizes(gpu_lib, l, b, k):
-    """Sketch widths across 1..7 padded column tiles, b from 1 to 32, k = l."""
+    """Sketch widths across 1..8 padded column tiles, b from 1 to 32, k = l.  The b values make
+    the earlier-basis width p = i*b hit 16 exactly (a single 16-row tile of the FP64 row
+    reductions, whose accumulator read-back needs the explicit drain)."""
     m, n = 2100, 1500
     sig = synth.noisy_spectrum(synth.inv_floor_spectrum(n, knee=200, floor=1e-4), 1e-4, l)
     A, _, s, _ = synth.small_matrix(m, n, sig, l + b)
