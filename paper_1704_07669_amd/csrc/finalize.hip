@@ -56,6 +56,24 @@ __device__ __forceinline__ void block_sum(double (&v)[CMAX], int cnt, double* re
   __syncthreads();
 }
 
+// Sum over the block of v[c] for c in [C0, C1) (compile-time range); result in out[c].
+template <int C0, int C1, int CMAX>
+__device__ __forceinline__ void block_sum_range(const double (&v)[CMAX], double* red, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = C0; c < C1; ++c) {
+    const double s = wave_sum(v[c]);
+    if (lane == 0) red[wave * CMAX + c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x >= C0 && threadIdx.x < C1) {
+    double s = 0;
+    for (int w = 0; w < TPB / 64; ++w) s += red[w * CMAX + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------------------------------------
 // Reductions over rows on the FP64 matrix cores: part[chunk][a][c] = sum_{r in chunk} X[a][r] Y[c][r].
 // The MFMA k index is the row: lane L supplies rows r0 + 4(L/16) .. +3 of column a = 16 mt + L%16
@@ -192,7 +210,8 @@ __global__ __launch_bounds__(TPB) void k_tn_final(const double* __restrict__ par
 }
 
 // out[c][r] = base[c][r] + alpha * sum_a X[a][r] W[a][c]  (W row-major p x q, ldw); base may be
-// null (taken as 0) and may alias out.
+// null (taken as 0) and may alias out.  A workgroup owns 64 rows; its four waves take interleaved
+// ranges of a, and their partial sums are added in wave order through LDS.
 template <typename BT, int QMAX>
 __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int64_t ldo,
                                                    const BT* base, int64_t ldb,
@@ -201,25 +220,49 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
                                                    int q, int64_t rows, double alpha,
                                                    const Ctrl* __restrict__ ctrl, int iter) {
   if (skip_iter(ctrl, iter)) return;
-  extern __shared__ double ws[];
+  extern __shared__ double ws[];              // p x q, then 3 x QMAX x 64 partials
+  double* part = ws + ((p * q + 1) & ~1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int idx = threadIdx.x; idx < p * q; idx += TPB) ws[idx] = W[(idx / q) * ldw + idx % q];
   __syncthreads();
-  for (int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x; r < rows;
-       r += (int64_t)gridDim.x * TPB) {
-    double acc[QMAX];
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = r < rows;
+  double acc[QMAX];
 #pragma unroll
-    for (int c = 0; c < QMAX; ++c) acc[c] = 0.0;
-    for (int a = 0; a < p; ++a) {
-      const double x = X[a * ldx + r];
+  for (int c = 0; c < QMAX; ++c) acc[c] = 0.0;
+  if (live) {
+    int a = wave;
+    for (; a + 12 < p; a += 16) {            // four columns per wave per step, loads first
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = X[(int64_t)(a + 4 * u) * ldx + r];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < QMAX; ++c)
+          if (c < q) acc[c] = fma(x[u], ws[(a + 4 * u) * q + c], acc[c]);
+    }
+    for (; a < p; a += 4) {
+      const double x = X[(int64_t)a * ldx + r];
 #pragma unroll
       for (int c = 0; c < QMAX; ++c)
         if (c < q) acc[c] = fma(x, ws[a * q + c], acc[c]);
     }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int c = 0; c < QMAX; ++c)
+      if (c < q) part[((wave - 1) * QMAX + c) * 64 + lane] = acc[c];
+  }
+  __syncthreads();
+  if (wave == 0 && live) {
 #pragma unroll
     for (int c = 0; c < QMAX; ++c) {
       if (c < q) {
+        double sum = acc[c];
+        for (int w = 1; w < TPB / 64; ++w) sum += part[((w - 1) * QMAX + c) * 64 + lane];
         const double bv = base ? (double)base[c * ldb + r] : 0.0;
-        out[c * ldo + r] = bv + alpha * acc[c];
+        out[c * ldo + r] = bv + alpha * sum;
       }
     }
   }
@@ -230,83 +273,100 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
 // Householder reflections (the LAPACK dlarfg convention) with RPT rows per thread held in
 // registers; its b x b R goes to the next level's stacked array.  The Q factor is then formed from
 // the root down by applying each chunk's reflectors to its b x b block of the level above.
-template <int BMAX, int RPT>
+// One column step of the Householder factorisation (J compile-time): with s_c = sum_{i>J} x_iJ x_ic,
+// the reflector of column J (LAPACK dlarfg: beta = -sign(alpha) sqrt(alpha^2 + s_J),
+// tau = (beta - alpha) / beta, v_i = x_iJ / (alpha - beta), v_J = 1) gives
+// w_c = v^T x_c = x_Jc + s_c / (alpha - beta) from a single block reduction.
+template <int J, int B, int RPT>
+__device__ __forceinline__ void house_col(double (&x)[RPT][B], int b, double* red, double* sc,
+                                          double* rowj, double* tau_out) {
+  double part[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) part[c] = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int i = threadIdx.x + t * TPB;
+    if (i > J) {
+#pragma unroll
+      for (int c = J; c < B; ++c) part[c] = fma(x[t][J], x[t][c], part[c]);
+    }
+  }
+  if (threadIdx.x == J) {
+#pragma unroll
+    for (int c = J; c < B; ++c) rowj[c] = x[0][c];
+  }
+  block_sum_range<J, B, B>(part, red, sc);
+  const double alpha = rowj[J], xn2 = sc[J];
+  double tj, beta, scal;
+  if (xn2 == 0.0) {
+    tj = 0.0; beta = alpha; scal = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    tj = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+  if (threadIdx.x == 0 && J < b) tau_out[J] = tj;
+  double w[B];
+#pragma unroll
+  for (int c = J + 1; c < B; ++c) w[c] = tj * (rowj[c] + scal * sc[c]);
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int i = threadIdx.x + t * TPB;
+    if (i > J) {
+      const double vi = x[t][J] * scal;
+#pragma unroll
+      for (int c = J + 1; c < B; ++c) x[t][c] = fma(-vi, w[c], x[t][c]);
+      x[t][J] = vi;
+    } else if (i == J) {
+#pragma unroll
+      for (int c = J + 1; c < B; ++c) x[t][c] -= w[c];
+      x[t][J] = beta;
+    }
+  }
+  __syncthreads();   // rowj / sc are rewritten by the next column
+}
+
+template <int J, int B, int RPT>
+struct HouseCols {
+  static __device__ __forceinline__ void run(double (&x)[RPT][B], int b, double* red, double* sc,
+                                             double* rowj, double* tau_out) {
+    house_col<J, B, RPT>(x, b, red, sc, rowj, tau_out);
+    HouseCols<J + 1, B, RPT>::run(x, b, red, sc, rowj, tau_out);
+  }
+};
+template <int B, int RPT>
+struct HouseCols<B, B, RPT> {
+  static __device__ __forceinline__ void run(double (&)[RPT][B], int, double*, double*, double*,
+                                             double*) {}
+};
+
+// Chunk factorisation; B >= b is the compile-time width (columns b..B-1 are zero padding).
+template <int B, int RPT>
 __global__ __launch_bounds__(TPB) void k_house_factor(double* __restrict__ X, int64_t ldx,
                                                       int64_t rows, int b, int CR,
                                                       double* __restrict__ tau,
                                                       double* __restrict__ Rnext, int64_t ldr,
                                                       const Ctrl* __restrict__ ctrl, int iter) {
   if (skip_iter(ctrl, iter)) return;
-  __shared__ double red[(TPB / 64) * BMAX];
-  __shared__ double sc[BMAX];       // s_c = sum_{i>j} x_ij x_ic   (c >= j)
-  __shared__ double rowj[BMAX];     // x_jc, the current pivot row
+  __shared__ double red[(TPB / 64) * B];
+  __shared__ double sc[B];
+  __shared__ double rowj[B];
   const int64_t r0 = (int64_t)blockIdx.x * CR;
   const int cnt = (int)min<int64_t>(CR, rows - r0);
-  double x[RPT][BMAX];
+  double x[RPT][B];
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int i = threadIdx.x + t * TPB;
 #pragma unroll
-    for (int c = 0; c < BMAX; ++c) x[t][c] = (c < b && i < cnt) ? X[c * ldx + r0 + i] : 0.0;
+    for (int c = 0; c < B; ++c) x[t][c] = (c < b && i < cnt) ? X[c * ldx + r0 + i] : 0.0;
   }
-  // One block reduction per column: with s_c = sum_{i>j} x_ij x_ic, the reflector of column j
-  // (LAPACK dlarfg: beta = -sign(alpha) sqrt(alpha^2 + s_j), tau = (beta - alpha) / beta,
-  // v_i = x_ij / (alpha - beta)) gives w_c = v^T x_c = x_jc + s_c / (alpha - beta) directly.
-  for (int j = 0; j < b; ++j) {
-    double part[BMAX];
-#pragma unroll
-    for (int c = 0; c < BMAX; ++c) part[c] = 0.0;
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-      const int i = threadIdx.x + t * TPB;
-      double xij = 0.0;
-#pragma unroll
-      for (int c = 0; c < BMAX; ++c)
-        if (c == j) xij = x[t][c];
-      if (i > j) {
-#pragma unroll
-        for (int c = 0; c < BMAX; ++c)
-          if (c >= j && c < b) part[c] = fma(xij, x[t][c], part[c]);
-      }
-      if (i == j) {
-#pragma unroll
-        for (int c = 0; c < BMAX; ++c) rowj[c] = x[t][c];
-      }
-    }
-    block_sum<BMAX>(part, b, red, sc);
-    const double alpha = rowj[j], xn2 = sc[j];
-    double tj, beta, scal;
-    if (xn2 == 0.0) {
-      tj = 0.0; beta = alpha; scal = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      tj = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
-    }
-    if (threadIdx.x == 0) tau[(int64_t)blockIdx.x * b + j] = tj;
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-      const int i = threadIdx.x + t * TPB;
-      double vi = 0.0;
-#pragma unroll
-      for (int c = 0; c < BMAX; ++c)
-        if (c == j) vi = (i > j) ? x[t][c] * scal : (i == j ? 1.0 : 0.0);
-      if (i >= j) {
-#pragma unroll
-        for (int c = 0; c < BMAX; ++c) {
-          if (c > j && c < b) x[t][c] -= tj * vi * (rowj[c] + scal * sc[c]);
-          if (c == j) x[t][c] = (i > j) ? vi : beta;
-        }
-      }
-    }
-    __syncthreads();   // rowj / sc are rewritten by the next column
-  }
+  HouseCols<0, B, RPT>::run(x, b, red, sc, rowj, tau + (int64_t)blockIdx.x * b);
   // reflectors back in place (rows < cnt), R (upper triangle, zero below) to the next level
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int i = threadIdx.x + t * TPB;
 #pragma unroll
-    for (int c = 0; c < BMAX; ++c) {
+    for (int c = 0; c < B; ++c) {
       if (c < b) {
         if (i < cnt) X[c * ldx + r0 + i] = x[t][c];
         if (i < b) Rnext[c * ldr + (int64_t)blockIdx.x * b + i] = (i <= c) ? x[t][c] : 0.0;
@@ -319,7 +379,48 @@ __global__ __launch_bounds__(TPB) void k_house_factor(double* __restrict__ X, in
 // chunk's reflectors.  At the root (Qabove == null) the start is D = diag(sign(R_jj)) with R the
 // root's stacked rows, so the final R = D R has a nonnegative diagonal; the root also writes that
 // R (row-major b x b) to Rout.
-template <int BMAX, int RPT>
+template <int J, int B, int RPT>
+struct FormCols {   // applies H_J, then H_{J-1}, ..., H_0
+  static __device__ __forceinline__ void run(const double (&v)[RPT][B], double (&y)[RPT][B], int b,
+                                             const double* tau, double* red, double* bc) {
+    if (J < b) {
+      const double tj = tau[J];
+      if (tj != 0.0) {
+        double w[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) w[c] = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          const int i = threadIdx.x + t * TPB;
+          const double vi = (i > J) ? v[t][J] : (i == J ? 1.0 : 0.0);
+#pragma unroll
+          for (int c = 0; c < B; ++c) w[c] = fma(vi, y[t][c], w[c]);
+        }
+        block_sum_range<0, B, B>(w, red, bc);
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          const int i = threadIdx.x + t * TPB;
+          const double vi = (i > J) ? v[t][J] : (i == J ? 1.0 : 0.0);
+#pragma unroll
+          for (int c = 0; c < B; ++c) y[t][c] = fma(-tj * vi, bc[c], y[t][c]);
+        }
+        __syncthreads();
+      }
+    }
+    FormCols<J - 1, B, RPT>::run(v, y, b, tau, red, bc);
+  }
+};
+template <int B, int RPT>
+struct FormCols<-1, B, RPT> {
+  static __device__ __forceinline__ void run(const double (&)[RPT][B], double (&)[RPT][B], int,
+                                             const double*, double*, double*) {}
+};
+
+// Explicit Q of each chunk: Y = H_0 H_1 ... H_{b-1} [Qabove(chunk rows); 0], written over the
+// chunk's reflectors.  At the root (Qabove == null) the start is D = diag(sign(R_jj)) with R the
+// root's stacked rows, so the final R = D R has a nonnegative diagonal; the root also writes that
+// R (row-major b x b) to Rout.
+template <int B, int RPT>
 __global__ __launch_bounds__(TPB) void k_house_form(double* __restrict__ X, int64_t ldx,
                                                     int64_t rows, int b, int CR,
                                                     const double* __restrict__ tau,
@@ -328,9 +429,9 @@ __global__ __launch_bounds__(TPB) void k_house_form(double* __restrict__ X, int6
                                                     int64_t ldr, double* __restrict__ Rout,
                                                     const Ctrl* __restrict__ ctrl, int iter) {
   if (skip_iter(ctrl, iter)) return;
-  __shared__ double red[(TPB / 64) * BMAX];
-  __shared__ double bc[BMAX];
-  __shared__ double d[BMAX];
+  __shared__ double red[(TPB / 64) * B];
+  __shared__ double bc[B];
+  __shared__ double d[B];
   const int64_t r0 = (int64_t)blockIdx.x * CR;
   const int cnt = (int)min<int64_t>(CR, rows - r0);
   if (Qabove == nullptr && threadIdx.x < b) {
@@ -344,12 +445,12 @@ __global__ __launch_bounds__(TPB) void k_house_form(double* __restrict__ X, int6
       Rout[idx] = (c >= i) ? d[i] * Rroot[c * ldr + i] : 0.0;
     }
   }
-  double v[RPT][BMAX], y[RPT][BMAX];
+  double v[RPT][B], y[RPT][B];
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int i = threadIdx.x + t * TPB;
 #pragma unroll
-    for (int c = 0; c < BMAX; ++c) {
+    for (int c = 0; c < B; ++c) {
       v[t][c] = (c < b && i < cnt) ? X[c * ldx + r0 + i] : 0.0;
       double y0 = 0.0;
       if (c < b && i < b) {
@@ -359,43 +460,13 @@ __global__ __launch_bounds__(TPB) void k_house_form(double* __restrict__ X, int6
       y[t][c] = y0;
     }
   }
-  for (int j = b - 1; j >= 0; --j) {
-    const double tj = tau[(int64_t)blockIdx.x * b + j];
-    if (tj == 0.0) continue;
-    double w[BMAX];
-#pragma unroll
-    for (int c = 0; c < BMAX; ++c) w[c] = 0.0;
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-      const int i = threadIdx.x + t * TPB;
-      double vi = 0.0;
-#pragma unroll
-      for (int c = 0; c < BMAX; ++c)
-        if (c == j) vi = (i > j) ? v[t][c] : (i == j ? 1.0 : 0.0);
-#pragma unroll
-      for (int c = 0; c < BMAX; ++c)
-        if (c < b) w[c] = fma(vi, y[t][c], w[c]);
-    }
-    block_sum<BMAX>(w, b, red, bc);
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-      const int i = threadIdx.x + t * TPB;
-      double vi = 0.0;
-#pragma unroll
-      for (int c = 0; c < BMAX; ++c)
-        if (c == j) vi = (i > j) ? v[t][c] : (i == j ? 1.0 : 0.0);
-#pragma unroll
-      for (int c = 0; c < BMAX; ++c)
-        if (c < b) y[t][c] -= tj * vi * bc[c];
-    }
-    __syncthreads();
-  }
+  FormCols<B - 1, B, RPT>::run(v, y, b, tau + (int64_t)blockIdx.x * b, red, bc);
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int i = threadIdx.x + t * TPB;
     if (i < cnt) {
 #pragma unroll
-      for (int c = 0; c < BMAX; ++c)
+      for (int c = 0; c < B; ++c)
         if (c < b) X[c * ldx + r0 + i] = y[t][c];
     }
   }
@@ -498,11 +569,10 @@ __global__ void k_rb_assemble(const double* __restrict__ C1, const double* __res
 // ------------------------------------------------------------------------------------------------
 // One-sided Jacobi on M = R_B^T (L x L, L = l_eff): columns of M are the rows of R_B.  Round-robin
 // ordering: in each of the N-1 rounds (N = L rounded up to even) the N/2 disjoint pairs are rotated
-// in parallel, one wave per pair.  Each rotation is logged as (p, q, c, s) so J can be rebuilt by
-// k_jacobi_apply.  Outputs: sig (descending), perm, W = M J (column perm[j] holds sigma_j u_j).
+// in parallel, one 16-lane row per pair.  Outputs: sig (descending), perm, W = M J (column perm[j]
+// holds sigma_j u_j).
 constexpr int JMAX = 128;
 constexpr int JSWEEPS = 40;
-constexpr int kJacobiLds = 160 * 1024 - 256;   // dynamic LDS of the fused Jacobi kernel
 
 __device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
   if (k == 0) { p = N - 1; q = r; }
@@ -510,45 +580,49 @@ __device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
   if (p > q) { const int t = p; p = q; q = t; }
 }
 
-// With fuse_j, J (N x N, column-major) lives in LDS after M and each rotation is applied to it
-// at once; otherwise the rotations are logged for k_jacobi_apply.  Each 16-lane row holds the L
-// (<= 128) entries of its pair's columns as 8 registers per lane.
+// M (N columns padded to LP rows, zero beyond L) lives in LDS; the round-robin pair table is
+// precomputed once.  The right factor is not accumulated: with M J = W (orthogonal columns,
+// norms sigma), B^T = Q_B R_B and M = R_B^T, B^T W = Q_B J S^2, so V = B^T W S^-2 (see run_finalize).
+constexpr int kJacobiLds = 160 * 1024 - 1024;   // dynamic LDS limit of k_jacobi
+
 __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, int ldr, int L,
                                                  double* __restrict__ W, int ldw,
-                                                 double4* __restrict__ log, int* __restrict__ info,
-                                                 double* __restrict__ sig, int* __restrict__ perm,
-                                                 double* __restrict__ Jout, int fuse_j) {
-  extern __shared__ double M[];           // N columns of L entries, then J when fused
+                                                 int* __restrict__ info, double* __restrict__ sig,
+                                                 int* __restrict__ perm, double* __restrict__ nrm) {
+  extern __shared__ double M[];           // N columns x LPAD rows, then the pair table
   __shared__ int rotated;
   const int N = (L + 1) & ~1;
-  double* Jl = M + N * L;
+  const int LPAD = (L + 15) & ~15;
+  uint8_t* pairs = reinterpret_cast<uint8_t*>(M + (int64_t)N * LPAD);   // (N-1) x N/2 x {p, q}
   const double tol = (double)L * 2.220446049250313e-16;
-  constexpr int EPL = JMAX / 16;          // entries per lane of a column
+  constexpr int EPL = JMAX / 16;          // entries per lane of a column (LPAD <= 128)
   const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15, ngrp = blockDim.x >> 4;
-  for (int idx = threadIdx.x; idx < N * L; idx += blockDim.x) {
-    const int col = idx / L, i = idx % L;
-    M[idx] = (col < L) ? RB[col * ldr + i] : 0.0;     // M(:, col) = R_B(col, :)^T
+  for (int idx = threadIdx.x; idx < N * LPAD; idx += blockDim.x) {
+    const int col = idx / LPAD, i = idx % LPAD;
+    M[idx] = (col < L && i < L) ? RB[col * ldr + i] : 0.0;     // M(:, col) = R_B(col, :)^T
   }
-  if (fuse_j)
-    for (int idx = threadIdx.x; idx < N * N; idx += blockDim.x)
-      Jl[idx] = (idx / N == idx % N) ? 1.0 : 0.0;
+  for (int idx = threadIdx.x; idx < (N - 1) * (N / 2); idx += blockDim.x) {
+    int p, q;
+    rr_pair(N, idx / (N / 2), idx % (N / 2), p, q);
+    pairs[2 * idx] = (uint8_t)p;
+    pairs[2 * idx + 1] = (uint8_t)q;
+  }
   __syncthreads();
+  const int nel = LPAD / 16;
   int sweep = 0;
   for (; sweep < JSWEEPS && N > 1; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
       for (int k = grp; k < N / 2; k += ngrp) {
-        int p, q;
-        rr_pair(N, r, k, p, q);
-        double* mp = M + p * L;
-        double* mq = M + q * L;
+        const int p = pairs[2 * (r * (N / 2) + k)], q = pairs[2 * (r * (N / 2) + k) + 1];
+        double* mp = M + p * LPAD + gl;
+        double* mq = M + q * LPAD + gl;
         double xp[EPL], xq[EPL];
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-          const int i = gl + 16 * e;
-          xp[e] = (i < L) ? mp[i] : 0.0;
-          xq[e] = (i < L) ? mq[i] : 0.0;
+          if (e < nel) { xp[e] = mp[16 * e]; xq[e] = mq[16 * e]; }
+          else { xp[e] = 0.0; xq[e] = 0.0; }
         }
         double a = 0, bb = 0, g = 0;
 #pragma unroll
@@ -556,46 +630,21 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, 
           a = fma(xp[e], xp[e], a); bb = fma(xq[e], xq[e], bb); g = fma(xp[e], xq[e], g);
         }
         a = row16_sum(a); bb = row16_sum(bb); g = row16_sum(g);
-        double c = 1.0, s = 0.0;
         // rotate unless the pair is orthogonal to working precision (L eps relative)
-        const bool rot = (g != 0.0) && (fabs(g) > tol * sqrt(a * bb));
-        if (rot) {
+        if ((g != 0.0) && (fabs(g) > tol * sqrt(a * bb))) {
           const double zeta = (bb - a) / (2.0 * g);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = c * t;
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double s = c * t;
 #pragma unroll
           for (int e = 0; e < EPL; ++e) {
-            const int i = gl + 16 * e;
-            if (i < L) {
-              mp[i] = c * xp[e] - s * xq[e];
-              mq[i] = s * xp[e] + c * xq[e];
-            }
-          }
-          if (fuse_j) {
-            double* jp = Jl + p * N;
-            double* jq = Jl + q * N;
-            double yp[EPL], yq[EPL];
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) {
-              const int i = gl + 16 * e;
-              yp[e] = (i < N) ? jp[i] : 0.0;
-              yq[e] = (i < N) ? jq[i] : 0.0;
-            }
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) {
-              const int i = gl + 16 * e;
-              if (i < N) {
-                jp[i] = c * yp[e] - s * yq[e];
-                jq[i] = s * yp[e] + c * yq[e];
-              }
+            if (e < nel) {
+              mp[16 * e] = c * xp[e] - s * xq[e];
+              mq[16 * e] = s * xp[e] + c * xq[e];
             }
           }
           if (gl == 0) rotated = 1;
         }
-        if (!fuse_j && gl == 0)
-          log[((int64_t)sweep * (N - 1) + r) * (N / 2) + k] =
-              make_double4((double)p, (double)q, c, rot ? s : 0.0);
       }
       __syncthreads();
     }
@@ -603,11 +652,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, 
     __syncthreads();
   }
   if (threadIdx.x == 0) info[0] = sweep;
-  // column norms into the (now free) log-independent scratch at the end of W's rows
-  double* nrm = Jout + (int64_t)L * ldw;   // L scratch doubles past J (see carve_small)
   for (int col = threadIdx.x; col < L; col += blockDim.x) {
     double s = 0;
-    for (int i = 0; i < L; ++i) s = fma(M[col * L + i], M[col * L + i], s);
+    for (int i = 0; i < L; ++i) s = fma(M[col * LPAD + i], M[col * LPAD + i], s);
     nrm[col] = sqrt(s);
   }
   __syncthreads();
@@ -620,56 +667,21 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, 
   }
   for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x) {
     const int col = idx / L, i = idx % L;
-    W[i * ldw + col] = M[col * L + i];   // W row-major L x L
-    if (fuse_j) Jout[i * ldw + col] = Jl[col * N + i];
+    W[i * ldw + col] = M[col * LPAD + i];   // W row-major L x L
   }
 }
 
-// J = product of the logged rotations, applied round by round to the rows of the identity; the
-// next round's rotations are fetched into LDS while the current round is applied.
-__global__ __launch_bounds__(1024) void k_jacobi_apply(const double4* __restrict__ log,
-                                                       const int* __restrict__ info, int L,
-                                                       double* __restrict__ J, int ldj) {
-  extern __shared__ double Js[];          // N x N row-major
-  __shared__ double4 lg[2][JMAX / 2];
-  const int N = (L + 1) & ~1;
-  const int half = N / 2;
-  for (int idx = threadIdx.x; idx < N * N; idx += blockDim.x)
-    Js[idx] = (idx / N == idx % N) ? 1.0 : 0.0;
-  const int rounds = info[0] * (N - 1);
-  if (rounds > 0 && threadIdx.x < half) lg[0][threadIdx.x] = log[threadIdx.x];
-  __syncthreads();
-  for (int sr = 0; sr < rounds; ++sr) {
-    const int cur = sr & 1;
-    double4 nxt = make_double4(0, 0, 0, 0);
-    const bool pre = (sr + 1 < rounds) && (threadIdx.x < half);
-    if (pre) nxt = log[(int64_t)(sr + 1) * half + threadIdx.x];   // lands while this round runs
-    for (int item = threadIdx.x; item < N * half; item += blockDim.x) {
-      const int row = item / half, k = item % half;
-      const double4 e = lg[cur][k];
-      if (e.w != 0.0) {
-        const int p = (int)e.x, q = (int)e.y;
-        const double xp = Js[row * N + p], xq = Js[row * N + q];
-        Js[row * N + p] = e.z * xp - e.w * xq;
-        Js[row * N + q] = e.w * xp + e.z * xq;
-      }
-    }
-    if (pre) lg[cur ^ 1][threadIdx.x] = nxt;
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x)
-    J[(idx / L) * ldj + idx % L] = Js[(idx / L) * N + idx % L];
-}
-
-// Gather the k leading right/left factors: Jk = J(:, perm[0:kk]), Wk = W(:, perm[0:kk]) / sig.
-__global__ void k_gather(const double* __restrict__ J, const double* __restrict__ W, int ld, int L,
-                         const int* __restrict__ perm, const double* __restrict__ sig, int kk,
-                         double* __restrict__ Jk, double* __restrict__ Wk) {
+// Gather the k leading factors: Wk = W(:, perm[0:kk]) / sig (U = Q Wk) and
+// Wv = W(:, perm[0:kk]) / sig^2 (V = B^T Wv).
+__global__ void k_gather(const double* __restrict__ W, int ld, int L, const int* __restrict__ perm,
+                         const double* __restrict__ sig, int kk, double* __restrict__ Wv,
+                         double* __restrict__ Wk) {
   for (int idx = threadIdx.x; idx < L * kk; idx += blockDim.x) {
     const int i = idx / kk, j = idx % kk;
     const int col = perm[j];
-    Jk[idx] = J[i * ld + col];
-    Wk[idx] = sig[j] > 0.0 ? W[i * ld + col] / sig[j] : 0.0;
+    const double sj = sig[j];
+    Wk[idx] = sj > 0.0 ? W[i * ld + col] / sj : 0.0;
+    Wv[idx] = sj > 0.0 ? W[i * ld + col] / (sj * sj) : 0.0;
   }
 }
 
@@ -704,36 +716,59 @@ __global__ __launch_bounds__(TPB) void k_signs(const double* __restrict__ V, int
 }
 
 // out = sign_j * (X Wk)(r, j) for j < kk, 0 for kk <= j < k; row-major (out[r*ld + j]) or, with
-// colmajor, out[j*ld + r].  sgn may be null (all +1).
+// colmajor, out[j*ld + r].  sgn may be null (all +1).  Grid: x = row blocks, y = 16-column slabs.
 __global__ __launch_bounds__(TPB) void k_write_rows(const double* __restrict__ X, int64_t ldx,
                                                     int L, const double* __restrict__ Wk, int kk,
                                                     int k, const double* __restrict__ sgn,
                                                     int64_t rows, double* __restrict__ out,
                                                     int64_t ld, int colmajor) {
   extern __shared__ double ws[];
-  for (int idx = threadIdx.x; idx < L * kk; idx += TPB) ws[idx] = Wk[idx];
+  const int j0 = blockIdx.y * 16;
+  for (int idx = threadIdx.x; idx < L * 16; idx += TPB) {
+    const int a = idx / 16, j = idx % 16;
+    ws[idx] = (j0 + j < kk) ? Wk[a * kk + j0 + j] : 0.0;
+  }
   __syncthreads();
   for (int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x; r < rows;
        r += (int64_t)gridDim.x * TPB) {
-    for (int j0 = 0; j0 < k; j0 += 16) {
-      double acc[16];
+    double acc[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-      for (int a = 0; a < L; ++a) {
-        const double x = X[a * ldx + r];
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    int a = 0;
+    for (; a + 4 <= L; a += 4) {
+      double x[4];
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j0 + j < kk) acc[j] = fma(x, ws[a * kk + j0 + j], acc[j]);
-      }
+      for (int u = 0; u < 4; ++u) x[u] = X[(a + u) * ldx + r];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        if (j0 + j < k) {
-          const double v = (j0 + j < kk) ? (sgn ? sgn[j0 + j] : 1.0) * acc[j] : 0.0;
-          if (colmajor) out[(int64_t)(j0 + j) * ld + r] = v;
-          else out[r * ld + j0 + j] = v;
-        }
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = fma(x[u], ws[(a + u) * 16 + j], acc[j]);
+    }
+    for (; a < L; ++a) {
+      const double x = X[a * ldx + r];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = fma(x, ws[a * 16 + j], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j0 + j < k) {
+        const double v = (j0 + j < kk) ? (sgn ? sgn[j0 + j] : 1.0) * acc[j] : 0.0;
+        if (colmajor) out[(int64_t)(j0 + j) * ld + r] = v;
+        else out[r * ld + j0 + j] = v;
       }
     }
+  }
+}
+
+// out (row-major rows x k, ld) = sign_j * Vt(:, j) (column-major, ldv) for j < kk, 0 beyond.
+__global__ void k_signed_transpose(const double* __restrict__ Vt, int64_t ldv, int kk, int k,
+                                   const double* __restrict__ sgn, int64_t rows,
+                                   double* __restrict__ out, int64_t ld) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < rows * k;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = q / k;
+    const int j = (int)(q - r * k);
+    out[r * ld + j] = (j < kk) ? sgn[j] * Vt[(int64_t)j * ldv + r] : 0.0;
   }
 }
 
@@ -802,9 +837,10 @@ template <typename BT>
 void nn(Ctx& cx, double* out, int64_t ldo, const BT* base, int64_t ldb, const double* X,
         int64_t ldx, int p, const double* W, int ldw, int q, int64_t rows, double alpha,
         const Ctrl* ctrl, int iter) {
-  if (!cx.ok() || q == 0) return;
-  const size_t shm = (size_t)(p * q > 0 ? p * q : 1) * sizeof(double);
-  const dim3 g(grid_for(rows, TPB, 8192)), blk(TPB);
+  if (!cx.ok() || q == 0 || rows == 0) return;
+  const int qmax = q <= 8 ? 8 : (q <= 16 ? 16 : 32);
+  const size_t shm = (size_t)(((p * q + 1) & ~1) + 3 * qmax * 64) * sizeof(double);
+  const dim3 g((unsigned)cdiv<int64_t>(rows, 64)), blk(TPB);
   if (q <= 8)
     hipLaunchKernelGGL((k_nn_update<BT, 8>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p, W,
                        ldw, q, rows, alpha, ctrl, iter);
@@ -865,15 +901,22 @@ void tsqr_t(Ctx& cx, double* X, int64_t ldx, int64_t rows, int b, double* ws, do
 void tsqr(Ctx& cx, double* X, int64_t ldx, int64_t rows, int b, double* ws, double* Rout,
           const Ctrl* ctrl, int iter) {
   if (!cx.ok()) return;
-  if (b <= 8) tsqr_t<8, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  // exact widths for the common b; others run in the next wider instantiation with zero padding
+  if (b <= 1) tsqr_t<1, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  else if (b <= 2) tsqr_t<2, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  else if (b <= 4) tsqr_t<4, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  else if (b <= 5) tsqr_t<5, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  else if (b <= 8) tsqr_t<8, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  else if (b <= 10) tsqr_t<10, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
   else if (b <= 16) tsqr_t<16, 4>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
+  else if (b <= 20) tsqr_t<20, 2>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
   else tsqr_t<32, 2>(cx, X, ldx, rows, b, ws, Rout, ctrl, iter);
 }
 
 // Small-buffer layout (doubles), see finalize_small_elems.
 struct Small {
   double *W, *T, *C, *Wn, *R1, *R2, *R, *RB, *C1, *C2, *Jm, *Wm, *sig, *Jk, *Wk, *sgn;
-  int* perm; int* info; double4* log;
+  int* perm; int* info;
 };
 Small carve_small(double* base, int l, int b) {
   const int P = l * 32;   // p x b blocks with p <= l, b <= 32
@@ -887,38 +930,26 @@ Small carve_small(double* base, int l, int b) {
   sm.Jk = take((int64_t)l * l); sm.Wk = take((int64_t)l * l); sm.sgn = take(l);
   sm.perm = reinterpret_cast<int*>(take(l));
   sm.info = reinterpret_cast<int*>(take(4));
-  const int N = (l + 1) & ~1;
-  sm.log = reinterpret_cast<double4*>(take((int64_t)JSWEEPS * (N - 1 > 0 ? N - 1 : 1) * (N / 2 > 0 ? N / 2 : 1) * 4));
   return sm;
 }
 
 }  // namespace
 
 hipError_t finalize_prepare() {
-  const int big = JMAX * JMAX * (int)sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiLds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_jacobi_apply,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_write_rows,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  return e;
+  return hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             kJacobiLds);
 }
 
 size_t finalize_small_elems(int l, int b) {
   (void)b;
-  const int N = (l + 1) & ~1;
   const int64_t P = (int64_t)l * 32;
   int64_t e = 6 * rup<int64_t>(P, 32) + 3 * 1024 + 5 * rup<int64_t>((int64_t)l * l + l, 32) +
-              3 * rup<int64_t>(l, 32) + 32 +
-              rup<int64_t>((int64_t)JSWEEPS * (N - 1 > 0 ? N - 1 : 1) * (N / 2 > 0 ? N / 2 : 1) * 4, 32);
+              3 * rup<int64_t>(l, 32) + 32;
   return (size_t)e + 1024;
 }
 
 size_t tsqr_workspace_elems(int64_t rows, int b) {
-  const int RPT = (b <= 16) ? 4 : 2;
+  const int RPT = 2;   // the smallest rows-per-thread of any instantiation: most chunks
   const int64_t CR0 = TPB * RPT;
   int64_t total = 0, r = rows;
   for (int guard = 0; guard < 16; ++guard) {
@@ -1022,43 +1053,32 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
     }
     if (!cx.ok()) return cx.err;
     // ---------------- Jacobi SVD of R_B^T
-    const int N = (L + 1) & ~1;
-    const size_t jshm = (size_t)N * (L + N) * sizeof(double);
-    const int fuse = jshm <= (size_t)kJacobiLds;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024),
-                       fuse ? jshm : (size_t)N * L * sizeof(double), stream, sm.RB, L, L, sm.Wm, L,
-                       sm.log, sm.info, sm.sig, sm.perm, sm.Jm, fuse);
+    const int N = (L + 1) & ~1, LPAD = (L + 15) & ~15;
+    const size_t jshm = (size_t)N * LPAD * sizeof(double) + (size_t)(N - 1) * (N / 2) * 2 + 16;
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), jshm, stream, sm.RB, L, L, sm.Wm, L,
+                       sm.info, sm.sig, sm.perm, sm.Jm);
     cx.chk();
     if (!cx.ok()) return cx.err;
-    if (!fuse) {
-      hipLaunchKernelGGL(k_jacobi_apply, dim3(1), dim3(1024), (size_t)N * N * sizeof(double),
-                         stream, sm.log, sm.info, L, sm.Jm, L);
-      cx.chk();
-      if (!cx.ok()) return cx.err;
-    }
-    hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, stream, sm.Jm, sm.Wm, L, L, sm.perm,
-                       sm.sig, kk, sm.Jk, sm.Wk);
+    hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, stream, sm.Wm, L, L, sm.perm, sm.sig, kk,
+                       sm.Jk, sm.Wk);
     cx.chk();
-    // V (column-major temp in the H storage) = Q_B Jk, signs, then the row-major outputs
+    // V (column-major temp in the H storage) = B^T W S^-2, its signs, then the row-major outputs
     double* Vt = const_cast<double*>(f.H);
-    hipLaunchKernelGGL(k_write_rows, dim3(grid_for(n, TPB, 8192)), dim3(TPB),
-                       (size_t)L * kk * sizeof(double), stream, f.Qb, f.ldb, L, sm.Jk, kk, kk,
-                       (const double*)nullptr, n, Vt, f.ldh, 1);
+    const dim3 gv(grid_for(n, TPB, 4096), cdiv(kk, 16));
+    hipLaunchKernelGGL(k_write_rows, gv, dim3(TPB), (size_t)L * 16 * sizeof(double), stream,
+                       f.Bt, f.ldb, L, sm.Jk, kk, kk, (const double*)nullptr, n, Vt, f.ldh, 1);
     cx.chk();
     if (!cx.ok()) return cx.err;
     hipLaunchKernelGGL(k_signs, dim3(kk), dim3(TPB), 0, stream, Vt, f.ldh, n, sm.sgn);
     cx.chk();
     if (!cx.ok()) return cx.err;
-    // V = Vt with signs: reuse k_write_rows with X = Vt and Wk = identity would cost a pass; write
-    // directly from Q_B instead.
-    hipLaunchKernelGGL(k_write_rows, dim3(grid_for(n, TPB, 8192)), dim3(TPB),
-                       (size_t)L * kk * sizeof(double), stream, f.Qb, f.ldb, L, sm.Jk, kk, f.k,
-                       sm.sgn, n, f.V, f.ldv, 0);
+    hipLaunchKernelGGL(k_signed_transpose, dim3(grid_for(n * f.k)), dim3(TPB), 0, stream, Vt,
+                       f.ldh, kk, f.k, sm.sgn, n, f.V, f.ldv);
     cx.chk();
     if (f.U && cx.ok()) {
-      hipLaunchKernelGGL(k_write_rows, dim3(grid_for(m, TPB, 8192)), dim3(TPB),
-                         (size_t)L * kk * sizeof(double), stream, f.Q, f.ldq, L, sm.Wk, kk, f.k,
-                         sm.sgn, m, f.U, f.ldu, 0);
+      const dim3 gu(grid_for(m, TPB, 4096), cdiv(f.k, 16));
+      hipLaunchKernelGGL(k_write_rows, gu, dim3(TPB), (size_t)L * 16 * sizeof(double), stream,
+                         f.Q, f.ldq, L, sm.Wk, kk, f.k, sm.sgn, m, f.U, f.ldu, 0);
       cx.chk();
     }
     if (!cx.ok()) return cx.err;
@@ -1070,12 +1090,12 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
     (void)zero_s;
     cx.err = launch_fill_f64(f.S, f.k, 0.0, stream);
     for (int64_t r = 0; r < 1 && cx.ok(); ++r) {
-      hipLaunchKernelGGL(k_write_rows, dim3(grid_for(n, TPB, 8192)), dim3(TPB), 8, stream, f.Qb,
-                         f.ldb, 0, sm.Jk, 0, f.k, sm.sgn, n, f.V, f.ldv, 0);
+      hipLaunchKernelGGL(k_write_rows, dim3(grid_for(n, TPB, 4096), cdiv(f.k, 16)), dim3(TPB), 8,
+                         stream, f.Qb, f.ldb, 0, sm.Jk, 0, f.k, sm.sgn, n, f.V, f.ldv, 0);
       cx.chk();
       if (f.U && cx.ok()) {
-        hipLaunchKernelGGL(k_write_rows, dim3(grid_for(m, TPB, 8192)), dim3(TPB), 8, stream, f.Q,
-                           f.ldq, 0, sm.Wk, 0, f.k, sm.sgn, m, f.U, f.ldu, 0);
+        hipLaunchKernelGGL(k_write_rows, dim3(grid_for(m, TPB, 4096), cdiv(f.k, 16)), dim3(TPB),
+                           8, stream, f.Q, f.ldq, 0, sm.Wk, 0, f.k, sm.sgn, m, f.U, f.ldu, 0);
         cx.chk();
       }
     }

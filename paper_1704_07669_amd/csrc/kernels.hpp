@@ -44,7 +44,13 @@ struct PassArgs {
   int64_t ldh;
   const int* fp8_exp;  // device exponent e of the block scale 2^e (FP8 mode), else null
   Ctrl* ctrl;
+  void* P2;            // row-split partials of a^T g: strips x rsplit_max x LP x 64 (acc type)
+  unsigned* counters;  // one zero-initialised arrival counter per column strip
+  int rsplit_max;
 };
+// Sizes of the row-split scratch of a^T g for a configuration.
+int64_t gemm2_strips(int64_t n);
+constexpr int kGemm2MaxSplits = 8;
 int gemm1_row_tile(int mode);
 hipError_t launch_gemm1(const PassArgs& a, hipStream_t s);
 hipError_t launch_reduce1(const PassArgs& a, hipStream_t s);

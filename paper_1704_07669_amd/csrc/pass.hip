@@ -11,6 +11,7 @@
 // every matrix-core operand a run of consecutive k values per lane:
 //   g = a Omega : k = column of a; A operand = a rows, B operand = Omega' columns (staged in LDS).
 //   a^T g       : k = row of a;    A operand = G columns (the transposed G), B operand = a columns.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.hpp"
@@ -433,12 +434,15 @@ template <typename Src, int MODE, int NT>
 __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
     const Src* __restrict__ A, int64_t lda, int nrows, int64_t n, const void* __restrict__ gop,
     int64_t ldp, int LP, double* __restrict__ H, int64_t ldh, const int* __restrict__ fp8_exp,
-    int vec_ok) {
+    int vec_ok, int rsplit, int rchunk, typename PT<MODE>::acc_t* __restrict__ part,
+    unsigned* __restrict__ counters) {
   using T = PT<MODE>;
   using acc_t = typename T::acc_t;
   using accv = typename T::accv;
   constexpr int V2 = T::V2, VC = T::VC, KR = 4 * V2;
-  __shared__ acc_t red[(WAVES - 1) * VC * 4 * 64];
+  extern __shared__ __attribute__((aligned(16))) uint8_t red_raw[];   // (nwaves-1) x VC x 4 x 64
+  acc_t* red = reinterpret_cast<acc_t*>(red_raw);
+  const int nwaves = blockDim.x >> 6;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
   const int64_t c0 = (int64_t)blockIdx.x * 16 * VC;
@@ -451,11 +455,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
 #pragma unroll
     for (int j = 0; j < VC; ++j) acc[mt][j] = accv{0, 0, 0, 0};
 
+  // this workgroup's row range (blockIdx.y of rsplit), rows relative to the block
+  const int row_lo = blockIdx.y * rchunk;
+  const int row_hi = min(nrows, row_lo + rchunk);
+
   // A and G of the next super-step are fetched before the matrix-core work of the current one
   Src a0[V2][VC], a1[V2][VC];
   GFrag<MODE> g0[NT], g1[NT];
-  constexpr int STRIDE = WAVES * KR;
-  int kr = wave * KR;
+  const int STRIDE = nwaves * KR;
+  int kr = row_lo + wave * KR;
+  nrows = row_hi;
   if (kr < nrows) {
     fetch_cols<Src, V2, VC>(A, lda, kr, g, nrows, col, n, cols_full, a0);
     fetch_gall<MODE, NT>(gop, ldp, LP, r16, kr + V2 * g, nrows, g0);
@@ -476,6 +485,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
 
   mfma_drain();
   const double scale = fp8_exp ? ldexp(1.0, -(*fp8_exp)) : 1.0;
+  // Row-split partials: every workgroup of a strip writes its (wave-ordered) FP32 sum; the last
+  // one to finish, found with a per-strip counter, adds the rsplit partials in split order into
+  // the FP64 rows of H and resets the counter.  No workgroup waits on another.
+  const int64_t strip = blockIdx.x;
+  const int64_t pstride = (int64_t)LP * 16 * VC;          // one partial tile
+  acc_t* mine = part + (strip * rsplit + blockIdx.y) * pstride;
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
     __syncthreads();
@@ -489,18 +504,37 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
     if (wave == 0) {
 #pragma unroll
       for (int j = 0; j < VC; ++j) {
-        if (col + j >= n) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          acc_t s = acc[mt][j][i];
-          for (int w = 1; w < WAVES; ++w) s += red[(((w - 1) * VC + j) * 4 + i) * 64 + lane];
+          acc_t sm = acc[mt][j][i];
+          for (int w = 1; w < nwaves; ++w) sm += red[(((w - 1) * VC + j) * 4 + i) * 64 + lane];
           const int lidx = mt * 16 + acc_row<acc_t>(g, i);
-          double* h = H + (int64_t)lidx * ldh + col + j;
-          *h += scale * (double)s;
+          if (rsplit == 1) {
+            if (col + j < n) H[(int64_t)lidx * ldh + col + j] += scale * (double)sm;
+          } else {
+            mine[(int64_t)lidx * 16 * VC + VC * r16 + j] = sm;
+          }
         }
       }
     }
   }
+  if (rsplit == 1) return;
+  __shared__ unsigned last;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last = (atomicAdd(counters + strip, 1u) == (unsigned)(rsplit - 1));
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const acc_t* base = part + strip * rsplit * pstride;
+  for (int e = tid; e < pstride; e += blockDim.x) {
+    const int lidx = e / (16 * VC), cc = e - lidx * 16 * VC;
+    if (c0 + cc >= n) continue;
+    double sm = 0.0;
+    for (int t = 0; t < rsplit; ++t) sm += (double)base[t * pstride + e];
+    H[(int64_t)lidx * ldh + c0 + cc] += scale * sm;
+  }
+  if (tid == 0) counters[strip] = 0u;
 }
 
 // ---------------------------------------------------------------- FP8 block quantisation
@@ -570,12 +604,33 @@ hipError_t gemm1_t(const PassArgs& a, hipStream_t s) {
                      (typename PT<MODE>::acc_t*)a.P1, a.ldp, a.LP, vec_ok(a, sizeof(Src)));
   return hipGetLastError();
 }
+// Launch shape of a^T g: the kernel runs at one wave per SIMD (its accumulators and two-deep
+// operand buffers fill the register file).  Wide matrices get one four-wave workgroup per
+// 64-column strip; narrow ones also split the rows across workgroups so that about half of the
+// chip's 1024 wave slots are busy.
 template <typename Src, int MODE, int NT>
 hipError_t gemm2_t(const PassArgs& a, hipStream_t s) {
-  const dim3 grid(cdiv<int64_t>(a.n, 16 * PT<MODE>::VC));
-  hipLaunchKernelGGL((k_gemm2<Src, MODE, NT>), grid, dim3(WAVES * 64), 0, s, (const Src*)a.A,
+  constexpr int VC = PT<MODE>::VC, KR = 4 * PT<MODE>::V2;
+  constexpr int64_t kSlots = 1024;
+  const int64_t strips = cdiv<int64_t>(a.n, 16 * VC);
+  const int64_t steps = cdiv<int64_t>(a.nrows, KR);            // row super-steps in the block
+  // four waves per workgroup (one workgroup per CU at this register footprint); row splits only
+  // when the strips alone cannot occupy half the chip
+  int nw = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)WAVES, steps));
+  int rsplit = 1;
+  if (strips * nw < kSlots / 2) {
+    rsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)a.rsplit_max,
+                                                           kSlots / (strips * nw),
+                                                           steps / (2 * nw) + 1}));
+  }
+  const int rchunk = (int)rup<int64_t>(cdiv<int64_t>(a.nrows, rsplit), (int64_t)nw * KR);
+  rsplit = (int)cdiv<int64_t>(a.nrows, rchunk);
+  const size_t shm = (size_t)std::max(1, nw - 1) * VC * 4 * 64 * sizeof(typename PT<MODE>::acc_t);
+  const dim3 grid((unsigned)strips, (unsigned)rsplit);
+  hipLaunchKernelGGL((k_gemm2<Src, MODE, NT>), grid, dim3(64 * nw), shm, s, (const Src*)a.A,
                      a.lda, a.nrows, a.n, (const void*)a.Gop, a.ldp, a.LP, a.H, a.ldh, a.fp8_exp,
-                     vec_ok(a, sizeof(Src)));
+                     vec_ok(a, sizeof(Src)), rsplit, rchunk,
+                     (typename PT<MODE>::acc_t*)a.P2, a.counters);
   return hipGetLastError();
 }
 
@@ -620,6 +675,7 @@ enum { S_F64 = 0, S_F32 = 1, S_BF16 = 2, S_FP8 = 4 };
 }  // namespace
 
 int gemm1_row_tile(int) { return ROW_TILE; }
+int64_t gemm2_strips(int64_t n) { return cdiv<int64_t>(n, 32); }   // narrowest strip: 32 columns
 
 hipError_t launch_gemm1(const PassArgs& a, hipStream_t s) { SK_MODE_SWITCH(gemm1_t) }
 hipError_t launch_gemm2(const PassArgs& a, hipStream_t s) { SK_MODE_SWITCH(gemm2_t) }

@@ -70,7 +70,7 @@ int op_size(int mode) {
 struct Layout {
   int LP, NT, t, splits_max;
   int64_t NP, MCAP, RBP, LDST, NQ;
-  int64_t off_ctrl, off_fp8, off_om64, off_omc, off_G, off_H, off_P1, off_Gop, off_stage, off_fp8q,
+  int64_t off_ctrl, off_fp8, off_om64, off_omc, off_G, off_H, off_P1, off_Gop, off_P2, off_cnt, off_stage, off_fp8q,
       off_Q, off_Bt, off_Qb, off_Wn, off_tsqr, off_red, off_small, total;
   int64_t stage_slot_bytes;
   int64_t tsqr_elems, red_elems;
@@ -124,6 +124,8 @@ Layout plan(const sketch_config* c) {
   L.off_H = take((int64_t)L.LP * L.NP * 8);
   L.off_P1 = take((int64_t)L.splits_max * L.LP * L.RBP * gsz);
   L.off_Gop = take((int64_t)L.LP * L.RBP * gsz);
+  L.off_P2 = take(gemm2_strips(c->n) * kGemm2MaxSplits * L.LP * 64 * gsz);
+  L.off_cnt = take(gemm2_strips(c->n) * 4);
   L.off_stage = take(L.stage_slot_bytes * c->host_slots);
   L.off_fp8q = take(c->compute == SKETCH_FP8_E4M3 ? c->max_block_rows * L.NQ : 0);
   L.off_Q = take((int64_t)L.LP * L.MCAP * 8);
@@ -203,6 +205,8 @@ sketch_status start_pass(sketch_t h) {
   hipError_t e = launch_fill_f64(h->at<double>(L.off_H), (int64_t)L.LP * L.NP, 0.0, h->stream);
   if (e == hipSuccess)
     e = launch_fill_u32(reinterpret_cast<uint32_t*>(h->ctrl()), sizeof(Ctrl) / 4, 0u, h->stream);
+  if (e == hipSuccess)
+    e = launch_fill_u32(h->at<uint32_t>(L.off_cnt), gemm2_strips(h->cfg.n), 0u, h->stream);
   if (e != hipSuccess) return h->dev_fail(e, "reset state");
   h->rows = 0;
   if (h->cfg.omega_from_seed) {
@@ -368,6 +372,9 @@ sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtyp
   a.P1 = h->ws + L.off_P1;
   a.ldp = L.RBP;
   a.Gop = h->ws + L.off_Gop;
+  a.P2 = h->ws + L.off_P2;
+  a.counters = h->at<unsigned>(L.off_cnt);
+  a.rsplit_max = kGemm2MaxSplits;
   a.G = h->ws + L.off_G;
   a.ldg = L.MCAP;
   a.g_row0 = h->rows;
