@@ -48,7 +48,9 @@ def parse():
                     help="FP64 reference accuracy check on the whole workload")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-baseline sample (0 = skip)")
-    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (known bytes) to scale HBM "
+                         "counters")
     return ap.parse_args()
 
 
@@ -80,17 +82,15 @@ def bench_mode(mode, A, args, torch, sk):
     for _ in range(args.warmup):
         run_step(obj, A, args.block, 2002)
     torch.cuda.synchronize()
+    # per-kernel durations of the timed steps themselves: the library records HIP events on its
+    # launch stream around each product and around the finalize
+    obj.profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         S, V, _, rank = run_step(obj, A, args.block, 2002)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / max(1, args.steps)
-    # per-kernel HIP-event timing (events on the launch stream around every launch)
-    obj.profile(True)
-    lat = []
-    for _ in range(args.profile_steps):
-        run_step(obj, A, args.block, 2002)
     n1, t_g1 = obj.profile_read(0)
     n2, t_g2 = obj.profile_read(1)
     nf, t_fin = obj.profile_read(2)
@@ -125,8 +125,10 @@ def roofline(res, m, n, l, mode):
     """Dominant streaming kernel against its roof: HBM for the BF16/FP8 paths (algorithmic bytes
     = the block's FP32 bytes, read once per launch), the matrix-core peak for FP32/FP64
     (algorithmic flops = 2 l per element of the block, per launch)."""
-    dom, t = ("g = a Omega", res["gemm1_ms"]) if res["gemm1_ms"] >= res["gemm2_ms"] else \
-        ("H += a^T g", res["gemm2_ms"])
+    dom, t = ("k_gemm1+k_reduce1 (g = a Omega)", res["gemm1_ms"]) \
+        if res["gemm1_ms"] >= res["gemm2_ms"] else ("k_gemm2 (H += a^T g)", res["gemm2_ms"])
+    if not t > 0:
+        return None
     elems_per_launch = m * n / res["nblocks"]
     if mode in ("f32", "f64"):
         ach = 2.0 * l * elems_per_launch / (t * 1e-3) / 1e12
@@ -136,7 +138,8 @@ def roofline(res, m, n, l, mode):
         ach = 4.0 * elems_per_launch / (t * 1e-3) / 1e9
         out = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS)
     out["kernel"] = dom
-    out["traffic"] = traffic_for(dom, mode)
+    out["launch_us"] = t * 1e3
+    out["traffic"] = traffic_for(dom.split()[0], mode)
     return out
 
 
@@ -238,6 +241,15 @@ def main():
         print(f"[bench] mode {mode}: {results[-1]['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
     p50, p99 = block_latency(A, args, torch, sk, args.mode)
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 1073741824 bytes read, 1073741824 bytes written",
+              file=sys.stderr, flush=True)
+        del src, dst
     head = results[0]
     acc, cpu = {}, None
     if args.check == "full" or args.cpu_seconds > 0:
