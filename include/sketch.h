@@ -25,7 +25,7 @@
  *     distinct handles may be used concurrently.
  *   - Any HIP runtime error makes the handle sticky in SKETCH_E_DEVICE; only sketch_destroy is
  *     then valid.  A block holding a NaN or Inf makes it sticky in SKETCH_E_NONFINITE, reported
- *     by the next call that synchronises (sketch_poll, sketch_finalize).
+ *     by sketch_finalize, the first call that waits for the pass.
  */
 #ifndef SKETCH_H
 #define SKETCH_H
