@@ -19,42 +19,59 @@ hipError_t launch_philox_words(uint64_t seed, uint64_t first, int64_t count, uin
                                hipStream_t s);
 
 // ---------------------------------------------------------------- streaming pass (Alg. 4 steps 5-7)
-struct PassArgs {
-  int mode;            // Mode
-  int src;             // sketch_dtype of the rows actually read by the kernels (F64/F32/BF16,
-                       // or FP8 for pre-quantised staging)
-  const void* A;       // nrows x n row-major block
+// One row block of one stream as the streaming kernels see it.  A launch processes a group of such
+// items (one for a single handle; one block each of several streams in a grouped serving launch);
+// every workgroup finds its item by its first-workgroup offsets wg1 / wg2 / wgr.  The launch
+// parameters of an item (split counts, strips) depend only on the item, so a block gives the same
+// bits alone and in any group.
+struct PassItem {
+  const void* A;       // nrows x n row-major block (storage format of the group's src)
   int64_t lda;         // elements
-  int nrows;
   int64_t n;
   const void* omc;     // Omega' operand copy, LP x NP column-major
   int64_t NP;
-  int LP;              // l rounded up to 16
-  int NT;              // LP / 16
   void* P1;            // split partials of g = a Omega: splits x LP x ldp
-  int64_t ldp;
-  void* Gop;           // block-local operand copy of g for a^T g: LP x ldp (FP64 / FP32), or two
-                       // LP x ldp BF16 arrays (hi, lo) in the BF16-operand modes
-  int splits;
+  int64_t ldp;         // row stride of P1 and Gop (>= nrows)
   int64_t kchunk;      // columns per split (multiple of 512)
   void* G;             // G, LP x ldg column-major (FP64 in F64 mode, FP32 otherwise)
   int64_t ldg;
   int64_t g_row0;      // first row of this block in G
+  void* Gop;           // block-local operand copy of g for a^T g: LP x ldp (FP64 / FP32), or two
+                       // LP x ldp BF16 arrays (hi, lo) in the BF16-operand modes
   double* H;           // H, LP x ldh column-major, FP64
   int64_t ldh;
   const int* fp8_exp;  // device exponent e of the block scale 2^e (FP8 mode), else null
   Ctrl* ctrl;
-  void* P2;            // row-split partials of a^T g: strips x rsplit_max x LP x 64 (acc type)
-  unsigned* counters;  // one zero-initialised arrival counter per column strip
-  int rsplit_max;
+  void* P2;            // row-split partials of a^T g: strips x rsplit x LP x strip width
+  unsigned* counters;  // one zero-initialised arrival counter per strip
+  int32_t nrows, vec_ok, splits, row_tiles;
+  int32_t strips, rsplit, rchunk, red_wgs;
+  int32_t wg1, wg2, wgr, pad;   // first workgroup of the item in the g, a^T g and reduce grids
 };
-// Sizes of the row-split scratch of a^T g for a configuration.
-int64_t gemm2_strips(int64_t n);
-constexpr int kGemm2MaxSplits = 8;
-int gemm1_row_tile(int mode);
-hipError_t launch_gemm1(const PassArgs& a, hipStream_t s);
-hipError_t launch_reduce1(const PassArgs& a, hipStream_t s);
-hipError_t launch_gemm2(const PassArgs& a, hipStream_t s);
+struct PassGroup {
+  int mode;            // Mode
+  int src;             // sketch_dtype of the rows read by the kernels (F64/F32/BF16, or FP8 for
+                       // pre-quantised staging); one format per group
+  int LP;              // l rounded up to 16
+  int NT;              // LP / 16
+  int count;           // items
+  PassItem one;        // the item when count == 1 (passed by value)
+  const PassItem* dev; // device copy of the items when count > 1
+  int64_t wg1_total, wg2_total, wgr_total;
+};
+constexpr int kNpAlign = 512;        // n padding: multiple of every k-chunk of g = a Omega
+constexpr int kGemm2MaxSplits = 8;   // most row splits of one strip of a^T g
+// Fills the launch parameters of `it` (nrows, n, A, lda and the pointers set) for a P1 capacity of
+// `splits_max` partials.
+void plan_item(PassItem& it, int mode, int src, int splits_max);
+// Assigns the first-workgroup offsets of `count` planned items and the group's grid sizes.
+void plan_group(PassGroup& g, PassItem* items, int count);
+// Strips of a^T g for n columns in `mode` (sizes the row-split scratch and counters).
+int64_t gemm2_strips(int64_t n, int mode);
+int64_t gemm2_strip_width(int mode);
+hipError_t launch_gemm1(const PassGroup& g, hipStream_t s);
+hipError_t launch_reduce1(const PassGroup& g, hipStream_t s);
+hipError_t launch_gemm2(const PassGroup& g, hipStream_t s);
 // FP8 mode: amax of the block, then a' = e4m3(a 2^e) into `q` (nrows x ldq bytes).
 hipError_t launch_fp8_quantize(const float* A, int64_t lda, int nrows, int64_t n, uint32_t* amax,
                                uint8_t* q, int64_t ldq, int* exp_out, hipStream_t s);

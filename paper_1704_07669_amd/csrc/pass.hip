@@ -43,6 +43,16 @@ constexpr int RSUB = 2;      // 16-row sub-tiles per wave in g = a Omega
 constexpr int WAVES = 4;     // waves per workgroup in both products
 constexpr int ROW_TILE = WAVES * 16 * RSUB;
 
+// The item of workgroup b in a (possibly grouped) grid: the last item whose first workgroup,
+// selected by `first`, is <= b.  Uniform per workgroup.
+__device__ __forceinline__ PassItem item_of(const PassItem& one, const PassItem* __restrict__ grp,
+                                            int count, int b, int32_t PassItem::*first) {
+  if (count == 1) return one;
+  int i = count - 1;
+  while (i > 0 && grp[i].*first > b) --i;
+  return grp[i];
+}
+
 // ---------------------------------------------------------------- operand fragments
 template <int MODE> struct Frag;
 template <> struct Frag<M_F64> { double v[4]; };
@@ -187,25 +197,38 @@ __device__ __forceinline__ void gemm1_step(const Src (&buf)[RS][PT<MODE>::V1], c
   }
 }
 
+// Tiles of an item are (row tile, split) pairs, numbered split-major and spread so that the
+// workgroups of one split, which share one k-chunk of Omega', land on the same XCD (workgroups are
+// dealt to the 8 XCDs round-robin; item offsets are multiples of 8).
 template <typename Src, int MODE, int NT>
-__global__ __launch_bounds__(WAVES * 64) void k_gemm1(
-    const Src* __restrict__ A, int64_t lda, int nrows, int64_t n,
-    const typename PT<MODE>::op_t* __restrict__ omc, int64_t NP, int64_t kchunk,
-    typename PT<MODE>::acc_t* __restrict__ P, int64_t ldp, int LP, int vec_ok) {
+__global__ __launch_bounds__(WAVES * 64) void k_gemm1(const PassItem one,
+                                                      const PassItem* __restrict__ grp, int count) {
   using T = PT<MODE>;
   using op_t = typename T::op_t;
   using acc_t = typename T::acc_t;
   using accv = typename T::accv;
-  constexpr int V = T::V1, KSS = 4 * V, KC = T::KC;
+  constexpr int V = T::V1, KSS = 4 * V, KC = T::KC, LP = NT * 16;
   constexpr int ROW_BYTES = KC * (int)sizeof(op_t) + 16;   // +16 B: conflict-free 16-lane reads
   constexpr int PIECES = KC * (int)sizeof(op_t) / 16;
   __shared__ __attribute__((aligned(16))) uint8_t lds[NT * 16 * ROW_BYTES];
 
+  const PassItem it = item_of(one, grp, count, blockIdx.x, &PassItem::wg1);
+  const int ntile = it.row_tiles * it.splits;
+  const int u = blockIdx.x - it.wg1;
+  const int tile = (u & 7) * ((ntile + 7) >> 3) + (u >> 3);
+  if (tile >= ntile) return;
+  const int split = tile / it.row_tiles, rtile = tile - split * it.row_tiles;
+  const Src* __restrict__ A = reinterpret_cast<const Src*>(it.A);
+  const int64_t lda = it.lda, n = it.n, NP = it.NP, ldp = it.ldp;
+  const int nrows = it.nrows;
+  const op_t* __restrict__ omc = reinterpret_cast<const op_t*>(it.omc);
+  acc_t* __restrict__ P = reinterpret_cast<acc_t*>(it.P1);
+
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
-  const int row0 = blockIdx.x * ROW_TILE + wave * 16 * RSUB;
-  const bool rows_full = vec_ok && (row0 + 16 * RSUB <= nrows);
-  const int64_t k_begin = (int64_t)blockIdx.y * kchunk;
-  const int64_t k_end = min(n, k_begin + kchunk);
+  const int row0 = rtile * ROW_TILE + wave * 16 * RSUB;
+  const bool rows_full = it.vec_ok && (row0 + 16 * RSUB <= nrows);
+  const int64_t k_begin = (int64_t)split * it.kchunk;
+  const int64_t k_end = min(n, k_begin + it.kchunk);
 
   accv acc[RSUB][NT];
 #pragma unroll
@@ -238,7 +261,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(
   }
 
   mfma_drain();
-  const int64_t pbase = (int64_t)blockIdx.y * LP;
+  const int64_t pbase = (int64_t)split * LP;
 #pragma unroll
   for (int rs = 0; rs < RSUB; ++rs)
 #pragma unroll
@@ -254,14 +277,18 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(
 // writes the block-local operand copy read by a^T g: FP64 / FP32 as is, or, in the BF16-operand
 // modes, the pair hi = bf16(g), lo = bf16(g - hi) (two LP x ldp BF16 arrays).
 template <typename acc_t, bool HILO>
-__global__ void k_reduce1(const acc_t* __restrict__ P, int64_t ldp, int splits, int LP, int nrows,
-                          acc_t* __restrict__ G, int64_t ldg, int64_t g_row0, void* __restrict__ gop,
-                          const int* __restrict__ fp8_exp, Ctrl* __restrict__ ctrl) {
-  const acc_t scale = fp8_exp ? (acc_t)ldexp(1.0, -(*fp8_exp) - 5) : (acc_t)1;
+__global__ void k_reduce1(const PassItem one, const PassItem* __restrict__ grp, int count, int LP) {
+  const PassItem it = item_of(one, grp, count, blockIdx.x, &PassItem::wgr);
+  const acc_t* __restrict__ P = reinterpret_cast<const acc_t*>(it.P1);
+  acc_t* __restrict__ G = reinterpret_cast<acc_t*>(it.G);
+  void* __restrict__ gop = it.Gop;
+  const int64_t ldp = it.ldp, ldg = it.ldg, g_row0 = it.g_row0;
+  const int splits = it.splits, nrows = it.nrows;
+  const acc_t scale = it.fp8_exp ? (acc_t)ldexp(1.0, -(*it.fp8_exp) - 5) : (acc_t)1;
   const int64_t total = (int64_t)LP * nrows;
   bool bad = false;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = (int64_t)(blockIdx.x - it.wgr) * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)it.red_wgs * blockDim.x) {
     const int c = (int)(q / nrows);
     const int r = (int)(q - (int64_t)c * nrows);
     acc_t s = 0;
@@ -279,7 +306,7 @@ __global__ void k_reduce1(const acc_t* __restrict__ P, int64_t ldp, int splits, 
       reinterpret_cast<acc_t*>(gop)[(int64_t)c * ldp + r] = s;
     }
   }
-  if (bad) ctrl->nonfinite = 1;
+  if (bad) it.ctrl->nonfinite = 1;
 }
 
 // ---------------------------------------------------------------- H += a^T g
@@ -431,23 +458,30 @@ __device__ __forceinline__ void gemm2_step(const Src (&a)[PT<MODE>::V2][PT<MODE>
 // super-steps of 4*V2 rows (loads issued one super-step ahead); their partial sums are added in
 // wave order through LDS and the FP64 sum is added into the workgroup's own rows of H.
 template <typename Src, int MODE, int NT>
-__global__ __launch_bounds__(WAVES * 64) void k_gemm2(
-    const Src* __restrict__ A, int64_t lda, int nrows, int64_t n, const void* __restrict__ gop,
-    int64_t ldp, int LP, double* __restrict__ H, int64_t ldh, const int* __restrict__ fp8_exp,
-    int vec_ok, int rsplit, int rchunk, typename PT<MODE>::acc_t* __restrict__ part,
-    unsigned* __restrict__ counters) {
+__global__ __launch_bounds__(WAVES * 64) void k_gemm2(const PassItem one,
+                                                      const PassItem* __restrict__ grp, int count) {
   using T = PT<MODE>;
   using acc_t = typename T::acc_t;
   using accv = typename T::accv;
-  constexpr int V2 = T::V2, VC = T::VC, KR = 4 * V2;
-  extern __shared__ __attribute__((aligned(16))) uint8_t red_raw[];   // (nwaves-1) x VC x 4 x 64
-  acc_t* red = reinterpret_cast<acc_t*>(red_raw);
-  const int nwaves = blockDim.x >> 6;
+  constexpr int V2 = T::V2, VC = T::VC, KR = 4 * V2, LP = NT * 16;
+  __shared__ acc_t red[(WAVES - 1) * VC * 4 * 64];
+
+  const PassItem it = item_of(one, grp, count, blockIdx.x, &PassItem::wg2);
+  const int tile = blockIdx.x - it.wg2;
+  const int64_t strip = tile % it.strips;
+  const int rs = tile / it.strips, rsplit = it.rsplit;
+  const Src* __restrict__ A = reinterpret_cast<const Src*>(it.A);
+  const void* __restrict__ gop = it.Gop;
+  const int64_t lda = it.lda, n = it.n, ldp = it.ldp, ldh = it.ldh;
+  double* __restrict__ H = it.H;
+  acc_t* __restrict__ part = reinterpret_cast<acc_t*>(it.P2);
+  unsigned* __restrict__ counters = it.counters;
+  int nrows = it.nrows;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
-  const int64_t c0 = (int64_t)blockIdx.x * 16 * VC;
+  const int64_t c0 = strip * 16 * VC;
   const int64_t col = c0 + VC * r16;
-  const bool cols_full = vec_ok && (c0 + 16 * VC <= n);
+  const bool cols_full = it.vec_ok && (c0 + 16 * VC <= n);
 
   accv acc[NT][VC];
 #pragma unroll
@@ -455,14 +489,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
 #pragma unroll
     for (int j = 0; j < VC; ++j) acc[mt][j] = accv{0, 0, 0, 0};
 
-  // this workgroup's row range (blockIdx.y of rsplit), rows relative to the block
-  const int row_lo = blockIdx.y * rchunk;
-  const int row_hi = min(nrows, row_lo + rchunk);
+  // this workgroup's row range (split rs of rsplit), rows relative to the block
+  const int row_lo = rs * it.rchunk;
+  const int row_hi = min(nrows, row_lo + it.rchunk);
 
   // A and G of the next super-step are fetched before the matrix-core work of the current one
   Src a0[V2][VC], a1[V2][VC];
   GFrag<MODE> g0[NT], g1[NT];
-  const int STRIDE = nwaves * KR;
+  constexpr int STRIDE = WAVES * KR;
   int kr = row_lo + wave * KR;
   nrows = row_hi;
   if (kr < nrows) {
@@ -484,13 +518,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
   }
 
   mfma_drain();
-  const double scale = fp8_exp ? ldexp(1.0, -(*fp8_exp)) : 1.0;
+  const double scale = it.fp8_exp ? ldexp(1.0, -(*it.fp8_exp)) : 1.0;
   // Row-split partials: every workgroup of a strip writes its (wave-ordered) FP32 sum; the last
   // one to finish, found with a per-strip counter, adds the rsplit partials in split order into
   // the FP64 rows of H and resets the counter.  No workgroup waits on another.
-  const int64_t strip = blockIdx.x;
   const int64_t pstride = (int64_t)LP * 16 * VC;          // one partial tile
-  acc_t* mine = part + (strip * rsplit + blockIdx.y) * pstride;
+  acc_t* mine = part + (strip * rsplit + rs) * pstride;
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
     __syncthreads();
@@ -507,7 +540,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           acc_t sm = acc[mt][j][i];
-          for (int w = 1; w < nwaves; ++w) sm += red[(((w - 1) * VC + j) * 4 + i) * 64 + lane];
+#pragma unroll
+          for (int w = 1; w < WAVES; ++w) sm += red[(((w - 1) * VC + j) * 4 + i) * 64 + lane];
           const int lidx = mt * 16 + acc_row<acc_t>(g, i);
           if (rsplit == 1) {
             if (col + j < n) H[(int64_t)lidx * ldh + col + j] += scale * (double)sm;
@@ -586,51 +620,17 @@ __global__ void k_quant_fp8(const float* __restrict__ A, int64_t lda, int nrows,
   }
 }
 
-inline int grid_for(int64_t work, int block = 256, int cap = 65536) {
-  int64_t g = cdiv<int64_t>(work, block);
-  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
-}
-
 // ---------------------------------------------------------------- dispatch
-inline int vec_ok(const PassArgs& a, int es) {
-  return (((uintptr_t)a.A) % 16 == 0) && ((a.lda * es) % 16 == 0);
-}
-
 template <typename Src, int MODE, int NT>
-hipError_t gemm1_t(const PassArgs& a, hipStream_t s) {
-  const dim3 grid(cdiv<int64_t>(a.nrows, ROW_TILE), a.splits);
-  hipLaunchKernelGGL((k_gemm1<Src, MODE, NT>), grid, dim3(WAVES * 64), 0, s, (const Src*)a.A,
-                     a.lda, a.nrows, a.n, (const typename PT<MODE>::op_t*)a.omc, a.NP, a.kchunk,
-                     (typename PT<MODE>::acc_t*)a.P1, a.ldp, a.LP, vec_ok(a, sizeof(Src)));
+hipError_t gemm1_t(const PassGroup& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm1<Src, MODE, NT>), dim3((unsigned)a.wg1_total), dim3(WAVES * 64), 0, s,
+                     a.one, a.dev, a.count);
   return hipGetLastError();
 }
-// Launch shape of a^T g: the kernel runs at one wave per SIMD (its accumulators and two-deep
-// operand buffers fill the register file).  Wide matrices get one four-wave workgroup per
-// 64-column strip; narrow ones also split the rows across workgroups so that about half of the
-// chip's 1024 wave slots are busy.
 template <typename Src, int MODE, int NT>
-hipError_t gemm2_t(const PassArgs& a, hipStream_t s) {
-  constexpr int VC = PT<MODE>::VC, KR = 4 * PT<MODE>::V2;
-  constexpr int64_t kSlots = 1024;
-  const int64_t strips = cdiv<int64_t>(a.n, 16 * VC);
-  const int64_t steps = cdiv<int64_t>(a.nrows, KR);            // row super-steps in the block
-  // four waves per workgroup (one workgroup per CU at this register footprint); row splits only
-  // when the strips alone cannot occupy half the chip
-  int nw = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)WAVES, steps));
-  int rsplit = 1;
-  if (strips * nw < kSlots / 2) {
-    rsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)a.rsplit_max,
-                                                           kSlots / (strips * nw),
-                                                           steps / (2 * nw) + 1}));
-  }
-  const int rchunk = (int)rup<int64_t>(cdiv<int64_t>(a.nrows, rsplit), (int64_t)nw * KR);
-  rsplit = (int)cdiv<int64_t>(a.nrows, rchunk);
-  const size_t shm = (size_t)std::max(1, nw - 1) * VC * 4 * 64 * sizeof(typename PT<MODE>::acc_t);
-  const dim3 grid((unsigned)strips, (unsigned)rsplit);
-  hipLaunchKernelGGL((k_gemm2<Src, MODE, NT>), grid, dim3(64 * nw), shm, s, (const Src*)a.A,
-                     a.lda, a.nrows, a.n, (const void*)a.Gop, a.ldp, a.LP, a.H, a.ldh, a.fp8_exp,
-                     vec_ok(a, sizeof(Src)), rsplit, rchunk,
-                     (typename PT<MODE>::acc_t*)a.P2, a.counters);
+hipError_t gemm2_t(const PassGroup& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm2<Src, MODE, NT>), dim3((unsigned)a.wg2_total), dim3(WAVES * 64), 0, s,
+                     a.one, a.dev, a.count);
   return hipGetLastError();
 }
 
@@ -672,31 +672,92 @@ enum { S_F64 = 0, S_F32 = 1, S_BF16 = 2, S_FP8 = 4 };
   }                                                                             \
   return hipErrorInvalidValue;
 
+// Per-mode tile shape of a^T g: columns per lane (VC) and rows per lane per step (V2).
+struct G2Shape { int VC, V2; };
+G2Shape g2_shape(int mode) {
+  switch (mode) {
+    case M_F64: return {PT<M_F64>::VC, PT<M_F64>::V2};
+    case M_F32: return {PT<M_F32>::VC, PT<M_F32>::V2};
+    case M_FP8: return {PT<M_FP8>::VC, PT<M_FP8>::V2};
+    default: return {PT<M_BF16>::VC, PT<M_BF16>::V2};
+  }
+}
+int src_bytes(int src) { return src == S_F64 ? 8 : src == S_F32 ? 4 : src == S_BF16 ? 2 : 1; }
+
 }  // namespace
 
-int gemm1_row_tile(int) { return ROW_TILE; }
-int64_t gemm2_strips(int64_t n) { return cdiv<int64_t>(n, 32); }   // narrowest strip: 32 columns
+int64_t gemm2_strip_width(int mode) { return 16 * g2_shape(mode).VC; }
+int64_t gemm2_strips(int64_t n, int mode) { return cdiv<int64_t>(n, gemm2_strip_width(mode)); }
 
-hipError_t launch_gemm1(const PassArgs& a, hipStream_t s) { SK_MODE_SWITCH(gemm1_t) }
-hipError_t launch_gemm2(const PassArgs& a, hipStream_t s) { SK_MODE_SWITCH(gemm2_t) }
+// Launch shape of one item.
+//   g = a Omega: row tiles of 128 rows times k splits, enough splits for about 512 workgroups
+//     (two per CU), each split a multiple of 512 columns.
+//   a^T g: one four-wave workgroup per strip of 16 VC columns; narrow matrices also split the
+//     rows across workgroups so that about half of the chip's 1024 wave slots are busy.
+void plan_item(PassItem& it, int mode, int src, int splits_max) {
+  const int es = src_bytes(src);
+  it.vec_ok = ((((uintptr_t)it.A) % 16) == 0) && ((it.lda * es) % 16 == 0);
+  it.row_tiles = (int)cdiv<int64_t>(it.nrows, ROW_TILE);
+  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(splits_max, cdiv<int64_t>(512, it.row_tiles)));
+  it.kchunk = rup<int64_t>(cdiv<int64_t>(it.n, splits), kNpAlign);
+  it.splits = (int)cdiv<int64_t>(it.n, it.kchunk);
+  const G2Shape sh = g2_shape(mode);
+  const int KR = 4 * sh.V2;
+  constexpr int64_t kSlots = 1024;
+  const int64_t strips = cdiv<int64_t>(it.n, 16 * sh.VC);
+  const int64_t steps = cdiv<int64_t>(it.nrows, KR);
+  int rsplit = 1;
+  if (strips * WAVES < kSlots / 2) {
+    rsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kGemm2MaxSplits,
+                                                           kSlots / (strips * WAVES),
+                                                           steps / (2 * WAVES) + 1}));
+  }
+  it.rchunk = (int)rup<int64_t>(cdiv<int64_t>(it.nrows, rsplit), (int64_t)WAVES * KR);
+  it.rsplit = (int)cdiv<int64_t>(it.nrows, it.rchunk);
+  it.strips = (int)strips;
+}
 
-hipError_t launch_reduce1(const PassArgs& a, hipStream_t s) {
-  const dim3 grid(grid_for((int64_t)a.LP * a.nrows)), block(256);
+void plan_group(PassGroup& g, PassItem* items, int count) {
+  int64_t w1 = 0, w2 = 0, wr = 0;
+  for (int i = 0; i < count; ++i) {
+    PassItem& it = items[i];
+    it.red_wgs = (int)std::max<int64_t>(1, std::min<int64_t>(4096, cdiv<int64_t>((int64_t)g.LP * it.nrows, 256)));
+    it.wg1 = (int)w1;
+    it.wg2 = (int)w2;
+    it.wgr = (int)wr;
+    w1 += rup<int64_t>((int64_t)it.row_tiles * it.splits, 8);
+    w2 += (int64_t)it.strips * it.rsplit;
+    wr += it.red_wgs;
+  }
+  g.count = count;
+  g.wg1_total = w1;
+  g.wg2_total = w2;
+  g.wgr_total = wr;
+  if (count == 1) g.one = items[0];
+}
+
+hipError_t launch_gemm1(const PassGroup& a, hipStream_t s) { SK_MODE_SWITCH(gemm1_t) }
+hipError_t launch_gemm2(const PassGroup& a, hipStream_t s) { SK_MODE_SWITCH(gemm2_t) }
+
+hipError_t launch_reduce1(const PassGroup& a, hipStream_t s) {
+  const dim3 grid((unsigned)a.wgr_total), block(256);
   if (a.mode == M_F64) {
-    hipLaunchKernelGGL((k_reduce1<double, false>), grid, block, 0, s, (const double*)a.P1, a.ldp,
-                       a.splits, a.LP, a.nrows, (double*)a.G, a.ldg, a.g_row0, a.Gop, a.fp8_exp,
-                       a.ctrl);
+    hipLaunchKernelGGL((k_reduce1<double, false>), grid, block, 0, s, a.one, a.dev, a.count, a.LP);
   } else if (a.mode == M_F32) {
-    hipLaunchKernelGGL((k_reduce1<float, false>), grid, block, 0, s, (const float*)a.P1, a.ldp,
-                       a.splits, a.LP, a.nrows, (float*)a.G, a.ldg, a.g_row0, a.Gop, a.fp8_exp,
-                       a.ctrl);
+    hipLaunchKernelGGL((k_reduce1<float, false>), grid, block, 0, s, a.one, a.dev, a.count, a.LP);
   } else {
-    hipLaunchKernelGGL((k_reduce1<float, true>), grid, block, 0, s, (const float*)a.P1, a.ldp,
-                       a.splits, a.LP, a.nrows, (float*)a.G, a.ldg, a.g_row0, a.Gop, a.fp8_exp,
-                       a.ctrl);
+    hipLaunchKernelGGL((k_reduce1<float, true>), grid, block, 0, s, a.one, a.dev, a.count, a.LP);
   }
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------- FP8 quantisation launcher
+namespace {
+inline int grid_for(int64_t work, int block = 256, int cap = 65536) {
+  int64_t g = cdiv<int64_t>(work, block);
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+}  // namespace
 
 hipError_t launch_fp8_quantize(const float* A, int64_t lda, int nrows, int64_t n, uint32_t* amax,
                                uint8_t* q, int64_t ldq, int* exp_out, hipStream_t s) {

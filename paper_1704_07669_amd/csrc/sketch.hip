@@ -34,7 +34,6 @@ sketch_status fail(sketch_status st, const char* fmt, ...) {
 
 constexpr int kRing = 16;          // per-ticket completion events
 constexpr int64_t kAlign = 256;    // workspace carve alignment (bytes)
-constexpr int kNpAlign = 512;      // n padding: multiple of every k-chunk of g = a Omega
 constexpr int kMaxSplits = 64;
 
 int src_size(int dt) {
@@ -124,8 +123,9 @@ Layout plan(const sketch_config* c) {
   L.off_H = take((int64_t)L.LP * L.NP * 8);
   L.off_P1 = take((int64_t)L.splits_max * L.LP * L.RBP * gsz);
   L.off_Gop = take((int64_t)L.LP * L.RBP * gsz);
-  L.off_P2 = take(gemm2_strips(c->n) * kGemm2MaxSplits * L.LP * 64 * gsz);
-  L.off_cnt = take(gemm2_strips(c->n) * 4);
+  L.off_P2 = take(gemm2_strips(c->n, c->compute) * kGemm2MaxSplits * L.LP *
+                  gemm2_strip_width(c->compute) * gsz);
+  L.off_cnt = take(gemm2_strips(c->n, c->compute) * 4);
   L.off_stage = take(L.stage_slot_bytes * c->host_slots);
   L.off_fp8q = take(c->compute == SKETCH_FP8_E4M3 ? c->max_block_rows * L.NQ : 0);
   L.off_Q = take((int64_t)L.LP * L.MCAP * 8);
@@ -206,7 +206,8 @@ sketch_status start_pass(sketch_t h) {
   if (e == hipSuccess)
     e = launch_fill_u32(reinterpret_cast<uint32_t*>(h->ctrl()), sizeof(Ctrl) / 4, 0u, h->stream);
   if (e == hipSuccess)
-    e = launch_fill_u32(h->at<uint32_t>(L.off_cnt), gemm2_strips(h->cfg.n), 0u, h->stream);
+    e = launch_fill_u32(h->at<uint32_t>(L.off_cnt), gemm2_strips(h->cfg.n, h->cfg.compute), 0u,
+                        h->stream);
   if (e != hipSuccess) return h->dev_fail(e, "reset state");
   h->rows = 0;
   if (h->cfg.omega_from_seed) {
@@ -358,46 +359,44 @@ sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtyp
     lda = L.LDST;
   }
 
-  PassArgs a{};
-  a.mode = c.compute;
-  a.src = src_dtype;
-  a.A = A;
-  a.lda = lda;
-  a.nrows = (int)nrows;
-  a.n = c.n;
-  a.omc = h->ws + L.off_omc;
-  a.NP = L.NP;
-  a.LP = L.LP;
-  a.NT = L.NT;
-  a.P1 = h->ws + L.off_P1;
-  a.ldp = L.RBP;
-  a.Gop = h->ws + L.off_Gop;
-  a.P2 = h->ws + L.off_P2;
-  a.counters = h->at<unsigned>(L.off_cnt);
-  a.rsplit_max = kGemm2MaxSplits;
-  a.G = h->ws + L.off_G;
-  a.ldg = L.MCAP;
-  a.g_row0 = h->rows;
-  a.H = h->at<double>(L.off_H);
-  a.ldh = L.NP;
-  a.fp8_exp = nullptr;
-  a.ctrl = h->ctrl();
+  PassItem it{};
+  it.A = A;
+  it.lda = lda;
+  it.nrows = (int)nrows;
+  it.n = c.n;
+  it.omc = h->ws + L.off_omc;
+  it.NP = L.NP;
+  it.P1 = h->ws + L.off_P1;
+  it.ldp = L.RBP;
+  it.Gop = h->ws + L.off_Gop;
+  it.P2 = h->ws + L.off_P2;
+  it.counters = h->at<unsigned>(L.off_cnt);
+  it.G = h->ws + L.off_G;
+  it.ldg = L.MCAP;
+  it.g_row0 = h->rows;
+  it.H = h->at<double>(L.off_H);
+  it.ldh = L.NP;
+  it.fp8_exp = nullptr;
+  it.ctrl = h->ctrl();
+  int src = src_dtype;
   if (c.compute == SKETCH_FP8_E4M3) {
     uint32_t* amax = h->at<uint32_t>(L.off_fp8);
     int* ex = reinterpret_cast<int*>(amax + 4);
     uint8_t* q = h->ws + L.off_fp8q;
     e = launch_fp8_quantize((const float*)A, lda, (int)nrows, c.n, amax, q, L.NQ, ex, h->stream);
     if (e != hipSuccess) return h->dev_fail(e, "fp8 quantize");
-    a.A = q;
-    a.lda = L.NQ;
-    a.src = 4;
-    a.fp8_exp = ex;
+    it.A = q;
+    it.lda = L.NQ;
+    src = SKETCH_FP8_E4M3;
+    it.fp8_exp = ex;
   }
-  // k splits of g = a Omega: enough workgroups to fill the chip
-  const int64_t row_tiles = cdiv<int64_t>(nrows, gemm1_row_tile(c.compute));
-  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(L.splits_max, cdiv<int64_t>(512, row_tiles)));
-  a.kchunk = rup<int64_t>(cdiv<int64_t>(c.n, splits), kNpAlign);
-  a.splits = (int)cdiv<int64_t>(c.n, a.kchunk);
+  plan_item(it, c.compute, src, L.splits_max);
+  PassGroup a{};
+  a.mode = c.compute;
+  a.src = src;
+  a.LP = L.LP;
+  a.NT = L.NT;
+  plan_group(a, &it, 1);
 
   sketch_s::Rec rec{};
   if (h->prof) {
