@@ -163,6 +163,94 @@ sketch_status sketch_destroy(sketch_t h);
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* sketch_last_error(void);
 
+/* ================================================================ serving
+ * Many concurrent single-pass PCA streams on one GPU.  Each stream is one instance of Algorithm 4
+ * (its Omega seed, G, H resident in device memory); the server admits streams while their state
+ * fits a device-memory budget (later ones wait in FIFO order and are admitted as finalized
+ * streams release their memory), and runs continuous batching: a scheduler gathers one pending
+ * row block from each of up to max_group streams, of any widths n, and processes them with one
+ * grouped launch of each streaming product (g = a Omega, its split reduction, H = H + a^T g;
+ * Alg. 4 steps 5-7, Eq. 10).  Blocks that arrive while a group runs join the next group.  Every
+ * block is planned from its own shape only, so a stream's results are bitwise the same alone and
+ * in any mix.  The column-block loop and SVD (Alg. 4 steps 9-19) run per stream in
+ * sketch_server_finalize on a second stream, overlapping the other streams' ingestion.
+ *
+ * Rows are device pointers (row-major, ld >= n) in the server's source format; the caller keeps a
+ * block unchanged until sketch_server_poll reports its ticket.  The server owns one scheduler
+ * thread (worker = 1) or is driven by sketch_server_step (worker = 0), one finalize stream and
+ * its events; all device memory is the caller's workspace.  Calls are thread-safe. */
+typedef struct sketch_server_s* sketch_server_t;
+
+typedef struct {
+  int32_t compute;         /* sketch_dtype: F64, F32, BF16 or BF16X2 */
+  int32_t src;             /* format of every submitted block: F32 (F64 or F32 with compute F64;
+                              F32 or BF16 with compute BF16) */
+  int32_t l;               /* sketch width of every stream, 1..128 */
+  int32_t max_group;       /* most blocks in one grouped launch, 1..64 */
+  int64_t max_n;           /* widest stream (>= l) */
+  int64_t max_m;           /* most rows of one stream */
+  int64_t max_block_rows;  /* largest block */
+  int64_t state_bytes;     /* device memory for resident stream states (the admission budget) */
+  int32_t worker;          /* 1: a library thread schedules; 0: the caller calls sketch_server_step */
+  int32_t pad;
+} sketch_server_config;
+
+typedef struct {
+  int64_t active;          /* streams resident on the device */
+  int64_t queued;          /* streams waiting for memory */
+  int64_t state_used;      /* bytes of the state budget in use */
+  int64_t state_peak;      /* most bytes ever in use */
+  int64_t groups;          /* grouped launches issued */
+  int64_t blocks;          /* blocks processed */
+  int64_t max_blocks_in_group;
+  int64_t finalized;       /* streams finalized */
+} sketch_server_stats;
+
+/* Device bytes the server's workspace must hold (shared scratch + state budget); 0 if invalid. */
+size_t sketch_server_workspace_size(const sketch_server_config* cfg);
+
+/* Device bytes of one stream's resident state (what admission charges against state_bytes);
+ * cfg->l and cfg->compute must match the server's; 0 if invalid. */
+size_t sketch_server_stream_bytes(const sketch_server_config* srv, const sketch_config* cfg);
+
+/* Creates a server in `dev_ws` (device pointer, 256-byte aligned, >= workspace size, owned by the
+ * caller until sketch_server_destroy); grouped launches run on `hip_stream`. */
+sketch_status sketch_server_create(sketch_server_t* out, const sketch_server_config* cfg,
+                                   void* dev_ws, size_t ws_bytes, void* hip_stream);
+
+/* Opens a stream (cfg: n <= max_n, m_capacity <= max_m, max_block_rows <= the server's,
+ * l and compute equal to the server's, omega_from_seed = 1, host_slots = 0).  *admitted = 1 if its
+ * state was placed at once, 0 if it waits for memory (blocks may be submitted meanwhile).
+ * E_CAPACITY if the stream alone exceeds the state budget. */
+sketch_status sketch_server_open(sketch_server_t s, const sketch_config* cfg, uint64_t* stream_id,
+                                 int32_t* admitted);
+
+/* Queues the next nrows rows of a stream (device pointer, src format, ld >= n).  *ticket
+ * identifies the block in sketch_server_poll.  E_STATE after the stream's finalize began;
+ * E_CAPACITY past its m_capacity or max_block_rows. */
+sketch_status sketch_server_submit(sketch_server_t s, uint64_t stream_id, const void* rows,
+                                   int64_t nrows, int64_t ld, uint64_t* ticket);
+
+/* One scheduler round (worker = 0 only; with a worker it returns E_STATE): retire finished
+ * groups, admit waiting streams, launch at most one new group.  *launched = blocks launched. */
+sketch_status sketch_server_step(sketch_server_t s, int32_t* launched);
+
+/* Up to `cap` finished blocks since the last call: their tickets and latencies in seconds (from
+ * submit to the host seeing the group's completion).  *count = entries written. */
+sketch_status sketch_server_poll(sketch_server_t s, uint64_t* tickets, double* latency_s,
+                                 int32_t cap, int32_t* count);
+
+/* Waits for the stream's blocks, runs Alg. 4 steps 9-19 for it (outputs as sketch_finalize:
+ * device S (k), V (n x k, ldv), U (m x k, ldu) or NULL), then releases its state.  Blocks. */
+sketch_status sketch_server_finalize(sketch_server_t s, uint64_t stream_id, double* S_dev,
+                                     double* U_dev, int64_t ldu, double* V_dev, int64_t ldv,
+                                     int32_t* rank_out);
+
+sketch_status sketch_server_get_stats(sketch_server_t s, sketch_server_stats* out);
+
+/* Stops the scheduler, waits for outstanding work and releases host resources. */
+sketch_status sketch_server_destroy(sketch_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

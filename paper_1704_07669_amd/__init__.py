@@ -25,6 +25,9 @@ EXPORTED = [
     "sketch_ingest_block", "sketch_poll", "sketch_finalize", "sketch_get_omega",
     "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
     "sketch_destroy", "sketch_last_error",
+    "sketch_server_workspace_size", "sketch_server_stream_bytes", "sketch_server_create",
+    "sketch_server_open", "sketch_server_submit", "sketch_server_step", "sketch_server_poll",
+    "sketch_server_finalize", "sketch_server_get_stats", "sketch_server_destroy",
 ]
 
 
@@ -41,6 +44,21 @@ class sketch_config(ctypes.Structure):
         ("compute", ctypes.c_int32), ("host_slots", ctypes.c_int32), ("host_src", ctypes.c_int32),
         ("want_u", ctypes.c_int32), ("omega_from_seed", ctypes.c_int32), ("seed", ctypes.c_uint64),
     ]
+
+
+class sketch_server_config(ctypes.Structure):
+    _fields_ = [
+        ("compute", ctypes.c_int32), ("src", ctypes.c_int32), ("l", ctypes.c_int32),
+        ("max_group", ctypes.c_int32), ("max_n", ctypes.c_int64), ("max_m", ctypes.c_int64),
+        ("max_block_rows", ctypes.c_int64), ("state_bytes", ctypes.c_int64),
+        ("worker", ctypes.c_int32), ("pad", ctypes.c_int32),
+    ]
+
+
+class sketch_server_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "active", "queued", "state_used", "state_peak", "groups", "blocks", "max_blocks_in_group",
+        "finalized")]
 
 
 _lib = None
@@ -62,6 +80,7 @@ def load_library(path=None):
     P, I32, I64, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                            ctypes.c_double)
     cfgp = ctypes.POINTER(sketch_config)
+    scfgp = ctypes.POINTER(sketch_server_config)
     sig = {
         "sketch_workspace_size": (ctypes.c_size_t, [cfgp]),
         "sketch_init": (I32, [ctypes.POINTER(P), cfgp, P, ctypes.c_size_t, P]),
@@ -77,6 +96,17 @@ def load_library(path=None):
         "sketch_profile_read": (I32, [P, I32, ctypes.POINTER(I64), ctypes.POINTER(D)]),
         "sketch_destroy": (I32, [P]),
         "sketch_last_error": (ctypes.c_char_p, []),
+        "sketch_server_workspace_size": (ctypes.c_size_t, [scfgp]),
+        "sketch_server_stream_bytes": (ctypes.c_size_t, [scfgp, cfgp]),
+        "sketch_server_create": (I32, [ctypes.POINTER(P), scfgp, P, ctypes.c_size_t, P]),
+        "sketch_server_open": (I32, [P, cfgp, ctypes.POINTER(U64), ctypes.POINTER(I32)]),
+        "sketch_server_submit": (I32, [P, U64, P, I64, I64, ctypes.POINTER(U64)]),
+        "sketch_server_step": (I32, [P, ctypes.POINTER(I32)]),
+        "sketch_server_poll": (I32, [P, ctypes.POINTER(U64), ctypes.POINTER(D), I32,
+                                     ctypes.POINTER(I32)]),
+        "sketch_server_finalize": (I32, [P, U64, P, P, I64, P, I64, ctypes.POINTER(I32)]),
+        "sketch_server_get_stats": (I32, [P, ctypes.POINTER(sketch_server_stats)]),
+        "sketch_server_destroy": (I32, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -266,6 +296,151 @@ class Sketch:
     def close(self):
         if not self.closed:
             sketch_destroy(self.h)
+            self.closed = True
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving
+def sketch_server_workspace_size(scfg):
+    lib = load_library()
+    n = lib.sketch_server_workspace_size(ctypes.byref(scfg))
+    if n == 0:
+        raise SketchError(1, lib.sketch_last_error().decode())
+    return int(n)
+
+
+def sketch_server_stream_bytes(scfg, cfg):
+    lib = load_library()
+    n = lib.sketch_server_stream_bytes(ctypes.byref(scfg), ctypes.byref(cfg))
+    if n == 0:
+        raise SketchError(1, lib.sketch_last_error().decode())
+    return int(n)
+
+
+def sketch_server_create(scfg, workspace, stream=None):
+    lib = load_library()
+    h = ctypes.c_void_p()
+    _check(lib.sketch_server_create(ctypes.byref(h), ctypes.byref(scfg), _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(),
+                                    _stream_handle(stream)))
+    return h
+
+
+def sketch_server_open(srv, cfg):
+    sid, adm = ctypes.c_uint64(), ctypes.c_int32()
+    _check(load_library().sketch_server_open(srv, ctypes.byref(cfg), ctypes.byref(sid),
+                                             ctypes.byref(adm)))
+    return sid.value, bool(adm.value)
+
+
+def sketch_server_submit(srv, sid, rows):
+    tk = ctypes.c_uint64()
+    _check(load_library().sketch_server_submit(srv, sid, _ptr(rows), rows.shape[0],
+                                               rows.stride(0), ctypes.byref(tk)))
+    return tk.value
+
+
+def sketch_server_step(srv):
+    n = ctypes.c_int32()
+    _check(load_library().sketch_server_step(srv, ctypes.byref(n)))
+    return n.value
+
+
+def sketch_server_poll(srv, cap=4096):
+    tks = (ctypes.c_uint64 * cap)()
+    lat = (ctypes.c_double * cap)()
+    n = ctypes.c_int32()
+    _check(load_library().sketch_server_poll(srv, tks, lat, cap, ctypes.byref(n)))
+    return [(tks[i], lat[i]) for i in range(n.value)]
+
+
+def sketch_server_finalize(srv, sid, S, U, V):
+    r = ctypes.c_int32()
+    _check(load_library().sketch_server_finalize(srv, sid, _ptr(S), _ptr(U),
+                                                 0 if U is None else U.stride(0), _ptr(V),
+                                                 V.stride(0), ctypes.byref(r)))
+    return r.value
+
+
+def sketch_server_get_stats(srv):
+    st = sketch_server_stats()
+    _check(load_library().sketch_server_get_stats(srv, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in sketch_server_stats._fields_}
+
+
+def sketch_server_destroy(srv):
+    _check(load_library().sketch_server_destroy(srv))
+
+
+class Server:
+    """Continuous-batching server of many single-pass PCA streams on the current device.
+
+    ``state_bytes`` is the device-memory budget for resident stream states (admission control);
+    the workspace (group scratch, finalize scratch and that budget) is one torch allocation."""
+
+    def __init__(self, l, max_n, max_m, max_block_rows, state_bytes, compute="f32", src="f32",
+                 max_group=16, worker=True, stream=None):
+        import torch
+        load_library()
+        self.cfg = sketch_server_config(
+            compute=DTYPES[compute], src=DTYPES[src], l=l, max_group=max_group, max_n=max_n,
+            max_m=max_m, max_block_rows=max_block_rows, state_bytes=state_bytes,
+            worker=int(bool(worker)), pad=0)
+        self.l, self.compute, self.src = l, compute, src
+        ws = sketch_server_workspace_size(self.cfg)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device="cuda")
+        self.h = sketch_server_create(self.cfg, self.workspace, stream)
+        self.meta = {}
+        self.closed = False
+
+    def stream_config(self, n, m, k, b, seed, max_block_rows=None, want_u=False):
+        return sketch_config(n=n, m_capacity=m, max_block_rows=max_block_rows or
+                             self.cfg.max_block_rows, k=k, l=self.l, b=b,
+                             compute=self.cfg.compute, host_slots=0, host_src=self.cfg.src,
+                             want_u=int(bool(want_u)), omega_from_seed=1, seed=seed)
+
+    def stream_bytes(self, n, m, k, b, seed=0):
+        return sketch_server_stream_bytes(self.cfg, self.stream_config(n, m, k, b, seed))
+
+    def open(self, n, m, k, b, seed, want_u=False, max_block_rows=None):
+        cfg = self.stream_config(n, m, k, b, seed, max_block_rows, want_u)
+        sid, admitted = sketch_server_open(self.h, cfg)
+        self.meta[sid] = cfg
+        return sid, admitted
+
+    def submit(self, sid, rows):
+        if rows.dim() != 2 or rows.stride(1) != 1 or not rows.is_cuda:
+            raise ValueError("rows must be a row-major 2-D CUDA tensor")
+        return sketch_server_submit(self.h, sid, rows)
+
+    def step(self):
+        return sketch_server_step(self.h)
+
+    def poll(self, cap=4096):
+        return sketch_server_poll(self.h, cap)
+
+    def finalize(self, sid, want_u=None):
+        import torch
+        cfg = self.meta[sid]
+        want_u = bool(cfg.want_u) if want_u is None else want_u
+        S = torch.empty(cfg.k, dtype=torch.float64, device="cuda")
+        V = torch.empty(cfg.n, cfg.k, dtype=torch.float64, device="cuda")
+        U = torch.empty(cfg.m_capacity, cfg.k, dtype=torch.float64, device="cuda") if want_u else None
+        rank = sketch_server_finalize(self.h, sid, S, U, V)
+        del self.meta[sid]
+        return S, V, U, rank
+
+    def stats(self):
+        return sketch_server_get_stats(self.h)
+
+    def close(self):
+        if not self.closed:
+            sketch_server_destroy(self.h)
             self.closed = True
 
     def __del__(self):

@@ -22,7 +22,10 @@ namespace {
 
 thread_local std::string g_err;
 
-sketch_status fail(sketch_status st, const char* fmt, ...) {
+}  // namespace
+
+namespace sk {
+sketch_status set_error(sketch_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -31,6 +34,11 @@ sketch_status fail(sketch_status st, const char* fmt, ...) {
   g_err = buf;
   return st;
 }
+}  // namespace sk
+
+namespace {
+
+#define fail sk::set_error
 
 constexpr int kRing = 16;          // per-ticket completion events
 constexpr int64_t kAlign = 256;    // workspace carve alignment (bytes)
