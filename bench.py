@@ -48,6 +48,11 @@ def parse():
                     help="FP64 reference accuracy check on the whole workload")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-baseline sample (0 = skip)")
+    ap.add_argument("--serving-streams", type=int, default=64,
+                    help="streams of the serving scenario (0 = skip it)")
+    ap.add_argument("--serving-rho", type=float, default=0.8,
+                    help="offered load of the Poisson phase, as a fraction of saturation")
+    ap.add_argument("--serving-modes", default="f32,bf16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (known bytes) to scale HBM "
                          "counters")
@@ -119,6 +124,121 @@ def block_latency(A, args, torch, sk, mode):
     obj.close()
     full = [x for i, x in enumerate(lat) if (i + 1) * args.block <= m] or lat
     return float(np.percentile(full, 50)), float(np.percentile(full, 99))
+
+
+def serving_bench(args, torch, sk, mode):
+    """64 concurrent streams (n uniform over the multiples of 1024 up to 32768, m uniform in
+    [10000, 200000] rows, sigma_j = exp(-j/20) for j <= 256 and 0 beyond; k = 20, l = 40, b = 10;
+    blocks uniform in [256, 4096] rows), each a stacked pool resident on the GPU.
+
+    Phase 1 submits every block of every stream at once and measures the saturated grouped
+    throughput X.  Phase 2 replays the streams with per-stream Poisson block arrivals whose total
+    offered load is rho X (each stream's byte rate proportional to its size, so all streams span
+    the same interval), finalizing each stream on a helper thread when its last block has
+    completed; the per-block latency (submit to completion) is reported as p50 / p99."""
+    import threading
+    import synth
+    nstr = args.serving_streams
+    draws = synth.draw_serving_streams(nstr, seed=30000)
+    sig = np.zeros(1024)
+    sig[:256] = np.exp(-np.arange(1, 257) / 20.0)
+    pools = []
+    for s_ in range(nstr):
+        n, m = int(draws.n[s_]), int(draws.m[s_])
+        pools.append(synth.serving_pool_torch(n, sig, m // 1024, 10000 + s_, "cuda"))
+    torch.cuda.synchronize()
+    k, l, b = 20, 40, 10
+    probe = sk.Server(l, 32768, int(draws.m.max()), 4096, 0, compute=mode, src="f32", worker=False)
+    foot = [probe.stream_bytes(int(draws.n[s_]), int(draws.m[s_]), k, b) for s_ in range(nstr)]
+    probe.close()
+    budget = int(sum(foot) * 1.05) + (64 << 20)
+    total_bytes = float(sum(4.0 * int(draws.m[s_]) * int(draws.n[s_]) for s_ in range(nstr)))
+
+    def blocks_of(s_):
+        r0, out = 0, []
+        for rows in draws.blocks[s_]:
+            a = r0 % 1024
+            out.append(pools[s_][a:a + int(rows)])
+            r0 += int(rows)
+        return out
+
+    def run(arrivals):
+        srv = sk.Server(l, 32768, int(draws.m.max()), 4096, budget, compute=mode, src="f32",
+                        max_group=16, worker=True)
+        sids = [srv.open(int(draws.n[s_]), int(draws.m[s_]), k, b, 20000 + s_)[0]
+                for s_ in range(nstr)]
+        events = []
+        for s_ in range(nstr):
+            for i, blk in enumerate(blocks_of(s_)):
+                events.append((0.0 if arrivals is None else arrivals[s_][i], s_, i, blk))
+        events.sort(key=lambda e: (e[0], e[1], e[2]))
+        last_tk = {}
+        owner = {}
+        lat = {}
+        results = {}
+        fin_threads = []
+        remaining = {s_: len(draws.blocks[s_]) for s_ in range(nstr)}
+
+        def fin(s_):
+            S, V, _, rank = srv.finalize(sids[s_])
+            results[s_] = (S.cpu().numpy(), rank)
+
+        def drain():
+            for tk, lt in srv.poll():
+                lat[tk] = lt
+                s_ = owner[tk]
+                remaining[s_] -= 1
+                if remaining[s_] == 0:
+                    t = threading.Thread(target=fin, args=(s_,))
+                    t.start()
+                    fin_threads.append(t)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for at, s_, i, blk in events:
+            while True:
+                now = time.perf_counter() - t0
+                if now >= at:
+                    break
+                drain()
+                if at - now > 2e-4:
+                    time.sleep(min(at - now, 1e-3) * 0.5)
+            tk = srv.submit(sids[s_], blk)
+            owner[tk] = s_
+            last_tk[s_] = tk
+        while len(lat) < len(events):
+            drain()
+            time.sleep(1e-4)
+        t_pass = time.perf_counter() - t0
+        for t in fin_threads:
+            t.join()
+        t_all = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lats = np.array(list(lat.values())) * 1e3
+        errs = [abs(results[s_][0][k - 1] - sig[k - 1]) / sig[k - 1] for s_ in results]
+        return dict(pass_s=t_pass, total_s=t_all, gbps=total_bytes / t_pass / 1e9,
+                    p50_ms=float(np.percentile(lats, 50)), p99_ms=float(np.percentile(lats, 99)),
+                    blocks=int(st["blocks"]), groups=int(st["groups"]),
+                    mean_blocks_per_group=st["blocks"] / max(1, st["groups"]),
+                    max_blocks_in_group=int(st["max_blocks_in_group"]),
+                    finalized=int(st["finalized"]), state_peak_bytes=int(st["state_peak"]),
+                    median_rel_sigma_k_err_vs_known=float(np.median(errs)) if errs else None)
+
+    sat = run(None)
+    # each stream offers its bytes at a rate proportional to its size, so that all streams span
+    # the same interval and the total offered load stays rho X throughout
+    rng = np.random.default_rng(30001)
+    arrivals = []
+    for s_ in range(nstr):
+        bytes_blk = 4.0 * draws.blocks[s_] * int(draws.n[s_])
+        rate = args.serving_rho * sat["gbps"] * 1e9 * float(bytes_blk.sum()) / total_bytes
+        gaps = rng.exponential(bytes_blk / rate)
+        arrivals.append(np.cumsum(gaps))
+    loaded = run(arrivals)
+    pools.clear()
+    return {"mode": mode, "streams": nstr, "data_gb": total_bytes / 1e9, "k": k, "l": l, "b": b,
+            "saturated": sat, "rho": args.serving_rho, "poisson": loaded}
 
 
 def roofline(res, m, n, l, mode):
@@ -252,6 +372,17 @@ def main():
         del src, dst
     head = results[0]
     acc, cpu = {}, None
+    serving = []
+    if args.serving_streams > 0:
+        A_keep = A
+        for smode in [x for x in args.serving_modes.split(",") if x]:
+            print(f"[bench] serving scenario, {args.serving_streams} streams, {smode}",
+                  file=sys.stderr, flush=True)
+            serving.append(serving_bench(args, torch, sk, smode))
+            print(f"[bench] serving {smode}: saturated {serving[-1]['saturated']['gbps']:.1f} GB/s,"
+                  f" p99 {serving[-1]['poisson']['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        A = A_keep
     if args.check == "full" or args.cpu_seconds > 0:
         print("[bench] copying A to the host for the reference", file=sys.stderr, flush=True)
         A_host = A.cpu().numpy()
@@ -289,6 +420,7 @@ def main():
         "pass_only_gbps": 4.0 * args.m * args.n / ((head["gemm1_ms"] + head["gemm2_ms"]) *
                                                    head["nblocks"] * 1e-3) / 1e9,
         "block_latency_ms": {"p50": p50, "p99": p99, "rows": args.block},
+        "serving": serving,
         "accuracy": acc.get(head["mode"]),
         "compare": [
             {"dtype": r["mode"], "value": r["value"], "ms_per_step": r["ms_per_step"],

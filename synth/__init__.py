@@ -11,10 +11,10 @@ from .spectra import (paper_type_spectrum, noisy_spectrum, exp_spectrum, inv_spe
                       inv_floor_spectrum, inv_square_spectrum)
 from .matrices import (orthonormal_factor, small_matrix, KronMatrix, StackedPool,
                        gaussian_omega, low_rank_matrix)
-from .serving import ServingDraws, draw_serving_streams
+from .serving import ServingDraws, draw_serving_streams, serving_pool_torch
 
 __all__ = [
     "paper_type_spectrum", "noisy_spectrum", "exp_spectrum", "inv_spectrum", "inv_floor_spectrum",
     "inv_square_spectrum", "orthonormal_factor", "small_matrix", "KronMatrix", "StackedPool",
-    "gaussian_omega", "low_rank_matrix", "ServingDraws", "draw_serving_streams",
+    "gaussian_omega", "low_rank_matrix", "ServingDraws", "draw_serving_streams", "serving_pool_torch",
 ]

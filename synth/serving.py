@@ -45,3 +45,30 @@ def draw_serving_streams(num_streams: int = 64, n_choices=None, m_lo: int = 1000
         arrivals.append(np.cumsum(gaps))
     return ServingDraws(n=n.astype(np.int64), m=m.astype(np.int64), blocks=blocks,
                         arrivals=arrivals)
+
+
+def serving_pool_torch(n: int, sigma: np.ndarray, copies: int, seed: int, device, m0: int = 1024,
+                       ext: int = 4096):
+    """Stacking pool of one serving stream, as a float32 tensor of (m0 + ext) x n rows on `device`.
+
+    A = [A0; ...; A0] (``copies`` copies) with A0 = U0 diag(sigma / sqrt(copies)) V0^T, U0 (m0 x r)
+    and V0 (n x r) orthonormal from the QR of seeded Gaussians (r = number of nonzero sigma), so
+    sigma(A) = sigma exactly.  The pool is A0 followed by its first ``ext`` rows again: a block of
+    at most ``ext`` rows starting at row r0 of A is pool[r0 % m0 : r0 % m0 + rows].
+    """
+    import torch
+    sig = np.asarray(sigma, dtype=np.float64)
+    r = int(np.count_nonzero(sig))
+    gen = torch.Generator(device="cpu").manual_seed(int(seed))
+    U = torch.linalg.qr(torch.randn(m0, r, generator=gen, dtype=torch.float64).to(device))[0]
+    V = torch.linalg.qr(torch.randn(n, r, generator=gen, dtype=torch.float64).to(device))[0]
+    s = torch.as_tensor(sig[:r] / np.sqrt(copies), dtype=torch.float64, device=device)
+    A0 = (U * s[None, :]) @ V.t()
+    pool = torch.empty(m0 + ext, n, dtype=torch.float32, device=device)
+    pool[:m0] = A0.to(torch.float32)
+    reps = 0
+    while m0 + reps < m0 + ext:
+        cnt = min(m0, ext - reps)
+        pool[m0 + reps:m0 + reps + cnt] = pool[:cnt]
+        reps += cnt
+    return pool
