@@ -357,14 +357,21 @@ sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtyp
     h->next_slot = (h->next_slot + 1) % c.host_slots;
     uint8_t* dst = h->ws + L.off_stage + (int64_t)slot * L.stage_slot_bytes;
     if (h->slot_used[slot]) e = hipStreamWaitEvent(h->copy, h->slot_consumed[slot], 0);
-    if (e == hipSuccess)
-      e = hipMemcpy2DAsync(dst, L.LDST * es, rows, ld * es, c.n * es, nrows,
-                           hipMemcpyHostToDevice, h->copy);
+    // contiguous rows whose length keeps 16-byte alignment go as one linear copy; others as a
+    // pitched copy into rows padded to 64 elements
+    const bool linear = (ld == c.n) && ((c.n * es) % 16 == 0);
+    if (e == hipSuccess) {
+      if (linear)
+        e = hipMemcpyAsync(dst, rows, (size_t)(nrows * c.n * es), hipMemcpyHostToDevice, h->copy);
+      else
+        e = hipMemcpy2DAsync(dst, L.LDST * es, rows, ld * es, c.n * es, nrows,
+                             hipMemcpyHostToDevice, h->copy);
+    }
+    lda = linear ? c.n : L.LDST;
     if (e == hipSuccess) e = hipEventRecord(h->copy_ev[ring], h->copy);
     if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->copy_ev[ring], 0);
     if (e != hipSuccess) return h->dev_fail(e, "host block copy");
     A = dst;
-    lda = L.LDST;
   }
 
   PassItem it{};

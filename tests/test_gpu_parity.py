@@ -150,6 +150,21 @@ def test_host_staged_ingest(gpu_lib, ragged, mode, src):
         assert h["sketch"].poll(t)
 
 
+@pytest.mark.parametrize("mode,src", [("f32", "f32"), ("bf16", "bf16"), ("fp8", "f32")])
+def test_host_staged_linear_copy(gpu_lib, mode, src):
+    """Host rows whose length keeps 16-byte alignment (n = 1024) are copied linearly into the
+    staging ring; the result equals device ingest bit for bit."""
+    m, n, l, k, b = 1000, 1024, 32, 16, 8
+    sig = synth.noisy_spectrum(synth.exp_spectrum(min(m, n), 8.0), 1e-6, 31)
+    A, _, _, _ = synth.small_matrix(m, n, sig, 31)
+    Om = synth.gaussian_omega(n, l, 32)
+    blocks = [300, 300, 255, 145]
+    d = run_gpu(A, Om, k, b, mode, blocks, src=src)
+    h = run_gpu(A, Om, k, b, mode, blocks, src=src, host=True, host_slots=3)
+    assert np.array_equal(d["G"], h["G"]) and np.array_equal(d["H"], h["H"])
+    assert np.array_equal(d["S"], h["S"]) and np.array_equal(d["V"], h["V"])
+
+
 def test_deterministic(gpu_lib, ragged):
     """No atomics on the result path: repeated runs are bitwise identical."""
     A, Om, blocks = ragged["A"], ragged["Om"], ragged["blocks"]
