@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="bf16", choices=["f32", "bf16", "bf16x2", "fp8", "f64"])
-    ap.add_argument("--compare", default="f32", help="second mode reported alongside ('' = none)")
+    ap.add_argument("--compare", default="f32", help="second mode reported alongside ('none' = none)")
     ap.add_argument("--m", type=int, default=100000)
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--kron", default="500,200,100,200", help="m1,m2,n1,n2 with m=m1*m2, n=n1*n2")
@@ -504,7 +504,7 @@ def main():
         return
     print(f"[bench] generating A {args.m}x{args.n} FP32 on the GPU", file=sys.stderr, flush=True)
     A, K = make_matrix(args, torch)
-    modes = [args.mode] + ([args.compare] if args.compare and args.compare != args.mode else [])
+    modes = [args.mode] + ([args.compare] if args.compare not in ("", "none", args.mode) else [])
     results = []
     for mode in modes:
         print(f"[bench] mode {mode}: {args.warmup} warmup + {args.steps} timed steps",

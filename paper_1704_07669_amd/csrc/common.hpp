@@ -10,6 +10,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // Compute modes; the numeric values are those of sketch_dtype.
 enum Mode { M_F64 = 0, M_F32 = 1, M_BF16 = 2, M_BF16X2 = 3, M_FP8 = 4 };
@@ -106,6 +107,17 @@ template <typename T> __device__ __forceinline__ T row16_sum(T v) {
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
   v = row16_sum(v);
   return (dpp::lane(v, 0) + dpp::lane(v, 16)) + (dpp::lane(v, 32) + dpp::lane(v, 48));
+}
+
+// Pointers the compiler must treat as global memory.  Pointers read from a descriptor in memory
+// are generic, which makes every access a FLAT instruction; FLAT loads also count against the LDS
+// wait counter, so each LDS wait would drain all outstanding global prefetches.
+#define SK_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ SK_GLOBAL T* gptr(T* p) {
+  return (SK_GLOBAL T*)(p);
+}
+template <typename T> __device__ __forceinline__ const SK_GLOBAL T* gptr(const T* p) {
+  return (const SK_GLOBAL T*)(p);
 }
 
 template <typename T> __host__ __device__ constexpr T cdiv(T a, T b) { return (a + b - 1) / b; }

@@ -46,7 +46,9 @@ struct PassItem {
   unsigned* counters;  // one zero-initialised arrival counter per strip
   int32_t nrows, vec_ok, splits, row_tiles;
   int32_t strips, rsplit, rchunk, red_wgs;
-  int32_t wg1, wg2, wgr, pad;   // first workgroup of the item in the g, a^T g and reduce grids
+  int32_t wg1, wg2, wgr, wgh;   // first workgroup of the item in the g, a^T g, reduce and
+                                //   row-split sum grids
+  int32_t hsum_wgs, pad0, pad1, pad2;
 };
 struct PassGroup {
   int mode;            // Mode
@@ -57,7 +59,7 @@ struct PassGroup {
   int count;           // items
   PassItem one;        // the item when count == 1 (passed by value)
   const PassItem* dev; // device copy of the items when count > 1
-  int64_t wg1_total, wg2_total, wgr_total;
+  int64_t wg1_total, wg2_total, wgr_total, wgh_total;
 };
 constexpr int kNpAlign = 512;        // n padding: multiple of every k-chunk of g = a Omega
 constexpr int kGemm2MaxSplits = 8;   // most row splits of one strip of a^T g
@@ -69,8 +71,11 @@ void plan_group(PassGroup& g, PassItem* items, int count);
 // Strips of a^T g for n columns in `mode` (sizes the row-split scratch and counters).
 int64_t gemm2_strips(int64_t n, int mode);
 int64_t gemm2_strip_width(int mode);
+// Most (strip, row split) partial tiles of a^T g one item can have (sizes the partial scratch).
+int64_t gemm2_partial_tiles_max();
 hipError_t launch_gemm1(const PassGroup& g, hipStream_t s);
 hipError_t launch_reduce1(const PassGroup& g, hipStream_t s);
+// a^T g, plus (for items split over rows) the fixed-order sum of the row-split partials into H
 hipError_t launch_gemm2(const PassGroup& g, hipStream_t s);
 // FP8 mode: amax of the block, then a' = e4m3(a 2^e) into `q` (nrows x ldq bytes).
 hipError_t launch_fp8_quantize(const float* A, int64_t lda, int nrows, int64_t n, uint32_t* amax,

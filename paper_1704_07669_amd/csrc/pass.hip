@@ -158,14 +158,15 @@ __device__ __forceinline__ f32x4 mma(const Frag<M_FP8>& a, const Frag<M_FP8>& b,
 // the matrix-core work (two register buffers).  A wave whose rows and super-step lie inside the
 // block takes unconditional 16-byte loads; only tails take per-element masked loads.
 template <typename Src, int V, int RS>
-__device__ __forceinline__ void fetch_rows(const Src* __restrict__ A, int64_t lda, int row0,
+__device__ __forceinline__ void fetch_rows(const SK_GLOBAL Src* __restrict__ A, int64_t lda, int row0,
                                            int r16, int nrows, int64_t kbase, int g, int64_t n,
                                            bool rows_full, Src (&buf)[RS][V]) {
   const int64_t k = kbase + V * g;
   if (rows_full && kbase + 4 * V <= n) {
 #pragma unroll
     for (int rs = 0; rs < RS; ++rs) {
-      const u32x4* p = reinterpret_cast<const u32x4*>(A + (int64_t)(row0 + rs * 16 + r16) * lda + k);
+      const SK_GLOBAL u32x4* p =
+          reinterpret_cast<const SK_GLOBAL u32x4*>(A + (int64_t)(row0 + rs * 16 + r16) * lda + k);
       u32x4 tmp[V * sizeof(Src) / 16];
 #pragma unroll
       for (int i = 0; i < (int)(V * sizeof(Src) / 16); ++i) tmp[i] = p[i];
@@ -218,11 +219,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(const PassItem one,
   const int tile = (u & 7) * ((ntile + 7) >> 3) + (u >> 3);
   if (tile >= ntile) return;
   const int split = tile / it.row_tiles, rtile = tile - split * it.row_tiles;
-  const Src* __restrict__ A = reinterpret_cast<const Src*>(it.A);
+  const SK_GLOBAL Src* __restrict__ A = gptr(reinterpret_cast<const Src*>(it.A));
   const int64_t lda = it.lda, n = it.n, NP = it.NP, ldp = it.ldp;
   const int nrows = it.nrows;
-  const op_t* __restrict__ omc = reinterpret_cast<const op_t*>(it.omc);
-  acc_t* __restrict__ P = reinterpret_cast<acc_t*>(it.P1);
+  const SK_GLOBAL op_t* __restrict__ omc = gptr(reinterpret_cast<const op_t*>(it.omc));
+  SK_GLOBAL acc_t* __restrict__ P = gptr(reinterpret_cast<acc_t*>(it.P1));
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
   const int row0 = rtile * ROW_TILE + wave * 16 * RSUB;
@@ -241,8 +242,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(const PassItem one,
     __syncthreads();
     for (int p = tid; p < NT * 16 * PIECES; p += WAVES * 64) {
       const int c = p / PIECES, pc = p - c * PIECES;
-      const u32x4 v = *reinterpret_cast<const u32x4*>(
-          reinterpret_cast<const uint8_t*>(omc + (int64_t)c * NP + kc) + pc * 16);
+      const u32x4 v = *reinterpret_cast<const SK_GLOBAL u32x4*>(
+          reinterpret_cast<const SK_GLOBAL uint8_t*>(omc + (int64_t)c * NP + kc) + pc * 16);
       *reinterpret_cast<u32x4*>(lds + c * ROW_BYTES + pc * 16) = v;
     }
     fetch_rows<Src, V, RSUB>(A, lda, row0, r16, nrows, kc, g, n, rows_full, b0);
@@ -279,12 +280,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(const PassItem one,
 template <typename acc_t, bool HILO>
 __global__ void k_reduce1(const PassItem one, const PassItem* __restrict__ grp, int count, int LP) {
   const PassItem it = item_of(one, grp, count, blockIdx.x, &PassItem::wgr);
-  const acc_t* __restrict__ P = reinterpret_cast<const acc_t*>(it.P1);
-  acc_t* __restrict__ G = reinterpret_cast<acc_t*>(it.G);
-  void* __restrict__ gop = it.Gop;
+  const SK_GLOBAL acc_t* __restrict__ P = gptr(reinterpret_cast<const acc_t*>(it.P1));
+  SK_GLOBAL acc_t* __restrict__ G = gptr(reinterpret_cast<acc_t*>(it.G));
+  SK_GLOBAL uint8_t* __restrict__ gop = gptr(reinterpret_cast<uint8_t*>(it.Gop));
   const int64_t ldp = it.ldp, ldg = it.ldg, g_row0 = it.g_row0;
   const int splits = it.splits, nrows = it.nrows;
-  const acc_t scale = it.fp8_exp ? (acc_t)ldexp(1.0, -(*it.fp8_exp) - 5) : (acc_t)1;
+  const acc_t scale = it.fp8_exp ? (acc_t)ldexp(1.0, -(*gptr(it.fp8_exp)) - 5) : (acc_t)1;
   const int64_t total = (int64_t)LP * nrows;
   bool bad = false;
   for (int64_t q = (int64_t)(blockIdx.x - it.wgr) * blockDim.x + threadIdx.x; q < total;
@@ -297,16 +298,16 @@ __global__ void k_reduce1(const PassItem one, const PassItem* __restrict__ grp, 
     bad |= !isfinite(s);
     G[(int64_t)c * ldg + g_row0 + r] = s;
     if constexpr (HILO) {
-      __bf16* hi = reinterpret_cast<__bf16*>(gop);
-      __bf16* lo = hi + (int64_t)LP * ldp;
+      SK_GLOBAL __bf16* hi = reinterpret_cast<SK_GLOBAL __bf16*>(gop);
+      SK_GLOBAL __bf16* lo = hi + (int64_t)LP * ldp;
       const __bf16 h = to_bf16((float)s);
       hi[(int64_t)c * ldp + r] = h;
       lo[(int64_t)c * ldp + r] = to_bf16((float)s - from_bf16(h));
     } else {
-      reinterpret_cast<acc_t*>(gop)[(int64_t)c * ldp + r] = s;
+      reinterpret_cast<SK_GLOBAL acc_t*>(gop)[(int64_t)c * ldp + r] = s;
     }
   }
-  if (bad) it.ctrl->nonfinite = 1;
+  if (bad) gptr(it.ctrl)->nonfinite = 1;
 }
 
 // ---------------------------------------------------------------- H += a^T g
@@ -371,22 +372,22 @@ __device__ __forceinline__ AFrag2<MODE> make_a2(const Src (&a)[V2][VC], int j) {
 
 // V2 rows x VC columns of a (rows kr + V2*g + e, columns col .. col+VC-1).
 template <typename Src, int V2, int VC>
-__device__ __forceinline__ void fetch_cols(const Src* __restrict__ A, int64_t lda, int kr, int g,
+__device__ __forceinline__ void fetch_cols(const SK_GLOBAL Src* __restrict__ A, int64_t lda, int kr, int g,
                                            int nrows, int64_t col, int64_t n, bool cols_full,
                                            Src (&a)[V2][VC]) {
   const int r0 = kr + V2 * g;
   if (cols_full && kr + 4 * V2 <= nrows) {
 #pragma unroll
     for (int e = 0; e < V2; ++e) {
-      const Src* p = A + (int64_t)(r0 + e) * lda + col;
+      const SK_GLOBAL Src* p = A + (int64_t)(r0 + e) * lda + col;
       if constexpr (VC * sizeof(Src) == 16) {
-        const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+        const u32x4 v = *reinterpret_cast<const SK_GLOBAL u32x4*>(p);
         __builtin_memcpy(a[e], &v, 16);
       } else if constexpr (VC * sizeof(Src) == 8) {
-        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        const u32x2 v = *reinterpret_cast<const SK_GLOBAL u32x2*>(p);
         __builtin_memcpy(a[e], &v, 8);
       } else {
-        const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+        const uint32_t v = *reinterpret_cast<const SK_GLOBAL uint32_t*>(p);
         __builtin_memcpy(a[e], &v, 4);
       }
     }
@@ -402,24 +403,25 @@ __device__ __forceinline__ void fetch_cols(const Src* __restrict__ A, int64_t ld
 // G fragment of column m: V2 consecutive block rows r0 .. r0+V2-1 of the block-local operand copy
 // (rows past the block are zero).
 template <int MODE, int V2>
-__device__ __forceinline__ GFrag<MODE> fetch_g(const void* __restrict__ gop, int64_t ldp, int LP,
+__device__ __forceinline__ GFrag<MODE> fetch_g(const SK_GLOBAL uint8_t* __restrict__ gop, int64_t ldp, int LP,
                                                int m, int r0, int nrows) {
   GFrag<MODE> f;
   if constexpr (MODE == M_F64 || MODE == M_F32) {
     using gt = typename std::conditional<MODE == M_F64, double, float>::type;
-    const gt* p = reinterpret_cast<const gt*>(gop) + (int64_t)m * ldp + r0;
+    const SK_GLOBAL gt* p = reinterpret_cast<const SK_GLOBAL gt*>(gop) + (int64_t)m * ldp + r0;
     if (r0 + V2 <= nrows) {
-      __builtin_memcpy(f.v, p, sizeof(f.v));
+#pragma unroll
+      for (int e = 0; e < V2; ++e) f.v[e] = p[e];
     } else {
 #pragma unroll
       for (int e = 0; e < V2; ++e) f.v[e] = (r0 + e < nrows) ? p[e] : gt(0);
     }
   } else {
-    const __bf16* hi = reinterpret_cast<const __bf16*>(gop) + (int64_t)m * ldp + r0;
-    const __bf16* lo = hi + (int64_t)LP * ldp;
+    const SK_GLOBAL __bf16* hi = reinterpret_cast<const SK_GLOBAL __bf16*>(gop) + (int64_t)m * ldp + r0;
+    const SK_GLOBAL __bf16* lo = hi + (int64_t)LP * ldp;
     if (r0 + V2 <= nrows) {
-      const u32x4 vh = *reinterpret_cast<const u32x4*>(hi);
-      const u32x4 vl = *reinterpret_cast<const u32x4*>(lo);
+      const u32x4 vh = *reinterpret_cast<const SK_GLOBAL u32x4*>(hi);
+      const u32x4 vl = *reinterpret_cast<const SK_GLOBAL u32x4*>(lo);
       __builtin_memcpy(&f.hi, &vh, 16);
       __builtin_memcpy(&f.lo, &vl, 16);
     } else {
@@ -434,7 +436,7 @@ __device__ __forceinline__ GFrag<MODE> fetch_g(const void* __restrict__ gop, int
 }
 
 template <int MODE, int NT>
-__device__ __forceinline__ void fetch_gall(const void* __restrict__ gop, int64_t ldp, int LP,
+__device__ __forceinline__ void fetch_gall(const SK_GLOBAL uint8_t* __restrict__ gop, int64_t ldp, int LP,
                                            int r16, int r0, int nrows, GFrag<MODE> (&gq)[NT]) {
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) gq[mt] = fetch_g<MODE, PT<MODE>::V2>(gop, ldp, LP, mt * 16 + r16, r0, nrows);
@@ -470,11 +472,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(const PassItem one,
   const int tile = blockIdx.x - it.wg2;
   const int64_t strip = tile % it.strips;
   const int rs = tile / it.strips, rsplit = it.rsplit;
-  const Src* __restrict__ A = reinterpret_cast<const Src*>(it.A);
-  const void* __restrict__ gop = it.Gop;
+  const SK_GLOBAL Src* __restrict__ A = gptr(reinterpret_cast<const Src*>(it.A));
+  const SK_GLOBAL uint8_t* __restrict__ gop = gptr(reinterpret_cast<const uint8_t*>(it.Gop));
   const int64_t lda = it.lda, n = it.n, ldp = it.ldp, ldh = it.ldh;
-  double* __restrict__ H = it.H;
-  acc_t* __restrict__ part = reinterpret_cast<acc_t*>(it.P2);
+  SK_GLOBAL double* __restrict__ H = gptr(it.H);
+  SK_GLOBAL acc_t* __restrict__ part = gptr(reinterpret_cast<acc_t*>(it.P2));
   unsigned* __restrict__ counters = it.counters;
   int nrows = it.nrows;
 
@@ -518,12 +520,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(const PassItem one,
   }
 
   mfma_drain();
-  const double scale = it.fp8_exp ? ldexp(1.0, -(*it.fp8_exp)) : 1.0;
+  const double scale = it.fp8_exp ? ldexp(1.0, -(*gptr(it.fp8_exp))) : 1.0;
   // Row-split partials: every workgroup of a strip writes its (wave-ordered) FP32 sum; the last
   // one to finish, found with a per-strip counter, adds the rsplit partials in split order into
   // the FP64 rows of H and resets the counter.  No workgroup waits on another.
   const int64_t pstride = (int64_t)LP * 16 * VC;          // one partial tile
-  acc_t* mine = part + (strip * rsplit + rs) * pstride;
+  SK_GLOBAL acc_t* mine = part + (strip * rsplit + rs) * pstride;
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
     __syncthreads();
@@ -560,7 +562,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(const PassItem one,
   __syncthreads();
   if (!last) return;
   __threadfence();
-  const acc_t* base = part + strip * rsplit * pstride;
+  const SK_GLOBAL acc_t* base = part + strip * rsplit * pstride;
   for (int e = tid; e < pstride; e += blockDim.x) {
     const int lidx = e / (16 * VC), cc = e - lidx * 16 * VC;
     if (c0 + cc >= n) continue;
@@ -569,6 +571,281 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(const PassItem one,
     H[(int64_t)lidx * ldh + c0 + cc] += scale * sm;
   }
   if (tid == 0) counters[strip] = 0u;
+}
+
+// ---------------------------------------------------------------- H += a^T g, wide strips
+// Matrix-core modes with FP32 accumulation.  Each workgroup owns a strip of 256 columns of a (its
+// four waves take 64 columns each, all l_p sketch columns) and one range of the block's rows.
+// Per step of KR = 4 V2 rows, the G operand of those rows (BF16 hi and lo, or FP32) is loaded
+// once into LDS in lane order and read by the four waves; rows of a go straight to registers,
+// DEPTH steps ahead of the matrix-core work.  The step loop synchronises with a bare barrier
+// after an LDS-count wait only, so the a loads of later steps stay in flight across it.
+template <int MODE> struct G2W { static constexpr int HALVES = (MODE == M_F32) ? 1 : 2; };
+
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// The 16-byte G pieces of one step (rows kr .. kr+KR-1) in lane order.  Every thread issues GPT
+// loads (indices past the last piece repeat it) at clamped, always valid addresses, so every step
+// issues the same loads with no branch; rows at or past row_hi read as zero.
+template <int MODE, int NT, int GPT>
+__device__ __forceinline__ void fetch_gstep(const SK_GLOBAL uint8_t* __restrict__ gop, int64_t ldp, int tid,
+                                           int kr, int row_hi, u32x4 (&gr)[GPT]) {
+  constexpr int V2 = PT<MODE>::V2, HALVES = G2W<MODE>::HALVES;
+  constexpr int ES = (MODE == M_F32) ? 4 : 2;
+  constexpr int PIECES = HALVES * NT * 64;
+  constexpr int LP = NT * 16;
+#pragma unroll
+  for (int i = 0; i < GPT; ++i) {
+    const int p = min(tid + i * 256, PIECES - 1);
+    const int r16 = p & 15, g = (p >> 4) & 3, th = p >> 6;       // th = h * NT + t
+    const int h = th / NT, t = th - h * NT;
+    const int r0 = kr + V2 * g;
+    const int rc = min(r0, (int)ldp - V2);                       // rows past ldp are past row_hi
+    const SK_GLOBAL uint8_t* src =
+        gop + ((int64_t)h * LP * ldp + (int64_t)(t * 16 + r16) * ldp + rc) * ES;
+    gr[i] = *reinterpret_cast<const SK_GLOBAL u32x4*>(src);
+  }
+}
+
+// Stores the G pieces of the step at row kr into an LDS half, zeroing rows at or past row_hi.
+template <int MODE, int NT, int GPT>
+__device__ __forceinline__ void store_gstep(u32x4* dst, const u32x4 (&gr)[GPT], int tid, int kr,
+                                           int row_hi) {
+  constexpr int V2 = PT<MODE>::V2, HALVES = G2W<MODE>::HALVES;
+  constexpr int ES = (MODE == M_F32) ? 4 : 2;
+  constexpr int PIECES = HALVES * NT * 64, KRS = 4 * V2;
+  const bool full = kr + KRS <= row_hi;
+#pragma unroll
+  for (int i = 0; i < GPT; ++i) {
+    const int p = tid + i * 256;
+    if (p < PIECES) {
+      u32x4 v = gr[i];
+      if (!full) {
+        const int r0 = kr + V2 * ((p >> 4) & 3);
+        uint32_t w[4] = {v[0], v[1], v[2], v[3]};
+#pragma unroll
+        for (int e = 0; e < V2; ++e) {
+          if (r0 + e >= row_hi) {
+            if constexpr (ES == 4) w[e] = 0u;
+            else w[e >> 1] &= (e & 1) ? 0x0000ffffu : 0xffff0000u;
+          }
+        }
+        v = u32x4{w[0], w[1], w[2], w[3]};
+      }
+      dst[p] = v;
+    }
+  }
+}
+
+// V2 rows x VC columns of a at clamped addresses (rows past row_hi repeat row row_hi - 1, columns
+// start at most at n - VC): always valid, no branch.  Repeated rows meet zero G rows; clamped
+// columns only feed outputs past n, which are discarded.
+template <typename Src, int V2, int VC>
+__device__ __forceinline__ void fetch_cols_clamped(const SK_GLOBAL Src* __restrict__ A, int64_t lda,
+                                                   int kr, int g, int row_hi, int64_t colc,
+                                                   Src (&a)[V2][VC]) {
+  const int r0 = kr + V2 * g;
+#pragma unroll
+  for (int e = 0; e < V2; ++e) {
+    const int r = min(r0 + e, row_hi - 1);
+    const SK_GLOBAL Src* p = A + (int64_t)r * lda + colc;
+    if constexpr (VC * sizeof(Src) == 16) {
+      const u32x4 v = *reinterpret_cast<const SK_GLOBAL u32x4*>(p);
+      __builtin_memcpy(a[e], &v, 16);
+    } else if constexpr (VC * sizeof(Src) == 8) {
+      const u32x2 v = *reinterpret_cast<const SK_GLOBAL u32x2*>(p);
+      __builtin_memcpy(a[e], &v, 8);
+    } else {
+      const uint32_t v = *reinterpret_cast<const SK_GLOBAL uint32_t*>(p);
+      __builtin_memcpy(a[e], &v, 4);
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ GFrag<MODE> lds_gfrag(const u32x4* gl, int NTt, int t, int g, int r16) {
+  GFrag<MODE> f;
+  if constexpr (MODE == M_F32) {
+    const u32x4 v = gl[(t * 4 + g) * 16 + r16];
+    __builtin_memcpy(f.v, &v, 16);
+  } else {
+    const u32x4 vh = gl[(t * 4 + g) * 16 + r16];
+    const u32x4 vl = gl[((NTt + t) * 4 + g) * 16 + r16];
+    __builtin_memcpy(&f.hi, &vh, 16);
+    __builtin_memcpy(&f.lo, &vl, 16);
+  }
+  return f;
+}
+
+// The step loop of k_gemm2w.  Steps s of KR rows: a(s) sits in registers ab[s % DEPTH] and G(s)
+// in gr[s % DEPTH] until it is stored to LDS half s & 1 at the end of step s - 1.  a and G of step
+// s + DEPTH are issued together right after step s's matrix-core work (past the last step they
+// re-read it, unused), so every step issues the same loads and waiting for G(s + 1) leaves the
+// loads of DEPTH - 1 later steps in flight.  VEC: aligned rows, n a multiple of 4; otherwise the
+// masked element loads serve.
+template <typename Src, int MODE, int NT, int DEPTH, bool VEC>
+__device__ __forceinline__ void g2w_steps(const SK_GLOBAL Src* __restrict__ A, int64_t lda,
+                                          int64_t n, const SK_GLOBAL uint8_t* __restrict__ gop,
+                                          int64_t ldp, int row_lo, int row_hi, int nsteps, int tid,
+                                          int g, int r16, int64_t col, u32x4* gl,
+                                          f32x4 (&acc)[NT][4]) {
+  using T = PT<MODE>;
+  constexpr int V2 = T::V2, VC = 4, KR = 4 * V2;
+  constexpr int PIECES = G2W<MODE>::HALVES * NT * 64;
+  constexpr int GPT = (PIECES + 255) / 256;
+  const int64_t colc = VEC ? min(col, n - VC) : col;
+  Src ab[DEPTH][V2][VC];
+  u32x4 gr[DEPTH][GPT];
+  auto load_step = [&](int s, int d) {
+    const int sc = min(s, nsteps - 1);
+    if constexpr (VEC)
+      fetch_cols_clamped<Src, V2, VC>(A, lda, row_lo + sc * KR, g, row_hi, colc, ab[d]);
+    else
+      fetch_cols<Src, V2, VC>(A, lda, row_lo + sc * KR, g, row_hi, col, n, false, ab[d]);
+    fetch_gstep<MODE, NT, GPT>(gop, ldp, tid, row_lo + sc * KR, row_hi, gr[d]);
+  };
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) load_step(d, d);
+  store_gstep<MODE, NT, GPT>(gl, gr[0], tid, row_lo, row_hi);
+  lds_barrier();
+
+  for (int s0 = 0; s0 < nsteps; s0 += DEPTH) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      const int s = s0 + d;
+      const u32x4* gb = gl + (s & 1) * PIECES;
+      if (s < nsteps) {
+        AFrag2<MODE> af[VC];
+#pragma unroll
+        for (int j = 0; j < VC; ++j) af[j] = make_a2<MODE, Src, V2, VC>(ab[d], j);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const GFrag<MODE> gq = lds_gfrag<MODE>(gb, NT, t, g, r16);
+#pragma unroll
+          for (int j = 0; j < VC; ++j) acc[t][j] = mma2(gq, af[j], acc[t][j]);
+        }
+      }
+      load_step(s + DEPTH, d);
+      if (s + 1 < nsteps)
+        store_gstep<MODE, NT, GPT>(gl + ((s + 1) & 1) * PIECES, gr[(d + 1) % DEPTH], tid,
+                                   row_lo + (s + 1) * KR, row_hi);
+      lds_barrier();
+    }
+  }
+}
+
+template <typename Src, int MODE, int NT, int DEPTH>
+__global__ __launch_bounds__(256) void k_gemm2w(const PassItem one,
+                                                const PassItem* __restrict__ grp, int count) {
+  using T = PT<MODE>;
+  constexpr int V2 = T::V2, VC = 4, KR = 4 * V2, LP = NT * 16, SW = 256;
+  constexpr int PIECES = G2W<MODE>::HALVES * NT * 64;
+  constexpr int GPT = (PIECES + 255) / 256;
+  __shared__ u32x4 gl[2 * PIECES];
+
+  const PassItem it = item_of(one, grp, count, blockIdx.x, &PassItem::wg2);
+  const int tile = blockIdx.x - it.wg2;
+  const int64_t strip = tile % it.strips;
+  const int rs = tile / it.strips, rsplit = it.rsplit;
+  const SK_GLOBAL Src* __restrict__ A = gptr(reinterpret_cast<const Src*>(it.A));
+  const SK_GLOBAL uint8_t* __restrict__ gop = gptr(reinterpret_cast<const uint8_t*>(it.Gop));
+  const int64_t lda = it.lda, n = it.n, ldp = it.ldp, ldh = it.ldh;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
+  const int64_t c0 = strip * SW + wave * 64;
+  const int64_t col = c0 + VC * r16;
+  const int row_lo = rs * it.rchunk;
+  const int row_hi = min(it.nrows, row_lo + it.rchunk);
+  const int nsteps = (row_hi - row_lo + KR - 1) / KR;
+
+  f32x4 acc[NT][VC];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < VC; ++j) acc[t][j] = f32x4{0, 0, 0, 0};
+
+  if (it.vec_ok && (n % VC) == 0 && n >= VC)
+    g2w_steps<Src, MODE, NT, DEPTH, true>(A, lda, n, gop, ldp, row_lo, row_hi, nsteps, tid, g, r16,
+                                          col, gl, acc);
+  else
+    g2w_steps<Src, MODE, NT, DEPTH, false>(A, lda, n, gop, ldp, row_lo, row_hi, nsteps, tid, g,
+                                           r16, col, gl, acc);
+
+  const double scale = it.fp8_exp ? ldexp(1.0, -(*gptr(it.fp8_exp))) : 1.0;
+  SK_GLOBAL double* __restrict__ H = gptr(it.H);
+  if (rsplit == 1) {
+    // H rows of one sketch tile at a time: all 16 loads (4 rows x 4 columns per lane) are issued
+    // before any store, so each tile costs one memory round trip
+    const bool cfull = col + VC <= n;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double h[4][VC];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        SK_GLOBAL double* hp = H + (int64_t)(t * 16 + acc_row<float>(g, i)) * ldh + col;
+#pragma unroll
+        for (int j = 0; j < VC; ++j) h[i][j] = (cfull || col + j < n) ? hp[j] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        SK_GLOBAL double* hp = H + (int64_t)(t * 16 + acc_row<float>(g, i)) * ldh + col;
+#pragma unroll
+        for (int j = 0; j < VC; ++j)
+          if (cfull || col + j < n) hp[j] = h[i][j] + scale * (double)acc[t][j][i];
+      }
+    }
+    return;
+  }
+  // row splits: every workgroup writes its FP32 partial (strip-major, LP rows of 256 columns);
+  // k_hsum adds them in split order into H
+  SK_GLOBAL float* __restrict__ part = gptr(reinterpret_cast<float*>(it.P2));
+  const int64_t pstride = (int64_t)LP * SW;
+  SK_GLOBAL float* mine = part + (strip * rsplit + rs) * pstride;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int lidx = t * 16 + acc_row<float>(g, i);
+      const f32x4 v = {acc[t][0][i], acc[t][1][i], acc[t][2][i], acc[t][3][i]};
+      *reinterpret_cast<SK_GLOBAL f32x4*>(mine + (int64_t)lidx * SW + wave * 64 + VC * r16) = v;
+    }
+}
+
+// H += scale * (sum over row splits, in split order, of the FP32 partials), in FP64.  One thread
+// per 4 consecutive columns of one sketch row of one strip.
+__global__ __launch_bounds__(256) void k_hsum(const PassItem one, const PassItem* __restrict__ grp,
+                                              int count, int LP) {
+  const PassItem it = item_of(one, grp, count, blockIdx.x, &PassItem::wgh);
+  if (it.rsplit <= 1) return;
+  constexpr int SW = 256;
+  const int64_t q = (int64_t)(blockIdx.x - it.wgh) * 256 + threadIdx.x;   // group of 4 columns
+  const int64_t per_strip = (int64_t)LP * (SW / 4);
+  if (q >= per_strip * it.strips) return;
+  const int64_t strip = q / per_strip;
+  const int64_t w = q - strip * per_strip;
+  const int lidx = (int)(w / (SW / 4));
+  const int cc = (int)(w - (int64_t)lidx * (SW / 4)) * 4;
+  const int64_t col = strip * SW + cc;
+  if (col >= it.n) return;
+  const int64_t pstride = (int64_t)LP * SW;
+  const SK_GLOBAL float* base = gptr(reinterpret_cast<const float*>(it.P2)) +
+                                strip * it.rsplit * pstride + (int64_t)lidx * SW + cc;
+  double sm[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < it.rsplit; ++r) {
+    const f32x4 v = *reinterpret_cast<const SK_GLOBAL f32x4*>(base + r * pstride);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sm[j] += (double)v[j];
+  }
+  const double scale = it.fp8_exp ? ldexp(1.0, -(*gptr(it.fp8_exp))) : 1.0;
+  SK_GLOBAL double* h = gptr(it.H) + (int64_t)lidx * it.ldh + col;
+  double hv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) hv[j] = (col + j < it.n) ? h[j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (col + j < it.n) h[j] = hv[j] + scale * sm[j];
 }
 
 // ---------------------------------------------------------------- FP8 block quantisation
@@ -627,10 +904,18 @@ hipError_t gemm1_t(const PassGroup& a, hipStream_t s) {
                      a.one, a.dev, a.count);
   return hipGetLastError();
 }
+// a steps in flight per wave in the wide-strip product (2 and 3 measured alike on the FP32-resident
+// 100000 x 20000 workload; 2 needs fewer registers)
+constexpr int kG2Depth = 2;
 template <typename Src, int MODE, int NT>
 hipError_t gemm2_t(const PassGroup& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm2<Src, MODE, NT>), dim3((unsigned)a.wg2_total), dim3(WAVES * 64), 0, s,
-                     a.one, a.dev, a.count);
+  if constexpr (MODE == M_F64) {
+    hipLaunchKernelGGL((k_gemm2<Src, MODE, NT>), dim3((unsigned)a.wg2_total), dim3(WAVES * 64), 0,
+                       s, a.one, a.dev, a.count);
+  } else {
+    hipLaunchKernelGGL((k_gemm2w<Src, MODE, NT, kG2Depth>), dim3((unsigned)a.wg2_total), dim3(256),
+                       0, s, a.one, a.dev, a.count);
+  }
   return hipGetLastError();
 }
 
@@ -683,11 +968,16 @@ G2Shape g2_shape(int mode) {
   }
 }
 int src_bytes(int src) { return src == S_F64 ? 8 : src == S_F32 ? 4 : src == S_BF16 ? 2 : 1; }
+// workgroups the wide-strip product aims at for one block: one per CU (its register footprint
+// allows one four-wave workgroup per CU)
+constexpr int64_t kG2TargetWgs = 256;
+int64_t g2_target() { return kG2TargetWgs; }
 
 }  // namespace
 
-int64_t gemm2_strip_width(int mode) { return 16 * g2_shape(mode).VC; }
+int64_t gemm2_strip_width(int mode) { return mode == M_F64 ? 16 * g2_shape(mode).VC : 256; }
 int64_t gemm2_strips(int64_t n, int mode) { return cdiv<int64_t>(n, gemm2_strip_width(mode)); }
+int64_t gemm2_partial_tiles_max() { return std::max<int64_t>(g2_target(), 1024 / WAVES); }
 
 // Launch shape of one item.
 //   g = a Omega: row tiles of 128 rows times k splits, enough splits for about 512 workgroups
@@ -703,41 +993,65 @@ void plan_item(PassItem& it, int mode, int src, int splits_max) {
   it.splits = (int)cdiv<int64_t>(it.n, it.kchunk);
   const G2Shape sh = g2_shape(mode);
   const int KR = 4 * sh.V2;
-  constexpr int64_t kSlots = 1024;
-  const int64_t strips = cdiv<int64_t>(it.n, 16 * sh.VC);
   const int64_t steps = cdiv<int64_t>(it.nrows, KR);
-  int rsplit = 1;
-  if (strips * WAVES < kSlots / 2) {
-    rsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kGemm2MaxSplits,
-                                                           kSlots / (strips * WAVES),
-                                                           steps / (2 * WAVES) + 1}));
+  if (mode == M_F64) {
+    constexpr int64_t kSlots = 1024;
+    const int64_t strips = cdiv<int64_t>(it.n, 16 * sh.VC);
+    int rsplit = 1;
+    if (strips * WAVES < kSlots / 2) {
+      rsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kGemm2MaxSplits,
+                                                             kSlots / (strips * WAVES),
+                                                             steps / (2 * WAVES) + 1}));
+    }
+    it.rchunk = (int)rup<int64_t>(cdiv<int64_t>(it.nrows, rsplit), (int64_t)WAVES * KR);
+    it.rsplit = (int)cdiv<int64_t>(it.nrows, it.rchunk);
+    it.strips = (int)strips;
+  } else {
+    // wide strips: at most one workgroup per CU in total (row splits rounded down), each with at
+    // least 8 steps of rows
+    const int64_t strips = cdiv<int64_t>(it.n, 256);
+    const int64_t want = g2_target() / strips;
+    const int rsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kGemm2MaxSplits, want,
+                                                                    steps / 8}));
+    it.rchunk = (int)rup<int64_t>(cdiv<int64_t>(it.nrows, rsplit), (int64_t)KR);
+    it.rsplit = (int)cdiv<int64_t>(it.nrows, it.rchunk);
+    it.strips = (int)strips;
   }
-  it.rchunk = (int)rup<int64_t>(cdiv<int64_t>(it.nrows, rsplit), (int64_t)WAVES * KR);
-  it.rsplit = (int)cdiv<int64_t>(it.nrows, it.rchunk);
-  it.strips = (int)strips;
 }
 
 void plan_group(PassGroup& g, PassItem* items, int count) {
-  int64_t w1 = 0, w2 = 0, wr = 0;
+  int64_t w1 = 0, w2 = 0, wr = 0, wh = 0;
   for (int i = 0; i < count; ++i) {
     PassItem& it = items[i];
     it.red_wgs = (int)std::max<int64_t>(1, std::min<int64_t>(4096, cdiv<int64_t>((int64_t)g.LP * it.nrows, 256)));
+    it.hsum_wgs = (g.mode != M_F64 && it.rsplit > 1)
+                      ? (int)cdiv<int64_t>((int64_t)it.strips * g.LP * 64, 256) : 0;
     it.wg1 = (int)w1;
     it.wg2 = (int)w2;
     it.wgr = (int)wr;
+    it.wgh = (int)wh;
     w1 += rup<int64_t>((int64_t)it.row_tiles * it.splits, 8);
     w2 += (int64_t)it.strips * it.rsplit;
     wr += it.red_wgs;
+    wh += it.hsum_wgs;
   }
   g.count = count;
   g.wg1_total = w1;
   g.wg2_total = w2;
   g.wgr_total = wr;
+  g.wgh_total = wh;
   if (count == 1) g.one = items[0];
 }
 
 hipError_t launch_gemm1(const PassGroup& a, hipStream_t s) { SK_MODE_SWITCH(gemm1_t) }
-hipError_t launch_gemm2(const PassGroup& a, hipStream_t s) { SK_MODE_SWITCH(gemm2_t) }
+hipError_t launch_gemm2_main(const PassGroup& a, hipStream_t s) { SK_MODE_SWITCH(gemm2_t) }
+hipError_t launch_gemm2(const PassGroup& a, hipStream_t s) {
+  hipError_t e = launch_gemm2_main(a, s);
+  if (e != hipSuccess || a.wgh_total == 0) return e;
+  hipLaunchKernelGGL(k_hsum, dim3((unsigned)a.wgh_total), dim3(256), 0, s, a.one, a.dev, a.count,
+                     a.LP);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce1(const PassGroup& a, hipStream_t s) {
   const dim3 grid((unsigned)a.wgr_total), block(256);

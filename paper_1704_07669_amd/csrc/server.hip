@@ -99,7 +99,7 @@ int64_t up(int64_t v) { return rup<int64_t>(v, kAlign); }
 //   split partials: splits <= 512 / row_tiles + 1 of at most kSplitsCap, so
 //                   splits * rows16 <= 512 * 128 + 128 * row_tiles;
 //   g operand:      LP x rows16 (hi and lo BF16, or FP32 / FP64);
-//   row-split partials of a^T g: only when strips * 4 < 512, at most 1024 / 4 tiles.
+//   row-split partials of a^T g: at most gemm2_partial_tiles_max() tiles.
 int64_t item_bound(int64_t rows, int64_t n, int LP, int mode) {
   const int64_t rows16 = rup<int64_t>(rows, 16);
   const int64_t row_tiles = cdiv<int64_t>(rows, 128);
@@ -107,7 +107,7 @@ int64_t item_bound(int64_t rows, int64_t n, int LP, int mode) {
   const int g = acc_bytes(mode);
   const int64_t p1 = split_rows * LP * g;
   const int64_t gop = (int64_t)LP * rows16 * g;
-  const int64_t p2 = 256 * (int64_t)LP * gemm2_strip_width(mode) * g;
+  const int64_t p2 = gemm2_partial_tiles_max() * (int64_t)LP * gemm2_strip_width(mode) * g;
   (void)n;
   return up(p1) + up(gop) + up(p2);
 }
