@@ -53,6 +53,12 @@ __device__ __forceinline__ PassItem item_of(const PassItem& one, const PassItem*
   return grp[i];
 }
 
+// Workgroup barrier that waits only for the wave's LDS operations: global loads issued for later
+// steps stay in flight across it (a plain __syncthreads also waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ---------------------------------------------------------------- operand fragments
 template <int MODE> struct Frag;
 template <> struct Frag<M_F64> { double v[4]; };
@@ -198,6 +204,102 @@ __device__ __forceinline__ void gemm1_step(const Src (&buf)[RS][PT<MODE>::V1], c
   }
 }
 
+// Omega' chunks of g = a Omega: 256 bytes of each Omega' column (32 FP64 .. 256 FP8 values) per
+// LDS buffer, rows padded by 16 bytes so 16-lane reads are conflict free.
+template <int MODE> struct G1C {
+  using op_t = typename PT<MODE>::op_t;
+  static constexpr int KC = 256 / (int)sizeof(op_t);          // columns of a per chunk
+  static constexpr int KSS = 4 * PT<MODE>::V1;                 // columns of a per step
+  static constexpr int SPC = KC / KSS;                         // steps per chunk
+  static constexpr int ROWB = 256 + 16;
+};
+
+// A rows row0 + rs*16 + r16 (rs < RSUB), columns k .. k+V-1, at clamped addresses: rows past the
+// block repeat its last row (their g rows are never written), and a window at or past kmax (the
+// readable columns of a row, a multiple of V) reads column 0 instead: it meets zero rows of
+// Omega', which is zero-padded past n.
+template <typename Src, int V, int RS>
+__device__ __forceinline__ void fetch_rows_clamped(const SK_GLOBAL Src* __restrict__ A, int64_t lda,
+                                                   int row0, int r16, int nrows, int64_t k,
+                                                   int64_t kmax, Src (&buf)[RS][V]) {
+  const int64_t kc = (k < kmax) ? k : 0;
+#pragma unroll
+  for (int rs = 0; rs < RS; ++rs) {
+    const int row = min(row0 + rs * 16 + r16, nrows - 1);
+    const SK_GLOBAL u32x4* p = reinterpret_cast<const SK_GLOBAL u32x4*>(A + (int64_t)row * lda + kc);
+    u32x4 tmp[V * sizeof(Src) / 16];
+#pragma unroll
+    for (int i = 0; i < (int)(V * sizeof(Src) / 16); ++i) tmp[i] = p[i];
+    __builtin_memcpy(buf[rs], tmp, sizeof(buf[rs]));
+  }
+}
+
+// The step loop of k_gemm1.  Step t covers columns k_begin + t KSS .. + KSS - 1; chunk c (SPC
+// steps) reads Omega' buffer c & 1 of LDS.  a of step t + DEPTH is issued right after step t's
+// matrix-core work (past the last step it re-reads the last one, unused); the next chunk of
+// Omega' is loaded into registers one chunk ahead and stored to the idle buffer at the end of the
+// chunk, followed by the chunk's only barrier (an LDS-count wait, so a loads stay in flight).
+template <typename Src, int MODE, int NT, int DEPTH, bool VEC>
+__device__ __forceinline__ void g1_steps(const SK_GLOBAL Src* __restrict__ A, int64_t lda, int nrows,
+                                         int64_t n, int64_t kmax,
+                                         const SK_GLOBAL typename PT<MODE>::op_t* __restrict__ omc,
+                                         int64_t NP, int64_t k_begin, int64_t k_end, int row0,
+                                         int tid, int g, int r16, uint8_t* lds,
+                                         typename PT<MODE>::accv (&acc)[RSUB][NT]) {
+  using op_t = typename PT<MODE>::op_t;
+  constexpr int V = PT<MODE>::V1, KSS = G1C<MODE>::KSS, KC = G1C<MODE>::KC;
+  constexpr int SPC = G1C<MODE>::SPC, ROWB = G1C<MODE>::ROWB, BUF = NT * 16 * ROWB;
+  static_assert(SPC % DEPTH == 0, "the a ring must divide the steps of a chunk");
+  const int T = (int)((k_end - k_begin + KSS - 1) / KSS);
+  const int C = (T + SPC - 1) / SPC;
+  Src ab[DEPTH][RSUB][V];
+  u32x4 om[NT];                         // NT*16 rows x 16 pieces = NT pieces per thread
+  auto load_a = [&](int t, int d) {
+    const int tc = min(t, T - 1);
+    const int64_t kb = k_begin + (int64_t)tc * KSS;
+    if constexpr (VEC)
+      fetch_rows_clamped<Src, V, RSUB>(A, lda, row0, r16, nrows, kb + V * g, kmax, ab[d]);
+    else
+      fetch_rows<Src, V, RSUB>(A, lda, row0, r16, nrows, kb, g, n, false, ab[d]);
+  };
+  auto load_om = [&](int c) {
+    const int64_t kc = k_begin + (int64_t)min(c, C - 1) * KC;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int p = tid + i * 256, row = p >> 4, pc = p & 15;
+      om[i] = *reinterpret_cast<const SK_GLOBAL u32x4*>(
+          reinterpret_cast<const SK_GLOBAL uint8_t*>(omc + (int64_t)row * NP + kc) + pc * 16);
+    }
+  };
+  auto store_om = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int p = tid + i * 256, row = p >> 4, pc = p & 15;
+      *reinterpret_cast<u32x4*>(lds + b * BUF + row * ROWB + pc * 16) = om[i];
+    }
+  };
+  load_om(0);
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) load_a(d, d);
+  store_om(0);
+  lds_barrier();
+  load_om(1);
+  for (int c = 0; c < C; ++c) {
+    const uint8_t* buf = lds + (c & 1) * BUF;
+#pragma unroll
+    for (int j = 0; j < SPC; ++j) {
+      const int t = c * SPC + j;
+      if (t < T)
+        gemm1_step<Src, MODE, NT, RSUB>(ab[j % DEPTH], buf, ROWB,
+                                        (j * KSS + V * g) * (int)sizeof(op_t), r16, acc);
+      load_a(t + DEPTH, j % DEPTH);
+    }
+    if (c + 1 < C) store_om((c + 1) & 1);
+    lds_barrier();
+    load_om(c + 2);
+  }
+}
+
 // Tiles of an item are (row tile, split) pairs, numbered split-major and spread so that the
 // workgroups of one split, which share one k-chunk of Omega', land on the same XCD (workgroups are
 // dealt to the 8 XCDs round-robin; item offsets are multiples of 8).
@@ -208,10 +310,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(const PassItem one,
   using op_t = typename T::op_t;
   using acc_t = typename T::acc_t;
   using accv = typename T::accv;
-  constexpr int V = T::V1, KSS = 4 * V, KC = T::KC, LP = NT * 16;
-  constexpr int ROW_BYTES = KC * (int)sizeof(op_t) + 16;   // +16 B: conflict-free 16-lane reads
-  constexpr int PIECES = KC * (int)sizeof(op_t) / 16;
-  __shared__ __attribute__((aligned(16))) uint8_t lds[NT * 16 * ROW_BYTES];
+  constexpr int V = T::V1, LP = NT * 16;
+  constexpr int DEPTH = 2;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * NT * 16 * G1C<MODE>::ROWB];
 
   const PassItem it = item_of(one, grp, count, blockIdx.x, &PassItem::wg1);
   const int ntile = it.row_tiles * it.splits;
@@ -227,9 +328,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(const PassItem one,
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
   const int row0 = rtile * ROW_TILE + wave * 16 * RSUB;
-  const bool rows_full = it.vec_ok && (row0 + 16 * RSUB <= nrows);
   const int64_t k_begin = (int64_t)split * it.kchunk;
   const int64_t k_end = min(n, k_begin + it.kchunk);
+  // readable columns of a row: n, or the zero-padded staging width of pre-quantised FP8 rows
+  const int64_t kmax = (sizeof(Src) == 1) ? lda : n;
 
   accv acc[RSUB][NT];
 #pragma unroll
@@ -237,29 +339,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm1(const PassItem one,
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[rs][nt] = accv{0, 0, 0, 0};
 
-  Src b0[RSUB][V], b1[RSUB][V];
-  for (int64_t kc = k_begin; kc < k_end; kc += KC) {
-    __syncthreads();
-    for (int p = tid; p < NT * 16 * PIECES; p += WAVES * 64) {
-      const int c = p / PIECES, pc = p - c * PIECES;
-      const u32x4 v = *reinterpret_cast<const SK_GLOBAL u32x4*>(
-          reinterpret_cast<const SK_GLOBAL uint8_t*>(omc + (int64_t)c * NP + kc) + pc * 16);
-      *reinterpret_cast<u32x4*>(lds + c * ROW_BYTES + pc * 16) = v;
-    }
-    fetch_rows<Src, V, RSUB>(A, lda, row0, r16, nrows, kc, g, n, rows_full, b0);
-    __syncthreads();
-    const int kspan = (int)min<int64_t>(KC, k_end - kc);
-    for (int ks = 0; ks < kspan; ks += 2 * KSS) {
-      const bool has1 = ks + KSS < kspan;
-      if (has1) fetch_rows<Src, V, RSUB>(A, lda, row0, r16, nrows, kc + ks + KSS, g, n, rows_full, b1);
-      gemm1_step<Src, MODE, NT, RSUB>(b0, lds, ROW_BYTES, (ks + V * g) * (int)sizeof(op_t), r16, acc);
-      if (ks + 2 * KSS < kspan)
-        fetch_rows<Src, V, RSUB>(A, lda, row0, r16, nrows, kc + ks + 2 * KSS, g, n, rows_full, b0);
-      if (has1)
-        gemm1_step<Src, MODE, NT, RSUB>(b1, lds, ROW_BYTES, (ks + KSS + V * g) * (int)sizeof(op_t),
-                                        r16, acc);
-    }
-  }
+  if (it.vec_ok && (kmax % V) == 0)
+    g1_steps<Src, MODE, NT, DEPTH, true>(A, lda, nrows, n, kmax, omc, NP, k_begin, k_end, row0, tid,
+                                         g, r16, lds, acc);
+  else
+    g1_steps<Src, MODE, NT, DEPTH, false>(A, lda, nrows, n, kmax, omc, NP, k_begin, k_end, row0,
+                                          tid, g, r16, lds, acc);
 
   mfma_drain();
   const int64_t pbase = (int64_t)split * LP;
@@ -582,9 +667,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_gemm2(const PassItem one,
 // after an LDS-count wait only, so the a loads of later steps stay in flight across it.
 template <int MODE> struct G2W { static constexpr int HALVES = (MODE == M_F32) ? 1 : 2; };
 
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
 
 // The 16-byte G pieces of one step (rows kr .. kr+KR-1) in lane order.  Every thread issues GPT
 // loads (indices past the last piece repeat it) at clamped, always valid addresses, so every step
