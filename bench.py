@@ -394,8 +394,9 @@ def roofline(res, m, n, l, mode):
     """Dominant streaming kernel against its roof: HBM for the BF16/FP8 paths (algorithmic bytes
     = the block's FP32 bytes, read once per launch), the matrix-core peak for FP32/FP64
     (algorithmic flops = 2 l per element of the block, per launch)."""
-    dom, t = ("k_gemm1+k_reduce1 (g = a Omega)", res["gemm1_ms"]) \
-        if res["gemm1_ms"] >= res["gemm2_ms"] else ("k_gemm2 (H += a^T g)", res["gemm2_ms"])
+    dom, t = ("gemm1: g = a Omega (k_gemm1 + k_reduce1)", res["gemm1_ms"]) \
+        if res["gemm1_ms"] >= res["gemm2_ms"] else \
+        ("gemm2: H += a^T g (k_gemm2w + k_hsum)", res["gemm2_ms"])
     if not t > 0:
         return None
     elems_per_launch = m * n / res["nblocks"]
@@ -408,13 +409,14 @@ def roofline(res, m, n, l, mode):
         out = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS)
     out["kernel"] = dom
     out["launch_us"] = t * 1e3
-    out["traffic"] = traffic_for(dom.split()[0], mode)
+    out["traffic"] = traffic_for(dom.split(":")[0], mode)
     return out
 
 
 def traffic_for(kernel, mode):
-    """Counter-derived HBM bytes per launch recorded in profiles/traffic.json, valid only while the
-    kernel source is unchanged (its SHA-256 is stored next to the figure)."""
+    """Counter-derived HBM bytes per launch of one product (its kernels summed) recorded in
+    profiles/traffic.json, valid only while the kernel source is unchanged (its SHA-256 is stored
+    next to the figure)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_1704_07669_amd", "csrc", "pass.hip")
     try:
