@@ -580,6 +580,22 @@ __device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
   if (p > q) { const int t = p; p = q; q = t; }
 }
 
+// 1/x and 1/sqrt(x) in FP64 from the hardware estimates, each refined by two Newton steps (the
+// estimates are good to about 2^-23, so two steps reach full FP64 precision).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
 // M (N columns padded to LP rows, zero beyond L) lives in LDS; the round-robin pair table is
 // precomputed once.  The right factor is not accumulated: with M J = W (orthogonal columns,
 // norms sigma), B^T = Q_B R_B and M = R_B^T, B^T W = Q_B J S^2, so V = B^T W S^-2 (see run_finalize).
@@ -595,6 +611,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, 
   const int LPAD = (L + 15) & ~15;
   uint8_t* pairs = reinterpret_cast<uint8_t*>(M + (int64_t)N * LPAD);   // (N-1) x N/2 x {p, q}
   const double tol = (double)L * 2.220446049250313e-16;
+  const double tol2 = tol * tol;
   constexpr int EPL = JMAX / 16;          // entries per lane of a column (LPAD <= 128)
   const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15, ngrp = blockDim.x >> 4;
   for (int idx = threadIdx.x; idx < N * LPAD; idx += blockDim.x) {
@@ -631,10 +648,15 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, 
         }
         a = row16_sum(a); bb = row16_sum(bb); g = row16_sum(g);
         // rotate unless the pair is orthogonal to working precision (L eps relative)
-        if ((g != 0.0) && (fabs(g) > tol * sqrt(a * bb))) {
-          const double zeta = (bb - a) / (2.0 * g);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
+        if ((g != 0.0) && (g * g > tol2 * (a * bb))) {
+          // zeta = (bb - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2):
+          // hardware reciprocal and reciprocal-sqrt estimates refined by Newton steps (a rotation
+          // only needs c^2 + s^2 = 1 to working precision)
+          const double zeta = fmin(fmax((bb - a) * rcp_nr(2.0 * g), -1e150), 1e150);
+          const double z2 = fma(zeta, zeta, 1.0);
+          const double rz = rsq_nr(z2);
+          const double t = copysign(1.0, zeta) * rcp_nr(fma(z2, rz, fabs(zeta)));
+          const double c = rsq_nr(fma(t, t, 1.0));
           const double s = c * t;
 #pragma unroll
           for (int e = 0; e < EPL; ++e) {
