@@ -26,6 +26,7 @@ namespace {
 
 constexpr double kGuardTau = 1e-10;
 constexpr int TPB = 256;
+constexpr int JMAX = 128;       // largest l (the small SVD holds an l x l matrix in one workgroup)
 
 inline int grid_for(int64_t work, int block = TPB, int cap = 65536) {
   int64_t g = cdiv<int64_t>(work, block);
@@ -187,31 +188,45 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
   }
 }
 
-// out (p x q, row-major, leading dimension ldo) = sum over chunks in chunk order; one workgroup per
-// row a: thread t adds chunks t, t + 256, ..., then the 256 partial sums are added in a fixed tree.
-__global__ __launch_bounds__(TPB) void k_tn_final(const double* __restrict__ part, int nchunks,
-                                                  int p, int q, double* __restrict__ out, int ldo,
-                                                  const Ctrl* __restrict__ ctrl, int iter) {
+// out (p x q, row-major, leading dimension ldo) = sum of the chunk partials.  A workgroup owns 64
+// output entries (one per lane, consecutive in part, so the loads coalesce); its 16 waves take the
+// chunks in interleaved order and their partial sums are added in wave order through LDS, so the
+// summation order is fixed.
+constexpr int kTnFinalThreads = 1024;
+__global__ __launch_bounds__(kTnFinalThreads) void k_tn_final(const double* __restrict__ part,
+                                                              int nchunks, int p, int q,
+                                                              double* __restrict__ out, int ldo,
+                                                              const Ctrl* __restrict__ ctrl,
+                                                              int iter) {
   if (skip_iter(ctrl, iter)) return;
-  __shared__ double sm[TPB];
-  const int a = blockIdx.x;
-  for (int c = 0; c < q; ++c) {
-    double s = 0;
-    for (int ch = threadIdx.x; ch < nchunks; ch += TPB) s += part[((int64_t)ch * p + a) * q + c];
-    sm[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = TPB / 2; o > 0; o >>= 1) {
-      if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
-      __syncthreads();
+  constexpr int NW = kTnFinalThreads / 64;
+  __shared__ double sm[NW * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane, pq = (int64_t)p * q;
+  const bool live = e < pq;
+  double s0 = 0, s1 = 0;
+  if (live) {
+    int ch = wave;
+    for (; ch + NW < nchunks; ch += 2 * NW) {
+      s0 += part[(int64_t)ch * pq + e];
+      s1 += part[(int64_t)(ch + NW) * pq + e];
     }
-    if (threadIdx.x == 0) out[a * ldo + c] = sm[0];
-    __syncthreads();
+    if (ch < nchunks) s0 += part[(int64_t)ch * pq + e];
+  }
+  sm[wave * 64 + lane] = s0 + s1;
+  __syncthreads();
+  if (wave == 0 && live) {
+    double s = sm[lane];
+    for (int w = 1; w < NW; ++w) s += sm[w * 64 + lane];
+    const int a = (int)(e / q), c = (int)(e % q);
+    out[a * ldo + c] = s;
   }
 }
 
 // out[c][r] = base[c][r] + alpha * sum_a X[a][r] W[a][c]  (W row-major p x q, ldw); base may be
 // null (taken as 0) and may alias out.  A workgroup owns 64 rows; its four waves take interleaved
-// ranges of a, and their partial sums are added in wave order through LDS.
+// ranges of a, and their partial sums are added in wave order through LDS.  W is staged in LDS
+// zero-padded to QMAX columns, so the inner loop has no per-column conditions.
 template <typename BT, int QMAX>
 __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int64_t ldo,
                                                    const BT* base, int64_t ldb,
@@ -220,39 +235,55 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
                                                    int q, int64_t rows, double alpha,
                                                    const Ctrl* __restrict__ ctrl, int iter) {
   if (skip_iter(ctrl, iter)) return;
-  extern __shared__ double ws[];              // p x q, then 3 x QMAX x 64 partials
-  double* part = ws + ((p * q + 1) & ~1);
+  extern __shared__ double ws[];              // p x QMAX, then 3 x QMAX x 64 partials
+  double* part = ws + p * QMAX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int idx = threadIdx.x; idx < p * q; idx += TPB) ws[idx] = W[(idx / q) * ldw + idx % q];
+  {
+    // all loads first (clamped to W[0], which always exists), then the LDS stores
+    constexpr int FILL = (JMAX * QMAX + TPB - 1) / TPB;
+    const int np = p * QMAX;
+    double wv[FILL];
+#pragma unroll
+    for (int u = 0; u < FILL; ++u) {
+      const int idx = threadIdx.x + u * TPB, a = idx / QMAX, c = idx % QMAX;
+      const bool in = idx < np && c < q;
+      const double v = W[in ? a * ldw + c : 0];
+      wv[u] = in ? v : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < FILL; ++u) {
+      const int idx = threadIdx.x + u * TPB;
+      if (idx < np) ws[idx] = wv[u];
+    }
+  }
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
   const bool live = r < rows;
+  const int64_t rc = live ? r : 0;
+  // every X value this lane needs (a = wave + 4 s < p), fetched in one batch with clamped addresses
+  constexpr int SMAX = JMAX / 4;
+  double x[SMAX];
+  const int plast = p > 0 ? p - 1 : 0;
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    const int a = wave + 4 * s;
+    const double v = X[(int64_t)(a < p ? a : plast) * ldx + rc];
+    x[s] = a < p ? v : 0.0;
+  }
   double acc[QMAX];
 #pragma unroll
   for (int c = 0; c < QMAX; ++c) acc[c] = 0.0;
-  if (live) {
-    int a = wave;
-    for (; a + 12 < p; a += 16) {            // four columns per wave per step, loads first
-      double x[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = X[(int64_t)(a + 4 * u) * ldx + r];
+  for (int s = 0; s < SMAX; ++s) {
+    const int a = wave + 4 * s;                 // uniform over the wave
+    if (a < p) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int c = 0; c < QMAX; ++c)
-          if (c < q) acc[c] = fma(x[u], ws[(a + 4 * u) * q + c], acc[c]);
-    }
-    for (; a < p; a += 4) {
-      const double x = X[(int64_t)a * ldx + r];
-#pragma unroll
-      for (int c = 0; c < QMAX; ++c)
-        if (c < q) acc[c] = fma(x, ws[a * q + c], acc[c]);
+      for (int c = 0; c < QMAX; ++c) acc[c] = fma(x[s], ws[a * QMAX + c], acc[c]);
     }
   }
   if (wave > 0) {
 #pragma unroll
-    for (int c = 0; c < QMAX; ++c)
-      if (c < q) part[((wave - 1) * QMAX + c) * 64 + lane] = acc[c];
+    for (int c = 0; c < QMAX; ++c) part[((wave - 1) * QMAX + c) * 64 + lane] = acc[c];
   }
   __syncthreads();
   if (wave == 0 && live) {
@@ -567,11 +598,166 @@ __global__ void k_rb_assemble(const double* __restrict__ C1, const double* __res
 }
 
 // ------------------------------------------------------------------------------------------------
+// Cholesky QR of B^T (shifted Cholesky QR3: Fukaya, Kannan, Nakatsukasa, Zhang, Yamamoto, SIAM J.
+// Sci. Comput. 42(1), 2020).  Only R_B is needed downstream (V is formed from B^T itself), and R_B
+// is a Cholesky factor of the L x L Gram matrix B B^T.  One Cholesky of the Gram matrix squares
+// the condition number, so three passes are made: the first on B B^T + s I with the shift
+// s = 11 (n L + L (L + 1)) u tr(B B^T) (u = 2^-53; the trace bounds ||B||_2^2), which keeps the
+// factorisation defined for cond(B) up to about 1/u and gives Q1 = B^T R1^-1 with a moderate
+// condition number; then Cholesky QR twice on Q1.  R_B = R3 R2 R1.  A pivot that is not positive
+// and finite in any pass sends the host to the Gram-Schmidt + TSQR path.
+constexpr int kCholThreads = 1024;
+constexpr int kCholSlots = JMAX / 32;        // rows / columns per thread of the 32 x 32 layout
+
+size_t chol_lds_bytes(int L) { return ((size_t)L * (L + 1) + 2 * (size_t)L) * sizeof(double); }
+
+// Gm (upper triangle read, row-major, leading dimension ldg) + s I = R^T R with R upper triangular
+// with a positive diagonal; s = shift_rel tr(Gm) when shift_rel > 0, else 0.  Writes R and, when
+// Rinv is non-null, R^-1 (row-major, leading dimension ldr, zeros below the diagonal).  A pivot that
+// is not positive and finite sets *fail (left as it was otherwise) and the outputs are unspecified.
+// One workgroup, threads in a 32 x 32 grid, each owning rows ty + 32 m and columns tx + 32 n of the
+// trailing block.  Right-looking factorisation in LDS, one row of R per step (rank-1 update of the
+// trailing upper triangle); then R^-1 by right-looking back substitution on the identity, one row
+// per step from the bottom, with R^-1[k][c] (k < c) kept in the strictly lower triangle at [c][k].
+// Every step loads its operands into registers before it stores, so the loads overlap.
+__global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict__ Gm, int ldg,
+                                                       int L, double shift_rel,
+                                                       double* __restrict__ R,
+                                                       double* __restrict__ Rinv, int ldr,
+                                                       int* __restrict__ fail) {
+  extern __shared__ double a[];     // L x (L + 1), then rd[L] (diag of R), dinv[L] (its inverse)
+  const int LS = L + 1, tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+  double* rd = a + (int64_t)L * LS;
+  double* dinv = rd + L;
+  for (int idx = tid; idx < L * L; idx += kCholThreads) {
+    const int i = idx / L, c = idx % L;
+    a[i * LS + c] = (c >= i) ? Gm[(int64_t)i * ldg + c] : 0.0;
+  }
+  __syncthreads();
+  if (shift_rel > 0.0) {
+    if (tid < 64) {
+      double t = 0.0;
+      for (int i = tid; i < L; i += 64) t += a[i * LS + i];
+      t = wave_sum(t);
+      if (tid == 0) rd[0] = t * shift_rel;
+    }
+    __syncthreads();
+    const double sh = rd[0];
+    __syncthreads();
+    for (int i = tid; i < L; i += kCholThreads) a[i * LS + i] += sh;
+    __syncthreads();
+  }
+  for (int j = 0; j < L; ++j) {
+    const double d = a[j * LS + j];            // same value in every thread: uniform exit
+    if (!(d > 0.0) || !(d < INFINITY)) {
+      if (tid == 0) *fail = 1;
+      return;
+    }
+    const double inv = 1.0 / sqrt(d);
+    if (tid == 0) rd[j] = sqrt(d);
+    if (j + 1 + tid < L) a[j * LS + j + 1 + tid] *= inv;
+    __syncthreads();
+    // a[i][c] -= a[j][i] a[j][c] for j < i <= c < L
+    double rc[kCholSlots];
+#pragma unroll
+    for (int n = 0; n < kCholSlots; ++n) {
+      const int c = j + 1 + tx + 32 * n;
+      rc[n] = c < L ? a[j * LS + c] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < kCholSlots; ++m) {
+      const int i = j + 1 + ty + 32 * m;
+      if (i < L) {
+        const double ri = a[j * LS + i];
+        double v[kCholSlots];
+#pragma unroll
+        for (int n = 0; n < kCholSlots; ++n) {
+          const int c = j + 1 + tx + 32 * n;
+          v[n] = (c >= i && c < L) ? a[i * LS + c] : 0.0;
+        }
+#pragma unroll
+        for (int n = 0; n < kCholSlots; ++n) {
+          const int c = j + 1 + tx + 32 * n;
+          if (c >= i && c < L) a[i * LS + c] = fma(-ri, rc[n], v[n]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < L; i += kCholThreads) dinv[i] = 1.0 / rd[i];
+  __syncthreads();
+  if (Rinv != nullptr) {
+    // Solve R X = I from the bottom: row i of X is final once rows i+1.. have been subtracted from
+    // it; X[i][c] = rhs[i][c] / R_ii, then rhs[k][c] -= R[k][i] X[i][c] for k < i, c >= i.
+    for (int i = L - 1; i >= 0; --i) {
+      if (i + 1 + tid < L) a[(i + 1 + tid) * LS + i] *= dinv[i];
+      __syncthreads();
+      double xc[kCholSlots];
+#pragma unroll
+      for (int n = 0; n < kCholSlots; ++n) {
+        const int c = i + tx + 32 * n;
+        xc[n] = c < L ? (c == i ? dinv[i] : a[c * LS + i]) : 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m < kCholSlots; ++m) {
+        const int k = ty + 32 * m;
+        if (k < i) {
+          const double rk = a[k * LS + i];
+          double v[kCholSlots];
+#pragma unroll
+          for (int n = 0; n < kCholSlots; ++n) {
+            const int c = i + tx + 32 * n;
+            v[n] = c < L ? a[c * LS + k] : 0.0;
+          }
+#pragma unroll
+          for (int n = 0; n < kCholSlots; ++n) {
+            const int c = i + tx + 32 * n;
+            if (c < L) a[c * LS + k] = fma(-rk, xc[n], v[n]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int idx = tid; idx < L * L; idx += kCholThreads) {
+    const int i = idx / L, c = idx % L;
+    R[(int64_t)i * ldr + c] = c > i ? a[i * LS + c] : (c == i ? rd[i] : 0.0);
+    if (Rinv != nullptr) Rinv[(int64_t)i * ldr + c] = c > i ? a[c * LS + i] : (c == i ? dinv[i] : 0.0);
+  }
+}
+
+// out = X Y for upper triangular L x L X and Y (row-major, leading dimension L); out must not
+// alias X or Y.  One workgroup per row i (row i of X staged in LDS), one thread per column; the
+// loads of Y are issued eight at a time.
+__global__ __launch_bounds__(JMAX) void k_trmm_upper(const double* __restrict__ X,
+                                                     const double* __restrict__ Y,
+                                                     double* __restrict__ out, int L) {
+  __shared__ double xs[JMAX];
+  const int i = blockIdx.x, c = threadIdx.x;
+  if (c < L) xs[c] = X[i * L + c];
+  __syncthreads();
+  if (c >= L) return;
+  double s = 0.0;
+  for (int k0 = i; k0 <= c; k0 += 8) {
+    double y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[u] = Y[(k0 + u <= c ? k0 + u : c) * L + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u <= c) s = fma(xs[k0 + u], y[u], s);
+  }
+  out[i * L + c] = s;
+}
+
+__global__ void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+// ------------------------------------------------------------------------------------------------
 // One-sided Jacobi on M = R_B^T (L x L, L = l_eff): columns of M are the rows of R_B.  Round-robin
 // ordering: in each of the N-1 rounds (N = L rounded up to even) the N/2 disjoint pairs are rotated
 // in parallel, one 16-lane row per pair.  Outputs: sig (descending), perm, W = M J (column perm[j]
 // holds sigma_j u_j).
-constexpr int JMAX = 128;
 constexpr int JSWEEPS = 40;
 
 __device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
@@ -596,77 +782,109 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return y;
 }
 
-// M (N columns padded to LP rows, zero beyond L) lives in LDS; the round-robin pair table is
-// precomputed once.  The right factor is not accumulated: with M J = W (orthogonal columns,
-// norms sigma), B^T = Q_B R_B and M = R_B^T, B^T W = Q_B J S^2, so V = B^T W S^-2 (see run_finalize).
-constexpr int kJacobiLds = 160 * 1024 - 1024;   // dynamic LDS limit of k_jacobi
+// 1/x from the hardware estimate and one Newton step (about 2^-46 relative): enough for a
+// rotation angle, which only steers convergence.
+__device__ __forceinline__ double rcp_nr1(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return y * fma(-x, y, 2.0);
+}
+__device__ __forceinline__ double rsq_nr1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
 
-__global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, int ldr, int L,
-                                                 double* __restrict__ W, int ldw,
-                                                 int* __restrict__ info, double* __restrict__ sig,
-                                                 int* __restrict__ perm, double* __restrict__ nrm) {
-  extern __shared__ double M[];           // N columns x LPAD rows, then the pair table
+// M (N columns, each padded to LPAD = 8 EPL rows, zero beyond L) lives in LDS with column stride
+// CS (LPAD, plus 8 when LPAD / 8 is even, so that the 8 pairs a wave touches spread over the LDS
+// banks); the round-robin pair table is precomputed once.  Eight lanes per pair, lane gl holding
+// rows gl + 8 e: the three inner products are reduced within the 8 lanes.  The right factor is not
+// accumulated: with M J = W (orthogonal columns, norms sigma), B^T = Q_B R_B and M = R_B^T,
+// B^T W = Q_B J S^2, so V = B^T W S^-2 (see run_finalize).
+constexpr int kJacobiLds = 160 * 1024 - 1024;   // dynamic LDS limit of k_jacobi
+constexpr int kJacobiLpp = 8;                   // lanes per pair
+constexpr int kJacobiThreads = 64 * kJacobiLpp; // one lane group per pair for N <= 128
+
+__host__ __device__ constexpr int jacobi_cs(int lpad) {
+  return ((lpad / kJacobiLpp) % 2 == 0) ? lpad + kJacobiLpp : lpad;
+}
+
+template <int EPL>
+__global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restrict__ RB, int ldr,
+                                                           int L, double* __restrict__ W, int ldw,
+                                                           int* __restrict__ info,
+                                                           double* __restrict__ sig,
+                                                           int* __restrict__ perm,
+                                                           double* __restrict__ nrm) {
+  extern __shared__ double M[];           // N columns x CS, then the pair table
   __shared__ int rotated;
+  constexpr int LPP = kJacobiLpp, LPAD = LPP * EPL, CS = jacobi_cs(LPAD);
   const int N = (L + 1) & ~1;
-  const int LPAD = (L + 15) & ~15;
-  uint8_t* pairs = reinterpret_cast<uint8_t*>(M + (int64_t)N * LPAD);   // (N-1) x N/2 x {p, q}
+  uint8_t* pairs = reinterpret_cast<uint8_t*>(M + (int64_t)N * CS);   // (N-1) x N/2 x {p, q}
   const double tol = (double)L * 2.220446049250313e-16;
   const double tol2 = tol * tol;
-  constexpr int EPL = JMAX / 16;          // entries per lane of a column (LPAD <= 128)
-  const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15, ngrp = blockDim.x >> 4;
-  for (int idx = threadIdx.x; idx < N * LPAD; idx += blockDim.x) {
+  const int grp = threadIdx.x / LPP, gl = threadIdx.x % LPP;
+  for (int idx = threadIdx.x; idx < N * LPAD; idx += kJacobiThreads) {
     const int col = idx / LPAD, i = idx % LPAD;
-    M[idx] = (col < L && i < L) ? RB[col * ldr + i] : 0.0;     // M(:, col) = R_B(col, :)^T
+    M[col * CS + i] = (col < L && i < L) ? RB[col * ldr + i] : 0.0;     // M(:, col) = R_B(col, :)^T
   }
-  for (int idx = threadIdx.x; idx < (N - 1) * (N / 2); idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < (N - 1) * (N / 2); idx += kJacobiThreads) {
     int p, q;
     rr_pair(N, idx / (N / 2), idx % (N / 2), p, q);
     pairs[2 * idx] = (uint8_t)p;
     pairs[2 * idx + 1] = (uint8_t)q;
   }
   __syncthreads();
-  const int nel = LPAD / 16;
+  const bool active = grp < N / 2;
   int sweep = 0;
   for (; sweep < JSWEEPS && N > 1; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
+    int p = 0, q = 0;
+    if (active) { p = pairs[2 * grp]; q = pairs[2 * grp + 1]; }
     for (int r = 0; r < N - 1; ++r) {
-      for (int k = grp; k < N / 2; k += ngrp) {
-        const int p = pairs[2 * (r * (N / 2) + k)], q = pairs[2 * (r * (N / 2) + k) + 1];
-        double* mp = M + p * LPAD + gl;
-        double* mq = M + q * LPAD + gl;
+      if (active) {
+        // the next round's pair (the table never changes), fetched ahead of this round's work
+        int pn = 0, qn = 0;
+        if (r + 1 < N - 1) {
+          const int pi = 2 * ((r + 1) * (N / 2) + grp);
+          pn = pairs[pi]; qn = pairs[pi + 1];
+        }
+        double* mp = M + p * CS + gl;
+        double* mq = M + q * CS + gl;
         double xp[EPL], xq[EPL];
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-          if (e < nel) { xp[e] = mp[16 * e]; xq[e] = mq[16 * e]; }
-          else { xp[e] = 0.0; xq[e] = 0.0; }
-        }
-        double a = 0, bb = 0, g = 0;
+        for (int e = 0; e < EPL; ++e) { xp[e] = mp[LPP * e]; xq[e] = mq[LPP * e]; }
+        double a0 = 0, a1 = 0, b0 = 0, b1 = 0, g0 = 0, g1 = 0;
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-          a = fma(xp[e], xp[e], a); bb = fma(xq[e], xq[e], bb); g = fma(xp[e], xq[e], g);
+        for (int e = 0; e < EPL; e += 2) {
+          a0 = fma(xp[e], xp[e], a0); b0 = fma(xq[e], xq[e], b0); g0 = fma(xp[e], xq[e], g0);
+          if (e + 1 < EPL) {
+            a1 = fma(xp[e + 1], xp[e + 1], a1); b1 = fma(xq[e + 1], xq[e + 1], b1);
+            g1 = fma(xp[e + 1], xq[e + 1], g1);
+          }
         }
-        a = row16_sum(a); bb = row16_sum(bb); g = row16_sum(g);
+        double a = a0 + a1, bb = b0 + b1, g = g0 + g1;
+        a += dpp::mov<dpp::kXor1>(a); bb += dpp::mov<dpp::kXor1>(bb); g += dpp::mov<dpp::kXor1>(g);
+        a += dpp::mov<dpp::kXor2>(a); bb += dpp::mov<dpp::kXor2>(bb); g += dpp::mov<dpp::kXor2>(g);
+        a += dpp::mov<dpp::kHalfMirror>(a); bb += dpp::mov<dpp::kHalfMirror>(bb);
+        g += dpp::mov<dpp::kHalfMirror>(g);
         // rotate unless the pair is orthogonal to working precision (L eps relative)
         if ((g != 0.0) && (g * g > tol2 * (a * bb))) {
-          // zeta = (bb - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2):
-          // hardware reciprocal and reciprocal-sqrt estimates refined by Newton steps (a rotation
-          // only needs c^2 + s^2 = 1 to working precision)
-          const double zeta = fmin(fmax((bb - a) * rcp_nr(2.0 * g), -1e150), 1e150);
+          // zeta = (bb - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)): the angle from
+          // one-step refined estimates; c = 1/sqrt(1+t^2) to full precision and s = c t, so
+          // c^2 + s^2 = 1 to working precision whatever the accuracy of t
+          const double zeta = fmin(fmax((bb - a) * rcp_nr1(2.0 * g), -1e150), 1e150);
           const double z2 = fma(zeta, zeta, 1.0);
-          const double rz = rsq_nr(z2);
-          const double t = copysign(1.0, zeta) * rcp_nr(fma(z2, rz, fabs(zeta)));
+          const double t = copysign(1.0, zeta) * rcp_nr1(fma(z2, rsq_nr1(z2), fabs(zeta)));
           const double c = rsq_nr(fma(t, t, 1.0));
           const double s = c * t;
 #pragma unroll
           for (int e = 0; e < EPL; ++e) {
-            if (e < nel) {
-              mp[16 * e] = c * xp[e] - s * xq[e];
-              mq[16 * e] = s * xp[e] + c * xq[e];
-            }
+            mp[LPP * e] = c * xp[e] - s * xq[e];
+            mq[LPP * e] = s * xp[e] + c * xq[e];
           }
           if (gl == 0) rotated = 1;
         }
+        p = pn; q = qn;
       }
       __syncthreads();
     }
@@ -674,23 +892,33 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ RB, 
     __syncthreads();
   }
   if (threadIdx.x == 0) info[0] = sweep;
-  for (int col = threadIdx.x; col < L; col += blockDim.x) {
+  for (int col = threadIdx.x; col < L; col += kJacobiThreads) {
     double s = 0;
-    for (int i = 0; i < L; ++i) s = fma(M[col * LPAD + i], M[col * LPAD + i], s);
+    for (int i = 0; i < L; ++i) s = fma(M[col * CS + i], M[col * CS + i], s);
     nrm[col] = sqrt(s);
   }
   __syncthreads();
-  for (int col = threadIdx.x; col < L; col += blockDim.x) {
+  for (int col = threadIdx.x; col < L; col += kJacobiThreads) {
     int rank = 0;
     for (int o = 0; o < L; ++o)
       rank += (nrm[o] > nrm[col]) || (nrm[o] == nrm[col] && o < col);
     sig[rank] = nrm[col];
     perm[rank] = col;
   }
-  for (int idx = threadIdx.x; idx < L * L; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < L * L; idx += kJacobiThreads) {
     const int col = idx / L, i = idx % L;
-    W[i * ldw + col] = M[col * LPAD + i];   // W row-major L x L
+    W[i * ldw + col] = M[col * CS + i];   // W row-major L x L
   }
+}
+
+// EPL (rows per lane) for L: LPAD = 8 EPL >= L.
+inline int jacobi_epl(int L) {
+  const int need = cdiv(L, kJacobiLpp);
+  return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 14 ? 14 : 16;
+}
+size_t jacobi_lds_bytes(int L) {
+  const int N = (L + 1) & ~1, CS = jacobi_cs(kJacobiLpp * jacobi_epl(L));
+  return (size_t)N * CS * sizeof(double) + (size_t)(N - 1) * (N / 2) * 2 + 16;
 }
 
 // Gather the k leading factors: Wk = W(:, perm[0:kk]) / sig (U = Q Wk) and
@@ -818,40 +1046,48 @@ struct Ctx {
   void chk() { if (err == hipSuccess) err = hipGetLastError(); }
 };
 
-constexpr int kTnRows = 512;     // rows per workgroup of the row reductions
+// Row reductions: chunks of a multiple of 16 rows, at most kTnChunks of them (enough workgroups
+// to fill the chip; the partials stay small next to the rows read).
+constexpr int kTnChunks = 512;
+inline int tn_rows_per_chunk(int64_t rows) {
+  const int64_t r = rup<int64_t>(cdiv<int64_t>(rows, kTnChunks), 16);
+  return (int)(r < 64 ? 64 : r);
+}
 
 template <int MT>
 void tn_launch(Ctx& cx, int nq, dim3 grid, const double* X, int64_t ldx, const double* Y,
-               int64_t ldy, int p, int q, int64_t rows, double* part, const Ctrl* ctrl, int iter) {
+               int64_t ldy, int p, int q, int64_t rows, int rch, double* part, const Ctrl* ctrl,
+               int iter) {
   if (nq == 1)
     hipLaunchKernelGGL((k_tn_mfma<MT, 1>), grid, dim3(TPB), 0, cx.s, X, ldx, Y, ldy, p, q, rows,
-                       kTnRows, part, ctrl, iter);
+                       rch, part, ctrl, iter);
   else
     hipLaunchKernelGGL((k_tn_mfma<MT, 2>), grid, dim3(TPB), 0, cx.s, X, ldx, Y, ldy, p, q, rows,
-                       kTnRows, part, ctrl, iter);
+                       rch, part, ctrl, iter);
 }
 
 // out (p x q row-major, ldo) = X[:, 0:p]^T Y[:, 0:q] over `rows` rows (p <= 128, q <= 32).
 void tn(Ctx& cx, const double* X, int64_t ldx, const double* Y, int64_t ldy, int p, int q,
         int64_t rows, double* part, double* out, int ldo, const Ctrl* ctrl, int iter) {
   if (!cx.ok() || p == 0 || q == 0) return;
-  const int nch = (int)cdiv<int64_t>(rows, kTnRows);
+  const int rch = tn_rows_per_chunk(rows);
+  const int nch = (int)cdiv<int64_t>(rows, rch);
   const int mt = cdiv(p, 16), nq = cdiv(q, 16);
   const dim3 grid(nch);
   switch (mt) {
-    case 1: tn_launch<1>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
-    case 2: tn_launch<2>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
-    case 3: tn_launch<3>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
-    case 4: tn_launch<4>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
-    case 5: tn_launch<5>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
-    case 6: tn_launch<6>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
-    case 7: tn_launch<7>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
-    default: tn_launch<8>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter); break;
+    case 1: tn_launch<1>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
+    case 2: tn_launch<2>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
+    case 3: tn_launch<3>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
+    case 4: tn_launch<4>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
+    case 5: tn_launch<5>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
+    case 6: tn_launch<6>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
+    case 7: tn_launch<7>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
+    default: tn_launch<8>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
   }
   cx.chk();
   if (!cx.ok()) return;
-  hipLaunchKernelGGL(k_tn_final, dim3(p), dim3(TPB), 0, cx.s, part, nch, p, q, out, ldo, ctrl,
-                     iter);
+  hipLaunchKernelGGL(k_tn_final, dim3(cdiv(p * q, 64)), dim3(kTnFinalThreads), 0, cx.s, part, nch,
+                     p, q, out, ldo, ctrl, iter);
   cx.chk();
 }
 
@@ -861,7 +1097,7 @@ void nn(Ctx& cx, double* out, int64_t ldo, const BT* base, int64_t ldb, const do
         const Ctrl* ctrl, int iter) {
   if (!cx.ok() || q == 0 || rows == 0) return;
   const int qmax = q <= 8 ? 8 : (q <= 16 ? 16 : 32);
-  const size_t shm = (size_t)(((p * q + 1) & ~1) + 3 * qmax * 64) * sizeof(double);
+  const size_t shm = (size_t)(p * qmax + 3 * qmax * 64) * sizeof(double);
   const dim3 g((unsigned)cdiv<int64_t>(rows, 64)), blk(TPB);
   if (q <= 8)
     hipLaunchKernelGGL((k_nn_update<BT, 8>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p, W,
@@ -955,11 +1191,94 @@ Small carve_small(double* base, int l, int b) {
   return sm;
 }
 
+// Gram matrix X^T X (L x L, upper triangle, row-major, leading dimension L) of the n x L
+// column-major X, in column slices of at most 32.
+void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, double* red_ws,
+                double* Gm) {
+  for (int c0 = 0; c0 < L && cx.ok(); c0 += 32) {
+    const int w = (L - c0 < 32) ? (L - c0) : 32;
+    tn(cx, X, ldx, X + (int64_t)c0 * ldx, ldx, c0 + w, w, rows, red_ws, Gm + c0, L, nullptr, 0);
+  }
+}
+
+// Y = X R^-1 for the n x L column-major X and upper triangular R^-1 (row-major, leading dimension
+// L), in column slices of at most 32 (slice c0..c0+w-1 only needs rows 0..c0+w-1 of R^-1).
+void right_trmul(Ctx& cx, double* Y, int64_t ldy, const double* X, int64_t ldx, int64_t rows,
+                 int L, const double* Rinv) {
+  for (int c0 = 0; c0 < L && cx.ok(); c0 += 32) {
+    const int w = (L - c0 < 32) ? (L - c0) : 32;
+    nn<double>(cx, Y + (int64_t)c0 * ldy, ldy, (const double*)nullptr, 0, X, ldx, c0 + w,
+               Rinv + c0, L, w, rows, 1.0, nullptr, 0);
+  }
+}
+
+void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double* Rinv, int* fail) {
+  if (!cx.ok()) return;
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), chol_lds_bytes(L), cx.s, Gm, L, L,
+                     shift_rel, R, Rinv, L, fail);
+  cx.chk();
+}
+
+// R_B of B^T = Q_B R_B by shifted Cholesky QR3 (see k_chol).  Returns the device matrix holding R_B
+// (row-major L x L), or nullptr when a pivot failed (then the caller factors B^T another way).
+// Q1 goes to the Q_B storage and Q2 to the H storage (H is no longer needed at this point).
+const double* chol_qr3(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
+  const int64_t n = f.n;
+  double* Gm = sm.Jm;
+  double* Rs = sm.Wm;
+  double* Ri = sm.Jk;
+  double* Racc = sm.Wk;
+  double* Q2 = const_cast<double*>(f.H);
+  int* fail = sm.info + 1;
+  const double u = 1.1102230246251565e-16;     // 2^-53
+  const double shift_rel = 11.0 * ((double)n * L + (double)L * (L + 1)) * u;
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, fail, 0);
+  cx.chk();
+  // pass 1: B^T = Q1 R1 (shifted)
+  gram_upper(cx, f.Bt, f.ldb, n, L, f.red_ws, Gm);
+  chol(cx, Gm, L, shift_rel, Racc, Ri, fail);
+  right_trmul(cx, f.Qb, f.ldb, f.Bt, f.ldb, n, L, Ri);
+  // pass 2: Q1 = Q2 R2
+  gram_upper(cx, f.Qb, f.ldb, n, L, f.red_ws, Gm);
+  chol(cx, Gm, L, 0.0, Rs, Ri, fail);
+  right_trmul(cx, Q2, f.ldh, f.Qb, f.ldb, n, L, Ri);
+  if (!cx.ok()) return nullptr;
+  hipLaunchKernelGGL(k_trmm_upper, dim3(L), dim3(JMAX), 0, cx.s, Rs, Racc, sm.RB, L);
+  cx.chk();
+  // pass 3: Q2 = Q3 R3; R_B = R3 R2 R1
+  gram_upper(cx, Q2, f.ldh, n, L, f.red_ws, Gm);
+  chol(cx, Gm, L, 0.0, Rs, nullptr, fail);
+  if (!cx.ok()) return nullptr;
+  hipLaunchKernelGGL(k_trmm_upper, dim3(L), dim3(JMAX), 0, cx.s, Rs, sm.RB, Racc, L);
+  cx.chk();
+  int hfail = 1;
+  if (cx.ok()) cx.err = hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, cx.s);
+  if (cx.ok()) cx.err = hipStreamSynchronize(cx.s);
+  if (!cx.ok() || hfail != 0) return nullptr;
+  return Racc;
+}
+
 }  // namespace
 
 hipError_t finalize_prepare() {
-  return hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             kJacobiLds);
+  hipError_t e = hipSuccess;
+  for (const void* kj : {(const void*)k_jacobi<2>, (const void*)k_jacobi<4>,
+                         (const void*)k_jacobi<8>, (const void*)k_jacobi<12>,
+                         (const void*)k_jacobi<14>, (const void*)k_jacobi<16>})
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(kj, hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiLds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)chol_lds_bytes(JMAX));
+  // W (p x 32, p <= JMAX) plus the partial sums exceed 64 KB for the widest products
+  const int nn32 = (int)((JMAX * 32 + 3 * 32 * 64) * sizeof(double));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_nn_update<double, 32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, nn32);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_nn_update<float, 32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, nn32);
+  return e;
 }
 
 size_t finalize_small_elems(int l, int b) {
@@ -984,7 +1303,11 @@ size_t tsqr_workspace_elems(int64_t rows, int b) {
 }
 
 size_t reduce_workspace_elems(int64_t rows, int p, int q) {
-  return (size_t)(cdiv<int64_t>(rows, kTnRows) * p * 32) + 64;
+  (void)q;
+  // any row count up to `rows` splits into at most this many chunks (chunks hold >= 64 rows)
+  const int64_t c64 = cdiv<int64_t>(rows, 64);
+  const int64_t nch = c64 < kTnChunks ? c64 : kTnChunks;
+  return (size_t)(nch * p * 32) + 64;
 }
 
 hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
@@ -1056,29 +1379,48 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
   const int kk = (f.k < L) ? f.k : L;
 
   if (L > 0) {
-    // ---------------- B^T = Q_B R_B (panels of width b, re-orthogonalised)
-    cx.err = launch_fill_f64(sm.RB, (int64_t)L * L, 0.0, stream);
-    for (int c0 = 0; c0 < L && cx.ok(); c0 += b) {
-      const int w = (L - c0 < b) ? (L - c0) : b;
-      double* Qp = f.Qb + (int64_t)c0 * f.ldb;
-      const double* Bp = f.Bt + (int64_t)c0 * f.ldb;
-      tn(cx, f.Qb, f.ldb, Bp, f.ldb, c0, w, n, f.red_ws, sm.C1, w, nullptr, 0);
-      nn<double>(cx, Qp, f.ldb, Bp, f.ldb, f.Qb, f.ldb, c0, sm.C1, w, w, n, -1.0, nullptr, 0);
-      tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R1, nullptr, 0);
-      tn(cx, f.Qb, f.ldb, Qp, f.ldb, c0, w, n, f.red_ws, sm.C2, w, nullptr, 0);
-      nn<double>(cx, Qp, f.ldb, Qp, f.ldb, f.Qb, f.ldb, c0, sm.C2, w, w, n, -1.0, nullptr, 0);
-      tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R2, nullptr, 0);
-      if (!cx.ok()) break;
-      hipLaunchKernelGGL(k_rb_assemble, dim3(1), dim3(256), 0, stream, sm.C1, sm.C2, sm.R1, sm.R2,
-                         sm.RB, L, c0, w);
-      cx.chk();
-    }
+    // ---------------- R_B: shifted Cholesky QR3 of B^T; Gram-Schmidt + TSQR if a pivot fails
+    const double* RBp = chol_qr3(cx, f, sm, L);
     if (!cx.ok()) return cx.err;
+    if (RBp == nullptr) {
+      RBp = sm.RB;
+      cx.err = launch_fill_f64(sm.RB, (int64_t)L * L, 0.0, stream);
+      for (int c0 = 0; c0 < L && cx.ok(); c0 += b) {
+        const int w = (L - c0 < b) ? (L - c0) : b;
+        double* Qp = f.Qb + (int64_t)c0 * f.ldb;
+        const double* Bp = f.Bt + (int64_t)c0 * f.ldb;
+        tn(cx, f.Qb, f.ldb, Bp, f.ldb, c0, w, n, f.red_ws, sm.C1, w, nullptr, 0);
+        nn<double>(cx, Qp, f.ldb, Bp, f.ldb, f.Qb, f.ldb, c0, sm.C1, w, w, n, -1.0, nullptr, 0);
+        tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R1, nullptr, 0);
+        tn(cx, f.Qb, f.ldb, Qp, f.ldb, c0, w, n, f.red_ws, sm.C2, w, nullptr, 0);
+        nn<double>(cx, Qp, f.ldb, Qp, f.ldb, f.Qb, f.ldb, c0, sm.C2, w, w, n, -1.0, nullptr, 0);
+        tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R2, nullptr, 0);
+        if (!cx.ok()) break;
+        hipLaunchKernelGGL(k_rb_assemble, dim3(1), dim3(256), 0, stream, sm.C1, sm.C2, sm.R1,
+                           sm.R2, sm.RB, L, c0, w);
+        cx.chk();
+      }
+      if (!cx.ok()) return cx.err;
+    }
     // ---------------- Jacobi SVD of R_B^T
-    const int N = (L + 1) & ~1, LPAD = (L + 15) & ~15;
-    const size_t jshm = (size_t)N * LPAD * sizeof(double) + (size_t)(N - 1) * (N / 2) * 2 + 16;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), jshm, stream, sm.RB, L, L, sm.Wm, L,
-                       sm.info, sm.sig, sm.perm, sm.Jm);
+    {
+      const size_t jshm = jacobi_lds_bytes(L);
+      const dim3 g1(1), bj(kJacobiThreads);
+      switch (jacobi_epl(L)) {
+        case 2: hipLaunchKernelGGL(k_jacobi<2>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info,
+                                   sm.sig, sm.perm, sm.Jm); break;
+        case 4: hipLaunchKernelGGL(k_jacobi<4>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info,
+                                   sm.sig, sm.perm, sm.Jm); break;
+        case 8: hipLaunchKernelGGL(k_jacobi<8>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info,
+                                   sm.sig, sm.perm, sm.Jm); break;
+        case 12: hipLaunchKernelGGL(k_jacobi<12>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
+                                    sm.info, sm.sig, sm.perm, sm.Jm); break;
+        case 14: hipLaunchKernelGGL(k_jacobi<14>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
+                                    sm.info, sm.sig, sm.perm, sm.Jm); break;
+        default: hipLaunchKernelGGL(k_jacobi<16>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
+                                    sm.info, sm.sig, sm.perm, sm.Jm); break;
+      }
+    }
     cx.chk();
     if (!cx.ok()) return cx.err;
     hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, stream, sm.Wm, L, L, sm.perm, sm.sig, kk,
