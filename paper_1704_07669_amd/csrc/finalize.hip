@@ -507,6 +507,23 @@ __global__ __launch_bounds__(TPB) void k_house_form(double* __restrict__ X, int6
 // Small b x b / p x b kernels (one workgroup).
 
 // R = R2 R1 (upper triangular), then the rank guard of the column-block loop.
+// Rank guard on the combined R_i (b x b, row-major): the leading columns whose diagonal exceeds
+// kGuardTau r0 are kept (r0 = R_0[0][0]); the first iteration that keeps fewer than b is the last.
+__device__ void guard_apply(const double* R, int b, int iter, Ctrl* ctrl) {
+  if (iter == 0) ctrl->r0 = R[0];
+  const double thr = kGuardTau * ctrl->r0;
+  int keep = 0;
+  while (keep < b && fabs(R[keep * b + keep]) > thr) ++keep;
+  if (keep < b) {
+    ctrl->last_iter = iter;
+    ctrl->keep_last = keep;
+    ctrl->l_eff = iter * b + keep;
+  } else {
+    ctrl->l_eff = (iter + 1) * b;
+    ctrl->keep_last = b;
+  }
+}
+
 __global__ void k_guard(const double* __restrict__ R1, const double* __restrict__ R2,
                         double* __restrict__ R, int b, int iter, int t, Ctrl* __restrict__ ctrl) {
   if (skip_iter(ctrl, iter)) return;
@@ -517,20 +534,136 @@ __global__ void k_guard(const double* __restrict__ R1, const double* __restrict_
     R[idx] = (c >= i) ? s : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    if (iter == 0) ctrl->r0 = R[0];
-    const double thr = kGuardTau * ctrl->r0;
-    int keep = 0;
-    while (keep < b && fabs(R[keep * b + keep]) > thr) ++keep;
-    if (keep < b) {
-      ctrl->last_iter = iter;
-      ctrl->keep_last = keep;
-      ctrl->l_eff = iter * b + keep;
-    } else {
-      ctrl->l_eff = (iter + 1) * b;
-      ctrl->keep_last = b;
-    }
+  if (threadIdx.x == 0) guard_apply(R, b, iter, ctrl);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Cholesky QR of one column block (the panels of the loop above, b <= 32 columns): with the block
+// Gram matrix G = Y^T Y = R^T R, Y R^-1 has orthonormal columns up to O(u cond(Y)^2).  The loop
+// uses one such step on Y and two on the projected Z = Q_i - Q C (Eq. 7), which brings Z to
+// orthonormality at working precision whenever cond(Z) is below about 1/sqrt(u); R_i is the
+// product of the three factors.  A block whose Gram matrix has a pivot below kCholQrPivot G_jj
+// (its columns are too close to dependent for the Gram matrix to resolve) or a non-finite pivot is
+// flagged in ctrl->pad[0], and the host repeats the whole loop with Householder TSQR.
+constexpr double kCholQrPivot = 1e-10;
+
+// Y <- Y R^-1 in place for G = R^T R (b x b, row-major, leading dimension b, upper triangle read).
+// Every workgroup factors G itself in LDS (b steps, all threads), so the factorisation needs no
+// launch of its own and all workgroups apply the same R^-1.  Workgroup 0 writes Rout = R Rprev
+// (Rprev null: identity) and, when `last` is set, applies the rank guard to Rout and forms
+// Wn = T + W (p x b, the combined weights of the numerator of Eq. 9).
+template <int BMAX>
+__global__ __launch_bounds__(TPB) void k_cholqr_apply(double* __restrict__ Y, int64_t ldy,
+                                                      int64_t rows, const double* __restrict__ G,
+                                                      int b, const double* __restrict__ Rprev,
+                                                      double* __restrict__ Rout, int last,
+                                                      const double* __restrict__ T,
+                                                      const double* __restrict__ Wt,
+                                                      double* __restrict__ Wn, int p,
+                                                      Ctrl* __restrict__ ctrl, int iter) {
+  if (skip_iter(ctrl, iter)) return;
+  constexpr int LS = BMAX + 1, SL = (BMAX + 15) / 16;   // SL: slots per thread of the 16 x 16 grid
+  __shared__ double a[BMAX * LS];     // G -> R (upper), R^-1 (strictly lower, transposed)
+  __shared__ double rd[BMAX], dinv[BMAX], gd[BMAX];
+  __shared__ double rp[BMAX * BMAX];
+  __shared__ int bad;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const int64_t r = (int64_t)blockIdx.x * TPB + tid;
+  // this thread's row of Y, fetched before the factorisation so the load overlaps it
+  double y[BMAX];
+  const int64_t rc = r < rows ? r : 0;
+#pragma unroll
+  for (int c = 0; c < BMAX; ++c) {
+    const double v = Y[(c < b ? c : 0) * ldy + rc];
+    y[c] = (c < b) ? v : 0.0;
   }
+  for (int idx = tid; idx < BMAX * BMAX; idx += TPB) {
+    const int i = idx / BMAX, c = idx % BMAX;
+    const double g = (i < b && c < b && c >= i) ? G[i * b + c] : 0.0;
+    a[i * LS + c] = g;
+    if (i == c) gd[i] = g;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < b; ++j) {
+    const double d = a[j * LS + j];
+    if (!(d > kCholQrPivot * gd[j]) || !(d < INFINITY)) {   // uniform: every thread sees d
+      if (tid == 0) bad = 1;
+      break;
+    }
+    const double inv = 1.0 / sqrt(d);
+    if (tid == 0) rd[j] = sqrt(d);
+    if (j + 1 + tid < b) a[j * LS + j + 1 + tid] *= inv;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < SL; ++m) {
+      const int i = j + 1 + ty + 16 * m;
+#pragma unroll
+      for (int n = 0; n < SL; ++n) {
+        const int c = j + 1 + tx + 16 * n;
+        if (i < b && c < b && c >= i) a[i * LS + c] = fma(-a[j * LS + i], a[j * LS + c], a[i * LS + c]);
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (bad) {
+    if (blockIdx.x == 0 && tid == 0) ctrl->pad[0] = 1;
+    return;
+  }
+  for (int i = tid; i < b; i += TPB) dinv[i] = 1.0 / rd[i];
+  __syncthreads();
+  // R^-1 by back substitution from the bottom row; R^-1[k][c] (k < c) stored at a[c][k]
+  for (int i = b - 1; i >= 0; --i) {
+    if (i + 1 + tid < b) a[(i + 1 + tid) * LS + i] *= dinv[i];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < SL; ++m) {
+      const int k = ty + 16 * m;
+#pragma unroll
+      for (int n = 0; n < SL; ++n) {
+        const int c = i + tx + 16 * n;
+        if (k < i && c < b) {
+          const double xc = (c == i) ? dinv[i] : a[c * LS + i];
+          a[c * LS + k] = fma(-a[k * LS + i], xc, a[c * LS + k]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // out_c = sum_{k <= c} y_k R^-1[k][c]
+  if (r < rows) {
+    double o[BMAX];
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c) o[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < BMAX; ++k) {
+      if (k < b) {
+#pragma unroll
+        for (int c = k; c < BMAX; ++c) o[c] = fma(y[k], (c == k) ? dinv[c] : a[c * LS + k], o[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c)
+      if (c < b) Y[c * ldy + r] = o[c];
+  }
+  if (blockIdx.x != 0) return;
+  // Rout = R Rprev (upper triangular), then the guard and Wn on the last step
+  for (int idx = tid; idx < b * b; idx += TPB) {
+    const int i = idx / b, c = idx % b;
+    double s = 0.0;
+    if (c >= i) {
+      if (Rprev == nullptr) s = (c == i) ? rd[i] : a[i * LS + c];
+      else
+        for (int k = i; k <= c; ++k) s = fma(k == i ? rd[i] : a[i * LS + k], Rprev[k * b + c], s);
+    }
+    rp[idx] = s;
+    Rout[idx] = s;
+  }
+  if (!last) return;
+  for (int idx = tid; idx < p * b; idx += TPB) Wn[idx] = T[idx] + Wt[idx];
+  __syncthreads();
+  if (tid == 0) guard_apply(rp, b, iter, ctrl);
 }
 
 // out = A + B (p x q, row-major with leading dimension q)
@@ -1034,6 +1167,7 @@ __global__ void k_init_ctrl(Ctrl* ctrl, int t, int l) {
     ctrl->keep_last = 0;
     ctrl->l_eff = l;
     ctrl->nonfinite = nf;
+    ctrl->pad[0] = 0;          // set by a Cholesky QR step that cannot be trusted
   }
 }
 
@@ -1191,6 +1325,25 @@ Small carve_small(double* base, int l, int b) {
   return sm;
 }
 
+// One Cholesky QR step of the column block Y (rows x b, in place), see k_cholqr_apply.
+void cholqr(Ctx& cx, double* Y, int64_t ldy, int64_t rows, const double* G, int b,
+            const double* Rprev, double* Rout, bool last, const Small& sm, int p, Ctrl* ctrl,
+            int iter) {
+  if (!cx.ok()) return;
+  const dim3 g((unsigned)cdiv<int64_t>(rows, TPB)), blk(TPB);
+  const int lf = last ? 1 : 0;
+  if (b <= 8)
+    hipLaunchKernelGGL(k_cholqr_apply<8>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
+                       sm.T, sm.W, sm.Wn, p, ctrl, iter);
+  else if (b <= 16)
+    hipLaunchKernelGGL(k_cholqr_apply<16>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
+                       sm.T, sm.W, sm.Wn, p, ctrl, iter);
+  else
+    hipLaunchKernelGGL(k_cholqr_apply<32>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
+                       sm.T, sm.W, sm.Wn, p, ctrl, iter);
+  cx.chk();
+}
+
 // Gram matrix X^T X (L x L, upper triangle, row-major, leading dimension L) of the n x L
 // column-major X, in column slices of at most 32.
 void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, double* red_ws,
@@ -1317,56 +1470,79 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
   Small sm = carve_small(f.small, l, b);
   Ctrl* ctrl = f.ctrl;
 
-  hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l);
-  cx.chk();
-
-  // ---------------- column-block loop (Alg. 4 steps 9-15)
-  for (int i = 0; i < t && cx.ok(); ++i) {
-    const int c0 = i * b, p = c0;
-    double* Qi = f.Q + (int64_t)c0 * f.ldq;
-    // W = B Omega_i  (B^T is n x p)
-    tn(cx, f.Bt, f.ldb, f.om64 + (int64_t)c0 * f.ldo, f.ldo, p, b, n, f.red_ws, sm.W, b, ctrl, i);
-    // Y = G(:, c) - Q W, formed in the basis slot of Q_i
-    if (f.mode == M_F64)
-      nn<double>(cx, Qi, f.ldq, (const double*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
-                 sm.W, b, b, m, -1.0, ctrl, i);
-    else
-      nn<float>(cx, Qi, f.ldq, (const float*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
-                sm.W, b, b, m, -1.0, ctrl, i);
-    // T = Q^T Y
-    tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.T, b, ctrl, i);
-    // [Q_i, R_i] = qr(Y), in place
-    tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R1, ctrl, i);
-    // C = Q^T Q_i; Q_i <- Q_i - Q C; [Q_i, R~_i] = qr(Q_i)
-    tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
-    nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
-    tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R2, ctrl, i);
-    if (!cx.ok()) break;
-    // R_i = R~_i R_i and the rank guard
-    hipLaunchKernelGGL(k_guard, dim3(1), dim3(256), 0, stream, sm.R1, sm.R2, sm.R, b, i, t, ctrl);
+  // ---------------- column-block loop (Alg. 4 steps 9-15).  Cholesky QR of the blocks first; if a
+  // block was flagged as too ill-conditioned for it, the loop is repeated with Householder TSQR.
+  for (int attempt = 0; attempt < 2 && cx.ok(); ++attempt) {
+    const bool chol = (attempt == 0);
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l);
     cx.chk();
-    hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((int64_t)b * m)), dim3(TPB), 0, stream, f.Q,
-                       f.ldq, m, c0, b, ctrl, i);
-    cx.chk();
-    // N = H(:, c) - B^T (T + W);  B_i^T = N R_i^{-1}
-    if (p > 0) {
-      hipLaunchKernelGGL(k_add_small, dim3(1), dim3(256), 0, stream, sm.T, sm.W, sm.Wn, p * b,
-                         ctrl, i);
+    for (int i = 0; i < t && cx.ok(); ++i) {
+      const int c0 = i * b, p = c0;
+      double* Qi = f.Q + (int64_t)c0 * f.ldq;
+      // W = B Omega_i  (B^T is n x p)
+      tn(cx, f.Bt, f.ldb, f.om64 + (int64_t)c0 * f.ldo, f.ldo, p, b, n, f.red_ws, sm.W, b, ctrl, i);
+      // Y = G(:, c) - Q W, formed in the basis slot of Q_i
+      if (f.mode == M_F64)
+        nn<double>(cx, Qi, f.ldq, (const double*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
+                   sm.W, b, b, m, -1.0, ctrl, i);
+      else
+        nn<float>(cx, Qi, f.ldq, (const float*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
+                  sm.W, b, b, m, -1.0, ctrl, i);
+      if (chol) {
+        // [T; Y^T Y] = [Q, Y]^T Y in one reduction (Q and the slot of Q_i are adjacent)
+        tn(cx, f.Q, f.ldq, Qi, f.ldq, p + b, b, m, f.red_ws, sm.T, b, ctrl, i);
+        cholqr(cx, Qi, f.ldq, m, sm.T + (int64_t)p * b, b, nullptr, sm.R1, false, sm, p, ctrl, i);
+        // C = Q^T Q_i; Z = Q_i - Q C; two Cholesky QR steps on Z
+        tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
+        nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+        tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C1, b, ctrl, i);
+        cholqr(cx, Qi, f.ldq, m, sm.C1, b, sm.R1, sm.R2, false, sm, p, ctrl, i);
+        tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C2, b, ctrl, i);
+        cholqr(cx, Qi, f.ldq, m, sm.C2, b, sm.R2, sm.R, true, sm, p, ctrl, i);
+        if (!cx.ok()) break;
+      } else {
+        // T = Q^T Y
+        tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.T, b, ctrl, i);
+        // [Q_i, R_i] = qr(Y), in place
+        tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R1, ctrl, i);
+        // C = Q^T Q_i; Q_i <- Q_i - Q C; [Q_i, R~_i] = qr(Q_i)
+        tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
+        nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+        tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R2, ctrl, i);
+        if (!cx.ok()) break;
+        // R_i = R~_i R_i and the rank guard
+        hipLaunchKernelGGL(k_guard, dim3(1), dim3(256), 0, stream, sm.R1, sm.R2, sm.R, b, i, t,
+                           ctrl);
+        cx.chk();
+        if (p > 0) {
+          hipLaunchKernelGGL(k_add_small, dim3(1), dim3(256), 0, stream, sm.T, sm.W, sm.Wn, p * b,
+                             ctrl, i);
+          cx.chk();
+        }
+      }
+      hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((int64_t)b * m)), dim3(TPB), 0, stream, f.Q,
+                         f.ldq, m, c0, b, ctrl, i);
+      cx.chk();
+      // N = H(:, c) - B^T (T + W);  B_i^T = N R_i^{-1}
+      nn<double>(cx, f.Wn, f.ldb, f.H + (int64_t)c0 * f.ldh, f.ldh, f.Bt, f.ldb, p, sm.Wn, b, b, n,
+                 -1.0, ctrl, i);
+      if (!cx.ok()) break;
+      if (b <= 8)
+        hipLaunchKernelGGL(k_trsm_rows<8>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
+                           sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
+      else if (b <= 16)
+        hipLaunchKernelGGL(k_trsm_rows<16>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
+                           sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
+      else
+        hipLaunchKernelGGL(k_trsm_rows<32>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
+                           sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
       cx.chk();
     }
-    nn<double>(cx, f.Wn, f.ldb, f.H + (int64_t)c0 * f.ldh, f.ldh, f.Bt, f.ldb, p, sm.Wn, b, b, n,
-               -1.0, ctrl, i);
-    if (!cx.ok()) break;
-    if (b <= 8)
-      hipLaunchKernelGGL(k_trsm_rows<8>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
-                         sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
-    else if (b <= 16)
-      hipLaunchKernelGGL(k_trsm_rows<16>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
-                         sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
-    else
-      hipLaunchKernelGGL(k_trsm_rows<32>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
-                         sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
-    cx.chk();
+    if (!chol || !cx.ok()) break;
+    int flagged = 1;
+    cx.err = hipMemcpyAsync(&flagged, &ctrl->pad[0], sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+    if (!cx.ok() || flagged == 0) break;
   }
   if (!cx.ok()) return cx.err;
 
