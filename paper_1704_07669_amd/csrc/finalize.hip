@@ -75,6 +75,26 @@ __device__ __forceinline__ void block_sum_range(const double (&v)[CMAX], double*
   __syncthreads();
 }
 
+// Copies count values into shared memory with nthr threads, eight loads in flight per thread: each
+// batch issues all of its loads (load(i), i < count) before any of its stores (store(i, v)), so a
+// batch costs one memory latency instead of eight.
+template <typename LoadF, typename StoreF>
+__device__ __forceinline__ void stage8(int count, int tid, int nthr, LoadF load, StoreF store) {
+  for (int base = 0; base < count; base += 8 * nthr) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = base + tid + u * nthr;
+      v[u] = load(i < count ? i : count - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = base + tid + u * nthr;
+      if (i < count) store(i, v[u]);
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // Reductions over rows on the FP64 matrix cores: part[chunk][a][c] = sum_{r in chunk} X[a][r] Y[c][r].
 // The MFMA k index is the row: lane L supplies rows r0 + 4(L/16) .. +3 of column a = 16 mt + L%16
@@ -227,13 +247,19 @@ __global__ __launch_bounds__(kTnFinalThreads) void k_tn_final(const double* __re
 // null (taken as 0) and may alias out.  A workgroup owns 64 rows; its four waves take interleaved
 // ranges of a, and their partial sums are added in wave order through LDS.  W is staged in LDS
 // zero-padded to QMAX columns, so the inner loop has no per-column conditions.
+//
+// With Rs non-null (q x q upper triangular, row-major, leading dimension q) each row v of the
+// result is replaced by the solution x of x Rs = v (forward substitution) before it is written, and
+// only the first `keep` entries are solved (keep = ctrl->keep_last on the iteration the rank guard
+// stopped at, q otherwise); the others are written as zero.
 template <typename BT, int QMAX>
 __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int64_t ldo,
                                                    const BT* base, int64_t ldb,
                                                    const double* __restrict__ X, int64_t ldx,
                                                    int p, const double* __restrict__ W, int ldw,
                                                    int q, int64_t rows, double alpha,
-                                                   const Ctrl* __restrict__ ctrl, int iter) {
+                                                   const Ctrl* __restrict__ ctrl, int iter,
+                                                   const double* __restrict__ Rs = nullptr) {
   if (skip_iter(ctrl, iter)) return;
   extern __shared__ double ws[];              // p x QMAX, then 3 x QMAX x 64 partials
   double* part = ws + p * QMAX;
@@ -287,13 +313,32 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
   }
   __syncthreads();
   if (wave == 0 && live) {
+    if (Rs == nullptr) {
 #pragma unroll
-    for (int c = 0; c < QMAX; ++c) {
-      if (c < q) {
-        double sum = acc[c];
-        for (int w = 1; w < TPB / 64; ++w) sum += part[((w - 1) * QMAX + c) * 64 + lane];
-        const double bv = base ? (double)base[c * ldb + r] : 0.0;
-        out[c * ldo + r] = bv + alpha * sum;
+      for (int c = 0; c < QMAX; ++c) {
+        if (c < q) {
+          double sum = acc[c];
+          for (int w = 1; w < TPB / 64; ++w) sum += part[((w - 1) * QMAX + c) * 64 + lane];
+          const double bv = base ? (double)base[c * ldb + r] : 0.0;
+          out[c * ldo + r] = bv + alpha * sum;
+        }
+      }
+    } else {
+      const int keep = (ctrl != nullptr && iter == ctrl->last_iter) ? ctrl->keep_last : q;
+      double x[QMAX];
+#pragma unroll
+      for (int c = 0; c < QMAX; ++c) {
+        double v = 0.0;
+        if (c < q) {
+          double sum = acc[c];
+          for (int w = 1; w < TPB / 64; ++w) sum += part[((w - 1) * QMAX + c) * 64 + lane];
+          v = (base ? (double)base[c * ldb + r] : 0.0) + alpha * sum;
+#pragma unroll
+          for (int k = 0; k < c; ++k) v = fma(-x[k], Rs[k * q + c], v);
+          v = (c < keep) ? v / Rs[c * q + c] : 0.0;
+        }
+        x[c] = v;
+        if (c < q) out[c * ldo + r] = v;
       }
     }
   }
@@ -548,28 +593,28 @@ __global__ void k_guard(const double* __restrict__ R1, const double* __restrict_
 constexpr double kCholQrPivot = 1e-10;
 
 // Y <- Y R^-1 in place for G = R^T R (b x b, row-major, leading dimension b, upper triangle read).
-// Every workgroup factors G itself in LDS (b steps, all threads), so the factorisation needs no
-// launch of its own and all workgroups apply the same R^-1.  Workgroup 0 writes Rout = R Rprev
-// (Rprev null: identity) and, when `last` is set, applies the rank guard to Rout and forms
-// Wn = T + W (p x b, the combined weights of the numerator of Eq. 9).
+// One wave per workgroup and 64 rows each: every workgroup factors G itself in LDS (b steps), so the
+// factorisation needs no launch of its own, all workgroups apply the same R^-1, and its barriers
+// are those of a single wave.  Workgroup 0 writes Rout = R Rprev (Rprev null: identity).  On the
+// last step (`last` set) every workgroup also takes the rank guard's decision from the diagonal of
+// R Rprev and writes zeros in place of the columns it drops (the basis vectors past the numerical
+// rank), and workgroup 0 records the decision in ctrl and forms Wn = T + W (p x b, the combined
+// weights of the numerator of Eq. 9).
+constexpr int kApplyThreads = 64;
 template <int BMAX>
-__global__ __launch_bounds__(TPB) void k_cholqr_apply(double* __restrict__ Y, int64_t ldy,
-                                                      int64_t rows, const double* __restrict__ G,
-                                                      int b, const double* __restrict__ Rprev,
-                                                      double* __restrict__ Rout, int last,
-                                                      const double* __restrict__ T,
-                                                      const double* __restrict__ Wt,
-                                                      double* __restrict__ Wn, int p,
-                                                      Ctrl* __restrict__ ctrl, int iter) {
+__global__ __launch_bounds__(kApplyThreads) void k_cholqr_apply(
+    double* __restrict__ Y, int64_t ldy, int64_t rows, const double* __restrict__ G, int b,
+    const double* __restrict__ Rprev, double* __restrict__ Rout, int last,
+    const double* __restrict__ T, const double* __restrict__ Wt, double* __restrict__ Wn, int p,
+    Ctrl* __restrict__ ctrl, int iter) {
   if (skip_iter(ctrl, iter)) return;
-  constexpr int LS = BMAX + 1, SL = (BMAX + 15) / 16;   // SL: slots per thread of the 16 x 16 grid
+  constexpr int LS = BMAX + 1, SL = (BMAX + 7) / 8;   // SL: slots per lane of the 8 x 8 grid
   __shared__ double a[BMAX * LS];     // G -> R (upper), R^-1 (strictly lower, transposed)
   __shared__ double rd[BMAX], dinv[BMAX], gd[BMAX];
-  __shared__ double rp[BMAX * BMAX];
-  __shared__ int bad;
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  const int64_t r = (int64_t)blockIdx.x * TPB + tid;
-  // this thread's row of Y, fetched before the factorisation so the load overlaps it
+  __shared__ double rp[BMAX * BMAX], rpv[BMAX * BMAX];   // R Rprev, Rprev
+  const int tid = threadIdx.x, ty = tid >> 3, tx = tid & 7;
+  const int64_t r = (int64_t)blockIdx.x * kApplyThreads + tid;
+  // this lane's row of Y, fetched before the factorisation so the load overlaps it
   double y[BMAX];
   const int64_t rc = r < rows ? r : 0;
 #pragma unroll
@@ -577,41 +622,44 @@ __global__ __launch_bounds__(TPB) void k_cholqr_apply(double* __restrict__ Y, in
     const double v = Y[(c < b ? c : 0) * ldy + rc];
     y[c] = (c < b) ? v : 0.0;
   }
-  for (int idx = tid; idx < BMAX * BMAX; idx += TPB) {
-    const int i = idx / BMAX, c = idx % BMAX;
-    const double g = (i < b && c < b && c >= i) ? G[i * b + c] : 0.0;
-    a[i * LS + c] = g;
-    if (i == c) gd[i] = g;
-  }
-  if (tid == 0) bad = 0;
+  stage8(BMAX * BMAX, tid, kApplyThreads,
+         [&](int idx) {
+           const int i = idx / BMAX, c = idx % BMAX;
+           return (i < b && c < b) ? G[i * b + c] : 0.0;
+         },
+         [&](int idx, double v) {
+           const int i = idx / BMAX, c = idx % BMAX;
+           a[i * LS + c] = (c >= i) ? v : 0.0;
+           if (i == c) gd[i] = v;
+         });
+  if (Rprev != nullptr)
+    stage8(b * b, tid, kApplyThreads, [&](int idx) { return Rprev[idx]; },
+           [&](int idx, double v) { rpv[idx] = v; });
   __syncthreads();
+  bool bad = false;
   for (int j = 0; j < b; ++j) {
     const double d = a[j * LS + j];
-    if (!(d > kCholQrPivot * gd[j]) || !(d < INFINITY)) {   // uniform: every thread sees d
-      if (tid == 0) bad = 1;
-      break;
-    }
+    if (!(d > kCholQrPivot * gd[j]) || !(d < INFINITY)) { bad = true; break; }   // uniform
     const double inv = 1.0 / sqrt(d);
     if (tid == 0) rd[j] = sqrt(d);
     if (j + 1 + tid < b) a[j * LS + j + 1 + tid] *= inv;
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < SL; ++m) {
-      const int i = j + 1 + ty + 16 * m;
+      const int i = j + 1 + ty + 8 * m;
 #pragma unroll
       for (int n = 0; n < SL; ++n) {
-        const int c = j + 1 + tx + 16 * n;
+        const int c = j + 1 + tx + 8 * n;
         if (i < b && c < b && c >= i) a[i * LS + c] = fma(-a[j * LS + i], a[j * LS + c], a[i * LS + c]);
       }
     }
     __syncthreads();
   }
-  __syncthreads();
   if (bad) {
     if (blockIdx.x == 0 && tid == 0) ctrl->pad[0] = 1;
     return;
   }
-  for (int i = tid; i < b; i += TPB) dinv[i] = 1.0 / rd[i];
+  if (tid < b) dinv[tid] = 1.0 / rd[tid];
   __syncthreads();
   // R^-1 by back substitution from the bottom row; R^-1[k][c] (k < c) stored at a[c][k]
   for (int i = b - 1; i >= 0; --i) {
@@ -619,10 +667,10 @@ __global__ __launch_bounds__(TPB) void k_cholqr_apply(double* __restrict__ Y, in
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < SL; ++m) {
-      const int k = ty + 16 * m;
+      const int k = ty + 8 * m;
 #pragma unroll
       for (int n = 0; n < SL; ++n) {
-        const int c = i + tx + 16 * n;
+        const int c = i + tx + 8 * n;
         if (k < i && c < b) {
           const double xc = (c == i) ? dinv[i] : a[c * LS + i];
           a[c * LS + k] = fma(-a[k * LS + i], xc, a[c * LS + k]);
@@ -630,6 +678,14 @@ __global__ __launch_bounds__(TPB) void k_cholqr_apply(double* __restrict__ Y, in
       }
     }
     __syncthreads();
+  }
+  // the rank guard's decision on the last step: diag(R Rprev) = diag(R) diag(Rprev)
+  int keep = b;
+  if (last) {
+    const double r00 = rd[0] * (Rprev ? rpv[0] : 1.0);
+    const double thr = kGuardTau * (iter == 0 ? r00 : ctrl->r0);
+    keep = 0;
+    while (keep < b && fabs(rd[keep] * (Rprev ? rpv[keep * b + keep] : 1.0)) > thr) ++keep;
   }
   // out_c = sum_{k <= c} y_k R^-1[k][c]
   if (r < rows) {
@@ -645,23 +701,23 @@ __global__ __launch_bounds__(TPB) void k_cholqr_apply(double* __restrict__ Y, in
     }
 #pragma unroll
     for (int c = 0; c < BMAX; ++c)
-      if (c < b) Y[c * ldy + r] = o[c];
+      if (c < b) Y[c * ldy + r] = (c < keep) ? o[c] : 0.0;
   }
   if (blockIdx.x != 0) return;
   // Rout = R Rprev (upper triangular), then the guard and Wn on the last step
-  for (int idx = tid; idx < b * b; idx += TPB) {
+  for (int idx = tid; idx < b * b; idx += kApplyThreads) {
     const int i = idx / b, c = idx % b;
     double s = 0.0;
     if (c >= i) {
       if (Rprev == nullptr) s = (c == i) ? rd[i] : a[i * LS + c];
       else
-        for (int k = i; k <= c; ++k) s = fma(k == i ? rd[i] : a[i * LS + k], Rprev[k * b + c], s);
+        for (int k = i; k <= c; ++k) s = fma(k == i ? rd[i] : a[i * LS + k], rpv[k * b + c], s);
     }
     rp[idx] = s;
     Rout[idx] = s;
   }
   if (!last) return;
-  for (int idx = tid; idx < p * b; idx += TPB) Wn[idx] = T[idx] + Wt[idx];
+  for (int idx = tid; idx < p * b; idx += kApplyThreads) Wn[idx] = T[idx] + Wt[idx];
   __syncthreads();
   if (tid == 0) guard_apply(rp, b, iter, ctrl);
 }
@@ -672,31 +728,6 @@ __global__ void k_add_small(const double* __restrict__ A, const double* __restri
                             int iter) {
   if (skip_iter(ctrl, iter)) return;
   for (int i = threadIdx.x; i < count; i += blockDim.x) out[i] = A[i] + B[i];
-}
-
-// Bt(:, c0 + j) = (N R^{-1})(:, j) for j < keep (row-wise forward substitution), 0 for j >= keep;
-// Q columns c0 + keep .. c0 + b - 1 are zeroed by k_zero_cols.
-template <int BMAX>
-__global__ void k_trsm_rows(const double* __restrict__ N, int64_t ldn, const double* __restrict__ R,
-                            int b, int64_t rows, double* __restrict__ Bt, int64_t ldb, int c0,
-                            const Ctrl* __restrict__ ctrl, int iter) {
-  if (skip_iter(ctrl, iter)) return;
-  const int keep = (iter == ctrl->last_iter) ? ctrl->keep_last : b;
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
-       r += (int64_t)gridDim.x * blockDim.x) {
-    double y[BMAX];
-#pragma unroll
-    for (int j = 0; j < BMAX; ++j) {
-      if (j < b) {
-        double s = N[j * ldn + r];
-#pragma unroll
-        for (int q = 0; q < BMAX; ++q)
-          if (q < j) s -= y[q] * R[q * b + j];
-        y[j] = (j < keep) ? s / R[j * b + j] : 0.0;
-        Bt[(c0 + j) * ldb + r] = y[j];
-      }
-    }
-  }
 }
 
 __global__ void k_zero_cols(double* __restrict__ Q, int64_t ldq, int64_t rows, int c0, int b,
@@ -762,10 +793,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
   const int LS = L + 1, tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
   double* rd = a + (int64_t)L * LS;
   double* dinv = rd + L;
-  for (int idx = tid; idx < L * L; idx += kCholThreads) {
-    const int i = idx / L, c = idx % L;
-    a[i * LS + c] = (c >= i) ? Gm[(int64_t)i * ldg + c] : 0.0;
-  }
+  stage8(L * L, tid, kCholThreads,
+         [&](int idx) { return Gm[(int64_t)(idx / L) * ldg + idx % L]; },
+         [&](int idx, double v) {
+           const int i = idx / L, c = idx % L;
+           a[i * LS + c] = (c >= i) ? v : 0.0;
+         });
   __syncthreads();
   if (shift_rel > 0.0) {
     if (tid < 64) {
@@ -788,7 +821,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     }
     const double inv = 1.0 / sqrt(d);
     if (tid == 0) rd[j] = sqrt(d);
-    if (j + 1 + tid < L) a[j * LS + j + 1 + tid] *= inv;
+    for (int c = j + 1 + tid; c < L; c += kCholThreads) a[j * LS + c] *= inv;
     __syncthreads();
     // a[i][c] -= a[j][i] a[j][c] for j < i <= c < L
     double rc[kCholSlots];
@@ -823,7 +856,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     // Solve R X = I from the bottom: row i of X is final once rows i+1.. have been subtracted from
     // it; X[i][c] = rhs[i][c] / R_ii, then rhs[k][c] -= R[k][i] X[i][c] for k < i, c >= i.
     for (int i = L - 1; i >= 0; --i) {
-      if (i + 1 + tid < L) a[(i + 1 + tid) * LS + i] *= dinv[i];
+      for (int c = i + 1 + tid; c < L; c += kCholThreads) a[c * LS + i] *= dinv[i];
       __syncthreads();
       double xc[kCholSlots];
 #pragma unroll
@@ -932,7 +965,7 @@ __device__ __forceinline__ double rsq_nr1(double x) {
 // rows gl + 8 e: the three inner products are reduced within the 8 lanes.  The right factor is not
 // accumulated: with M J = W (orthogonal columns, norms sigma), B^T = Q_B R_B and M = R_B^T,
 // B^T W = Q_B J S^2, so V = B^T W S^-2 (see run_finalize).
-constexpr int kJacobiLds = 160 * 1024 - 1024;   // dynamic LDS limit of k_jacobi
+constexpr int kJacobiLds = 160 * 1024 - 4096;   // dynamic LDS limit of k_jacobi (static: norms)
 constexpr int kJacobiLpp = 8;                   // lanes per pair
 constexpr int kJacobiThreads = 64 * kJacobiLpp; // one lane group per pair for N <= 128
 
@@ -949,16 +982,19 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
                                                            double* __restrict__ nrm) {
   extern __shared__ double M[];           // N columns x CS, then the pair table
   __shared__ int rotated;
+  __shared__ double nrm2[JMAX];           // squared column norms
   constexpr int LPP = kJacobiLpp, LPAD = LPP * EPL, CS = jacobi_cs(LPAD);
   const int N = (L + 1) & ~1;
   uint8_t* pairs = reinterpret_cast<uint8_t*>(M + (int64_t)N * CS);   // (N-1) x N/2 x {p, q}
   const double tol = (double)L * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   const int grp = threadIdx.x / LPP, gl = threadIdx.x % LPP;
-  for (int idx = threadIdx.x; idx < N * LPAD; idx += kJacobiThreads) {
-    const int col = idx / LPAD, i = idx % LPAD;
-    M[col * CS + i] = (col < L && i < L) ? RB[col * ldr + i] : 0.0;     // M(:, col) = R_B(col, :)^T
-  }
+  stage8(N * LPAD, threadIdx.x, kJacobiThreads,                        // M(:, col) = R_B(col, :)^T
+         [&](int idx) {
+           const int col = idx / LPAD, i = idx % LPAD;
+           return (col < L && i < L) ? RB[col * ldr + i] : 0.0;
+         },
+         [&](int idx, double v) { M[(idx / LPAD) * CS + idx % LPAD] = v; });
   for (int idx = threadIdx.x; idx < (N - 1) * (N / 2); idx += kJacobiThreads) {
     int p, q;
     rr_pair(N, idx / (N / 2), idx % (N / 2), p, q);
@@ -969,36 +1005,49 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
   const bool active = grp < N / 2;
   int sweep = 0;
   for (; sweep < JSWEEPS && N > 1; ++sweep) {
+    // squared column norms, recomputed each sweep and carried through its rotations by
+    // a' = a - t g, b' = b + t g (exact for the rotation that zeroes g)
+    for (int col = grp; col < N; col += kJacobiThreads / LPP) {
+      const double* mc = M + col * CS + gl;
+      double s0 = 0, s1 = 0;
+#pragma unroll
+      for (int e = 0; e < EPL; e += 2) {
+        s0 = fma(mc[LPP * e], mc[LPP * e], s0);
+        if (e + 1 < EPL) s1 = fma(mc[LPP * (e + 1)], mc[LPP * (e + 1)], s1);
+      }
+      double v = s0 + s1;
+      v += dpp::mov<dpp::kXor1>(v);
+      v += dpp::mov<dpp::kXor2>(v);
+      v += dpp::mov<dpp::kHalfMirror>(v);
+      if (gl == 0) nrm2[col] = v;
+    }
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     int p = 0, q = 0;
     if (active) { p = pairs[2 * grp]; q = pairs[2 * grp + 1]; }
     for (int r = 0; r < N - 1; ++r) {
       if (active) {
-        // the next round's pair (the table never changes), fetched ahead of this round's work
-        int pn = 0, qn = 0;
-        if (r + 1 < N - 1) {
-          const int pi = 2 * ((r + 1) * (N / 2) + grp);
-          pn = pairs[pi]; qn = pairs[pi + 1];
-        }
         double* mp = M + p * CS + gl;
         double* mq = M + q * CS + gl;
         double xp[EPL], xq[EPL];
 #pragma unroll
         for (int e = 0; e < EPL; ++e) { xp[e] = mp[LPP * e]; xq[e] = mq[LPP * e]; }
-        double a0 = 0, a1 = 0, b0 = 0, b1 = 0, g0 = 0, g1 = 0;
+        const double a = nrm2[p], bb = nrm2[q];
+        // the next round's pair (the table never changes), fetched behind this round's loads
+        int pn = 0, qn = 0;
+        if (r + 1 < N - 1) {
+          const int pi = 2 * ((r + 1) * (N / 2) + grp);
+          pn = pairs[pi]; qn = pairs[pi + 1];
+        }
+        double g0 = 0, g1 = 0;
 #pragma unroll
         for (int e = 0; e < EPL; e += 2) {
-          a0 = fma(xp[e], xp[e], a0); b0 = fma(xq[e], xq[e], b0); g0 = fma(xp[e], xq[e], g0);
-          if (e + 1 < EPL) {
-            a1 = fma(xp[e + 1], xp[e + 1], a1); b1 = fma(xq[e + 1], xq[e + 1], b1);
-            g1 = fma(xp[e + 1], xq[e + 1], g1);
-          }
+          g0 = fma(xp[e], xq[e], g0);
+          if (e + 1 < EPL) g1 = fma(xp[e + 1], xq[e + 1], g1);
         }
-        double a = a0 + a1, bb = b0 + b1, g = g0 + g1;
-        a += dpp::mov<dpp::kXor1>(a); bb += dpp::mov<dpp::kXor1>(bb); g += dpp::mov<dpp::kXor1>(g);
-        a += dpp::mov<dpp::kXor2>(a); bb += dpp::mov<dpp::kXor2>(bb); g += dpp::mov<dpp::kXor2>(g);
-        a += dpp::mov<dpp::kHalfMirror>(a); bb += dpp::mov<dpp::kHalfMirror>(bb);
+        double g = g0 + g1;
+        g += dpp::mov<dpp::kXor1>(g);
+        g += dpp::mov<dpp::kXor2>(g);
         g += dpp::mov<dpp::kHalfMirror>(g);
         // rotate unless the pair is orthogonal to working precision (L eps relative)
         if ((g != 0.0) && (g * g > tol2 * (a * bb))) {
@@ -1015,7 +1064,11 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
             mp[LPP * e] = c * xp[e] - s * xq[e];
             mq[LPP * e] = s * xp[e] + c * xq[e];
           }
-          if (gl == 0) rotated = 1;
+          if (gl == 0) {
+            nrm2[p] = fmax(fma(-t, g, a), 0.0);
+            nrm2[q] = fma(t, g, bb);
+            rotated = 1;
+          }
         }
         p = pn; q = qn;
       }
@@ -1059,7 +1112,7 @@ size_t jacobi_lds_bytes(int L) {
 __global__ void k_gather(const double* __restrict__ W, int ld, int L, const int* __restrict__ perm,
                          const double* __restrict__ sig, int kk, double* __restrict__ Wv,
                          double* __restrict__ Wk) {
-  for (int idx = threadIdx.x; idx < L * kk; idx += blockDim.x) {
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < L * kk; idx += gridDim.x * blockDim.x) {
     const int i = idx / kk, j = idx % kk;
     const int col = perm[j];
     const double sj = sig[j];
@@ -1107,10 +1160,12 @@ __global__ __launch_bounds__(TPB) void k_write_rows(const double* __restrict__ X
                                                     int64_t ld, int colmajor) {
   extern __shared__ double ws[];
   const int j0 = blockIdx.y * 16;
-  for (int idx = threadIdx.x; idx < L * 16; idx += TPB) {
-    const int a = idx / 16, j = idx % 16;
-    ws[idx] = (j0 + j < kk) ? Wk[a * kk + j0 + j] : 0.0;
-  }
+  stage8(L * 16, threadIdx.x, TPB,
+         [&](int idx) {
+           const int a = idx / 16, j = idx % 16;
+           return (j0 + j < kk) ? Wk[a * kk + j0 + j] : 0.0;
+         },
+         [&](int idx, double v) { ws[idx] = v; });
   __syncthreads();
   for (int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x; r < rows;
        r += (int64_t)gridDim.x * TPB) {
@@ -1118,12 +1173,12 @@ __global__ __launch_bounds__(TPB) void k_write_rows(const double* __restrict__ X
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[j] = 0.0;
     int a = 0;
-    for (; a + 4 <= L; a += 4) {
-      double x[4];
+    for (; a + 16 <= L; a += 16) {            // sixteen loads in flight per batch
+      double x[16];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = X[(a + u) * ldx + r];
+      for (int u = 0; u < 16; ++u) x[u] = X[(a + u) * ldx + r];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 16; ++u)
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[j] = fma(x[u], ws[(a + u) * 16 + j], acc[j]);
     }
@@ -1228,20 +1283,20 @@ void tn(Ctx& cx, const double* X, int64_t ldx, const double* Y, int64_t ldy, int
 template <typename BT>
 void nn(Ctx& cx, double* out, int64_t ldo, const BT* base, int64_t ldb, const double* X,
         int64_t ldx, int p, const double* W, int ldw, int q, int64_t rows, double alpha,
-        const Ctrl* ctrl, int iter) {
+        const Ctrl* ctrl, int iter, const double* Rs = nullptr) {
   if (!cx.ok() || q == 0 || rows == 0) return;
   const int qmax = q <= 8 ? 8 : (q <= 16 ? 16 : 32);
   const size_t shm = (size_t)(p * qmax + 3 * qmax * 64) * sizeof(double);
   const dim3 g((unsigned)cdiv<int64_t>(rows, 64)), blk(TPB);
   if (q <= 8)
     hipLaunchKernelGGL((k_nn_update<BT, 8>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p, W,
-                       ldw, q, rows, alpha, ctrl, iter);
+                       ldw, q, rows, alpha, ctrl, iter, Rs);
   else if (q <= 16)
     hipLaunchKernelGGL((k_nn_update<BT, 16>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p,
-                       W, ldw, q, rows, alpha, ctrl, iter);
+                       W, ldw, q, rows, alpha, ctrl, iter, Rs);
   else
     hipLaunchKernelGGL((k_nn_update<BT, 32>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p,
-                       W, ldw, q, rows, alpha, ctrl, iter);
+                       W, ldw, q, rows, alpha, ctrl, iter, Rs);
   cx.chk();
 }
 
@@ -1330,7 +1385,7 @@ void cholqr(Ctx& cx, double* Y, int64_t ldy, int64_t rows, const double* G, int 
             const double* Rprev, double* Rout, bool last, const Small& sm, int p, Ctrl* ctrl,
             int iter) {
   if (!cx.ok()) return;
-  const dim3 g((unsigned)cdiv<int64_t>(rows, TPB)), blk(TPB);
+  const dim3 g((unsigned)cdiv<int64_t>(rows, kApplyThreads)), blk(kApplyThreads);
   const int lf = last ? 1 : 0;
   if (b <= 8)
     hipLaunchKernelGGL(k_cholqr_apply<8>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
@@ -1520,23 +1575,14 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
           cx.chk();
         }
       }
-      hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((int64_t)b * m)), dim3(TPB), 0, stream, f.Q,
-                         f.ldq, m, c0, b, ctrl, i);
-      cx.chk();
-      // N = H(:, c) - B^T (T + W);  B_i^T = N R_i^{-1}
-      nn<double>(cx, f.Wn, f.ldb, f.H + (int64_t)c0 * f.ldh, f.ldh, f.Bt, f.ldb, p, sm.Wn, b, b, n,
-                 -1.0, ctrl, i);
-      if (!cx.ok()) break;
-      if (b <= 8)
-        hipLaunchKernelGGL(k_trsm_rows<8>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
-                           sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
-      else if (b <= 16)
-        hipLaunchKernelGGL(k_trsm_rows<16>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
-                           sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
-      else
-        hipLaunchKernelGGL(k_trsm_rows<32>, dim3(grid_for(n)), dim3(TPB), 0, stream, f.Wn, f.ldb,
-                           sm.R, b, n, f.Bt, f.ldb, c0, ctrl, i);
-      cx.chk();
+      if (!chol) {
+        hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((int64_t)b * m)), dim3(TPB), 0, stream, f.Q,
+                           f.ldq, m, c0, b, ctrl, i);
+        cx.chk();
+      }
+      // N = H(:, c) - B^T (T + W);  B_i^T = N R_i^{-1} (row-wise solve in the same kernel)
+      nn<double>(cx, f.Bt + (int64_t)c0 * f.ldb, f.ldb, f.H + (int64_t)c0 * f.ldh, f.ldh, f.Bt,
+                 f.ldb, p, sm.Wn, b, b, n, -1.0, ctrl, i, sm.R);
     }
     if (!chol || !cx.ok()) break;
     int flagged = 1;
@@ -1599,8 +1645,8 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
     }
     cx.chk();
     if (!cx.ok()) return cx.err;
-    hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, stream, sm.Wm, L, L, sm.perm, sm.sig, kk,
-                       sm.Jk, sm.Wk);
+    hipLaunchKernelGGL(k_gather, dim3(cdiv(L * kk, 256)), dim3(256), 0, stream, sm.Wm, L, L,
+                       sm.perm, sm.sig, kk, sm.Jk, sm.Wk);
     cx.chk();
     // V (column-major temp in the H storage) = B^T W S^-2, its signs, then the row-major outputs
     double* Vt = const_cast<double*>(f.H);

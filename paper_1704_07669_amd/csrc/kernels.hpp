@@ -103,7 +103,6 @@ struct FinalizeArgs {
   const double* om64; int64_t ldo;   // Omega' (FP64), n-side
   double* Q; int64_t ldq;            // m x l basis
   double* Bt; double* Qb; int64_t ldb;   // B^T and the Q factor of B^T, n-side
-  double* Wn;                        // n x b work (ld = ldb)
   double* tsqr_ws; int64_t tsqr_ws_elems;
   double* red_ws; int64_t red_ws_elems;
   double* small;                     // small matrices, see finalize.hip

@@ -1053,6 +1053,8 @@ int src_bytes(int src) { return src == S_F64 ? 8 : src == S_F32 ? 4 : src == S_B
 // workgroups the wide-strip product aims at for one block: one per CU (its register footprint
 // allows one four-wave workgroup per CU)
 constexpr int64_t kG2TargetWgs = 256;
+constexpr int64_t kG1Wgs = 256;       // workgroups of g = a Omega per item: one per CU
+constexpr int64_t kG1KAlign = 256;    // split granularity in columns (a multiple of every KC)
 int64_t g2_target() { return kG2TargetWgs; }
 
 }  // namespace
@@ -1062,16 +1064,18 @@ int64_t gemm2_strips(int64_t n, int mode) { return cdiv<int64_t>(n, gemm2_strip_
 int64_t gemm2_partial_tiles_max() { return std::max<int64_t>(g2_target(), 1024 / WAVES); }
 
 // Launch shape of one item.
-//   g = a Omega: row tiles of 128 rows times k splits, enough splits for about 512 workgroups
-//     (two per CU), each split a multiple of 512 columns.
+//   g = a Omega: row tiles of 128 rows times k splits, as many splits as keep the launch within
+//     one workgroup per CU (256): a second, partly filled round of workgroups leaves the CUs that
+//     run two of them setting the pace.  Each split is a multiple of 256 columns (the widest
+//     Omega' chunk).
 //   a^T g: one four-wave workgroup per strip of 16 VC columns; narrow matrices also split the
 //     rows across workgroups so that about half of the chip's 1024 wave slots are busy.
 void plan_item(PassItem& it, int mode, int src, int splits_max) {
   const int es = src_bytes(src);
   it.vec_ok = ((((uintptr_t)it.A) % 16) == 0) && ((it.lda * es) % 16 == 0);
   it.row_tiles = (int)cdiv<int64_t>(it.nrows, ROW_TILE);
-  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(splits_max, cdiv<int64_t>(512, it.row_tiles)));
-  it.kchunk = rup<int64_t>(cdiv<int64_t>(it.n, splits), kNpAlign);
+  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(splits_max, kG1Wgs / it.row_tiles));
+  it.kchunk = rup<int64_t>(cdiv<int64_t>(it.n, splits), kG1KAlign);
   it.splits = (int)cdiv<int64_t>(it.n, it.kchunk);
   const G2Shape sh = g2_shape(mode);
   const int KR = 4 * sh.V2;

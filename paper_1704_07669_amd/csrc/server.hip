@@ -88,7 +88,7 @@ struct Sizes {
   int64_t item_bytes;     // group scratch one item may need (upper bound)
   int64_t group_bytes;    // all group slots
   int64_t cnt_per_slot;   // counters per group slot
-  int64_t off_group, off_cnt, off_table, off_Q, off_Bt, off_Qb, off_Wn, off_tsqr, off_red,
+  int64_t off_group, off_cnt, off_table, off_Q, off_Bt, off_Qb, off_tsqr, off_red,
       off_small, off_arena, total;
   int64_t NPmax, MCAPmax, tsqr_elems, red_elems;
 };
@@ -132,7 +132,6 @@ Sizes sizes(const sketch_server_config* c) {
   z.off_Q = take(z.MCAPmax * z.LP * 8);
   z.off_Bt = take(z.NPmax * z.LP * 8);
   z.off_Qb = take(z.NPmax * z.LP * 8);
-  z.off_Wn = take(32 * z.NPmax * 8);
   z.off_tsqr = take(z.tsqr_elems * 8);
   z.off_red = take(z.red_elems * 8);
   z.off_small = take((int64_t)finalize_small_elems(c->l, 32) * 8);
@@ -709,7 +708,6 @@ sketch_status sketch_server_finalize(sketch_server_t s, uint64_t stream_id, doub
       f.Bt = s->at<double>(z.off_Bt);
       f.Qb = s->at<double>(z.off_Qb);
       f.ldb = st.lay.NP;
-      f.Wn = s->at<double>(z.off_Wn);
       f.tsqr_ws = s->at<double>(z.off_tsqr);
       f.tsqr_ws_elems = z.tsqr_elems;
       f.red_ws = s->at<double>(z.off_red);

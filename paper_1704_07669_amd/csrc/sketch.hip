@@ -78,7 +78,7 @@ struct Layout {
   int LP, NT, t, splits_max;
   int64_t NP, MCAP, RBP, LDST, NQ;
   int64_t off_ctrl, off_fp8, off_om64, off_omc, off_G, off_H, off_P1, off_Gop, off_P2, off_cnt, off_stage, off_fp8q,
-      off_Q, off_Bt, off_Qb, off_Wn, off_tsqr, off_red, off_small, total;
+      off_Q, off_Bt, off_Qb, off_tsqr, off_red, off_small, total;
   int64_t stage_slot_bytes;
   int64_t tsqr_elems, red_elems;
 };
@@ -139,7 +139,6 @@ Layout plan(const sketch_config* c) {
   L.off_Q = take((int64_t)L.LP * L.MCAP * 8);
   L.off_Bt = take((int64_t)L.LP * L.NP * 8);
   L.off_Qb = take((int64_t)L.LP * L.NP * 8);
-  L.off_Wn = take((int64_t)32 * L.NP * 8);
   L.off_tsqr = take(L.tsqr_elems * 8);
   L.off_red = take(L.red_elems * 8);
   L.off_small = take((int64_t)finalize_small_elems(c->l, c->b) * 8);
@@ -499,7 +498,6 @@ sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t 
   f.Bt = h->at<double>(L.off_Bt);
   f.Qb = h->at<double>(L.off_Qb);
   f.ldb = L.NP;
-  f.Wn = h->at<double>(L.off_Wn);
   f.tsqr_ws = h->at<double>(L.off_tsqr);
   f.tsqr_ws_elems = L.tsqr_elems;
   f.red_ws = h->at<double>(L.off_red);
