@@ -22,7 +22,9 @@ STATUS = {0: "SKETCH_OK", 1: "SKETCH_E_INVAL", 2: "SKETCH_E_STATE", 3: "SKETCH_E
           4: "SKETCH_E_CAPACITY", 5: "SKETCH_E_NONFINITE", 6: "SKETCH_E_DEVICE"}
 EXPORTED = [
     "sketch_workspace_size", "sketch_init", "sketch_reset", "sketch_set_omega",
-    "sketch_ingest_block", "sketch_poll", "sketch_finalize", "sketch_get_omega",
+    "sketch_ingest_block", "sketch_poll", "sketch_finalize", "sketch_finalize_paths",
+    "sketch_debug_force_paths",
+    "sketch_get_omega",
     "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
     "sketch_destroy", "sketch_last_error",
     "sketch_server_workspace_size", "sketch_server_stream_bytes", "sketch_server_create",
@@ -89,6 +91,8 @@ def load_library(path=None):
         "sketch_ingest_block": (I32, [P, P, I32, I64, I64, I32, ctypes.POINTER(U64)]),
         "sketch_poll": (I32, [P, U64, ctypes.POINTER(I32)]),
         "sketch_finalize": (I32, [P, P, P, I64, P, I64, ctypes.POINTER(I32)]),
+        "sketch_finalize_paths": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "sketch_debug_force_paths": (I32, [P, I32, I32]),
         "sketch_get_omega": (I32, [P, P, I64]),
         "sketch_debug_state": (I32, [P, P, P, ctypes.POINTER(I64)]),
         "sketch_philox_words": (I32, [U64, U64, I64, P, P]),
@@ -177,6 +181,17 @@ def sketch_finalize(h, S, U, V):
     return r.value
 
 
+def sketch_finalize_paths(h):
+    """(loop_path, rb_path) of the last finalize: 0 Cholesky QR, 1 the Householder fallback."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().sketch_finalize_paths(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def sketch_debug_force_paths(h, loop_householder, rb_householder):
+    _check(load_library().sketch_debug_force_paths(h, int(loop_householder), int(rb_householder)))
+
+
 def sketch_get_omega(h, out):
     _check(load_library().sketch_get_omega(h, _ptr(out), out.stride(0)))
 
@@ -263,6 +278,12 @@ class Sketch:
             U = torch.empty(self.rows_capacity_used(), self.k, dtype=torch.float64, device="cuda")
         rank = sketch_finalize(self.h, S, U, V)
         return S, V, U, rank
+
+    def finalize_paths(self):
+        return sketch_finalize_paths(self.h)
+
+    def force_paths(self, loop_householder, rb_householder):
+        sketch_debug_force_paths(self.h, loop_householder, rb_householder)
 
     def rows_capacity_used(self):
         import torch

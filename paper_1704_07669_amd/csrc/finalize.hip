@@ -140,7 +140,6 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
                                                  int q, int64_t rows, int RCH,
                                                  double* __restrict__ part,
                                                  const Ctrl* __restrict__ ctrl, int iter) {
-  if (skip_iter(ctrl, iter)) return;
   __shared__ double red[(TPB / 64 - 1) * MT * NQ * 4 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
   const int64_t r_begin = (int64_t)blockIdx.x * RCH;
@@ -157,6 +156,8 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
   if (r0 < r_end)
     tn_fetch<MT, NQ>(X, ldx, Y, ldy, p, q, r0 + 4 * g, r_end, r16, aligned && r0 + 16 <= r_end,
                      xa0, yb0);
+  // the iteration check after the first loads are in flight, so its latency overlaps theirs
+  if (skip_iter(ctrl, iter)) return;
   for (; r0 < r_end; r0 += 2 * STEP) {
     const int64_t r1 = r0 + STEP, r2 = r0 + 2 * STEP;
     if (r1 < r_end)
@@ -218,7 +219,6 @@ __global__ __launch_bounds__(kTnFinalThreads) void k_tn_final(const double* __re
                                                               double* __restrict__ out, int ldo,
                                                               const Ctrl* __restrict__ ctrl,
                                                               int iter) {
-  if (skip_iter(ctrl, iter)) return;
   constexpr int NW = kTnFinalThreads / 64;
   __shared__ double sm[NW * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -233,6 +233,7 @@ __global__ __launch_bounds__(kTnFinalThreads) void k_tn_final(const double* __re
     }
     if (ch < nchunks) s0 += part[(int64_t)ch * pq + e];
   }
+  if (skip_iter(ctrl, iter)) return;      // after the loads (uniform over the workgroup)
   sm[wave * 64 + lane] = s0 + s1;
   __syncthreads();
   if (wave == 0 && live) {
@@ -260,10 +261,11 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
                                                    int q, int64_t rows, double alpha,
                                                    const Ctrl* __restrict__ ctrl, int iter,
                                                    const double* __restrict__ Rs = nullptr) {
-  if (skip_iter(ctrl, iter)) return;
   extern __shared__ double ws[];              // p x QMAX, then 3 x QMAX x 64 partials
   double* part = ws + p * QMAX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int SMAX = JMAX / 4;
+  double x[SMAX];
   {
     // all loads first (clamped to W[0], which always exists), then the LDS stores
     constexpr int FILL = (JMAX * QMAX + TPB - 1) / TPB;
@@ -276,6 +278,18 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
       const double v = W[in ? a * ldw + c : 0];
       wv[u] = in ? v : 0.0;
     }
+    // every X value this lane needs (a = wave + 4 s < p), fetched in the same batch with clamped
+    // addresses, then the iteration check, whose latency overlaps the loads
+    const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t rc = r < rows ? r : 0;
+    const int plast = p > 0 ? p - 1 : 0;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      const int a = wave + 4 * s;
+      const double v = X[(int64_t)(a < p ? a : plast) * ldx + rc];
+      x[s] = a < p ? v : 0.0;
+    }
+    if (skip_iter(ctrl, iter)) return;
 #pragma unroll
     for (int u = 0; u < FILL; ++u) {
       const int idx = threadIdx.x + u * TPB;
@@ -285,17 +299,6 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
   const bool live = r < rows;
-  const int64_t rc = live ? r : 0;
-  // every X value this lane needs (a = wave + 4 s < p), fetched in one batch with clamped addresses
-  constexpr int SMAX = JMAX / 4;
-  double x[SMAX];
-  const int plast = p > 0 ? p - 1 : 0;
-#pragma unroll
-  for (int s = 0; s < SMAX; ++s) {
-    const int a = wave + 4 * s;
-    const double v = X[(int64_t)(a < p ? a : plast) * ldx + rc];
-    x[s] = a < p ? v : 0.0;
-  }
   double acc[QMAX];
 #pragma unroll
   for (int c = 0; c < QMAX; ++c) acc[c] = 0.0;
@@ -607,7 +610,6 @@ __global__ __launch_bounds__(kApplyThreads) void k_cholqr_apply(
     const double* __restrict__ Rprev, double* __restrict__ Rout, int last,
     const double* __restrict__ T, const double* __restrict__ Wt, double* __restrict__ Wn, int p,
     Ctrl* __restrict__ ctrl, int iter) {
-  if (skip_iter(ctrl, iter)) return;
   constexpr int LS = BMAX + 1, SL = (BMAX + 7) / 8;   // SL: slots per lane of the 8 x 8 grid
   __shared__ double a[BMAX * LS];     // G -> R (upper), R^-1 (strictly lower, transposed)
   __shared__ double rd[BMAX], dinv[BMAX], gd[BMAX];
@@ -635,6 +637,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_cholqr_apply(
   if (Rprev != nullptr)
     stage8(b * b, tid, kApplyThreads, [&](int idx) { return Rprev[idx]; },
            [&](int idx, double v) { rpv[idx] = v; });
+  if (skip_iter(ctrl, iter)) return;      // uniform; nothing has been written to global memory
   __syncthreads();
   bool bad = false;
   for (int j = 0; j < b; ++j) {
@@ -1518,7 +1521,7 @@ size_t reduce_workspace_elems(int64_t rows, int p, int q) {
   return (size_t)(nch * p * 32) + 64;
 }
 
-hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
+hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   Ctx cx{stream};
   const int b = f.b, l = f.l, t = l / b;
   const int64_t m = f.m, n = f.n;
@@ -1527,7 +1530,7 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
 
   // ---------------- column-block loop (Alg. 4 steps 9-15).  Cholesky QR of the blocks first; if a
   // block was flagged as too ill-conditioned for it, the loop is repeated with Householder TSQR.
-  for (int attempt = 0; attempt < 2 && cx.ok(); ++attempt) {
+  for (int attempt = f.force_loop ? 1 : 0; attempt < 2 && cx.ok(); ++attempt) {
     const bool chol = (attempt == 0);
     hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l);
     cx.chk();
@@ -1584,6 +1587,7 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
       nn<double>(cx, f.Bt + (int64_t)c0 * f.ldb, f.ldb, f.H + (int64_t)c0 * f.ldh, f.ldh, f.Bt,
                  f.ldb, p, sm.Wn, b, b, n, -1.0, ctrl, i, sm.R);
     }
+    f.path_loop = chol ? 0 : 1;
     if (!chol || !cx.ok()) break;
     int flagged = 1;
     cx.err = hipMemcpyAsync(&flagged, &ctrl->pad[0], sizeof(int), hipMemcpyDeviceToHost, stream);
@@ -1602,8 +1606,9 @@ hipError_t run_finalize(const FinalizeArgs& f, hipStream_t stream) {
 
   if (L > 0) {
     // ---------------- R_B: shifted Cholesky QR3 of B^T; Gram-Schmidt + TSQR if a pivot fails
-    const double* RBp = chol_qr3(cx, f, sm, L);
+    const double* RBp = f.force_rb ? nullptr : chol_qr3(cx, f, sm, L);
     if (!cx.ok()) return cx.err;
+    f.path_rb = (RBp == nullptr) ? 1 : 0;
     if (RBp == nullptr) {
       RBp = sm.RB;
       cx.err = launch_fill_f64(sm.RB, (int64_t)L * L, 0.0, stream);

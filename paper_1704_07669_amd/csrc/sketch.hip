@@ -159,6 +159,8 @@ struct sketch_s {
   int64_t rows = 0;
   int phase = 0;                    // 0: needs Omega, 1: ingesting, 2: finalized
   sketch_status sticky = SKETCH_OK;
+  int32_t path_loop = -1, path_rb = -1;   // QR methods the last finalize used
+  int32_t force_loop = 0, force_rb = 0;   // test hook: take the Householder paths directly
   uint64_t next_ticket = 1;
   hipEvent_t done_ev[kRing] = {};
   hipEvent_t copy_ev[kRing] = {};
@@ -509,6 +511,8 @@ sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t 
   f.ldu = ldu;
   f.V = V_dev;
   f.ldv = ldv;
+  f.force_loop = h->force_loop;
+  f.force_rb = h->force_rb;
   if (e == hipSuccess) e = run_finalize(f, h->stream);
   if (e == hipSuccess && h->prof) e = hipEventRecord(fb, h->stream);
   Ctrl hc;
@@ -517,11 +521,28 @@ sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t 
   if (e != hipSuccess) return h->dev_fail(e, "finalize");
   if (h->prof) h->recs.push_back({fa, fb, nullptr, 2});
   h->phase = 2;
+  h->path_loop = f.path_loop;
+  h->path_rb = f.path_rb;
   if (hc.nonfinite) {
     h->sticky = SKETCH_E_NONFINITE;
     return fail(SKETCH_E_NONFINITE, "an ingested block held NaN or Inf");
   }
   if (rank_out) *rank_out = hc.l_eff;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_householder) {
+  if (sketch_status st = check_handle(h)) return st;
+  h->force_loop = loop_householder ? 1 : 0;
+  h->force_rb = rb_householder ? 1 : 0;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_finalize_paths(sketch_t h, int32_t* loop_path, int32_t* rb_path) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (h->phase != 2) return fail(SKETCH_E_STATE, "not finalized");
+  if (loop_path) *loop_path = h->path_loop;
+  if (rb_path) *rb_path = h->path_rb;
   return SKETCH_OK;
 }
 

@@ -9,10 +9,12 @@ U64 = 2.0 ** -53
 
 
 def run_gpu(A, Omega, k, b, mode, blocks, src="f32", want_u=True, host=False, host_slots=3,
-            seed=None, keep_state=True):
-    """Run the library on A (numpy) split into row blocks of the given sizes.
+            seed=None, keep_state=True, force=(0, 0)):
+    """Run the library on A (numpy) split into row blocks of the given sizes; `force` takes the
+    Householder paths of the finalize directly (loop, R_B).
 
-    Returns dict(S, V, U, rank, G, H, Om) as numpy float64 (G, H before finalize)."""
+    Returns dict(S, V, U, rank, G, H, Om, paths) as numpy float64 (G, H before finalize); paths =
+    the finalize's (loop, R_B) methods, 0 Cholesky QR, 1 Householder."""
     import torch
     import paper_1704_07669_amd as sk
     m, n = A.shape
@@ -37,10 +39,12 @@ def run_gpu(A, Omega, k, b, mode, blocks, src="f32", want_u=True, host=False, ho
         G, H = sketch.state()
         out["G"], out["H"] = G.cpu().numpy(), H.cpu().numpy()
     out["Om"] = sketch.omega().cpu().numpy()
+    if any(force):
+        sketch.force_paths(*force)
     S, V, U, rank = sketch.finalize()
     torch.cuda.synchronize()
     out.update(S=S.cpu().numpy(), V=V.cpu().numpy(), U=None if U is None else U.cpu().numpy(),
-               rank=rank, tickets=tickets, sketch=sketch)
+               rank=rank, tickets=tickets, sketch=sketch, paths=sketch.finalize_paths())
     return out
 
 

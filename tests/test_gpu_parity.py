@@ -132,6 +132,40 @@ def test_rank_guard(gpu_lib, rank):
     assert oracle.sin_theta_max(V[:, :kk], out["V"][:, :kk]) < 1e-8
 
 
+@pytest.mark.parametrize("force", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_finalize_paths_agree(gpu_lib, ragged, force):
+    """Cholesky QR and the Householder fallback (forced through the test hook) both match the
+    reference on the same sketch; without forcing, a well-conditioned sketch takes Cholesky QR."""
+    A, Om, blocks, k, b = ragged["A"], ragged["Om"], ragged["blocks"], ragged["k"], ragged["b"]
+    out = run_gpu(A, Om, k, b, "f64", blocks, src="f64", keep_state=False, force=force)
+    ref = oracle.single_pass_pca(split_blocks(A, blocks), Om, k, b)
+    assert out["paths"] == force
+    assert out["rank"] == ref.rank
+    assert np.max(oracle.rel_sigma_error(out["S"], ref.S)) < 1e-10
+    assert oracle.sin_theta_max(ref.V, out["V"]) < 1e-8
+    assert oracle.sin_theta_max(ref.U, out["U"]) < 1e-8
+
+
+def test_cholqr_flags_ill_conditioned_block(gpu_lib):
+    """Two sketch columns nearly parallel (Omega columns equal up to 1e-6): the first block's Gram
+    matrix has a pivot far below 1e-10 of its diagonal, so the loop falls back to Householder
+    TSQR; the rank guard keeps every column (the pair still differs by far more than 1e-10 of
+    R's first diagonal) and the result matches the reference.  The near-dependence amplifies
+    rounding by about 1e6, hence the looser bounds."""
+    m, n, l, k, b = 1200, 600, 20, 8, 10
+    sig = synth.noisy_spectrum(synth.exp_spectrum(n, 8.0), 1e-6, 5)
+    A, _, _, _ = synth.small_matrix(m, n, sig, 5)
+    Om = synth.gaussian_omega(n, l, 6)
+    Om[:, 1] = Om[:, 0] + 1e-6 * Om[:, 1]
+    blocks = [500, 500, 200]
+    out = run_gpu(A, Om, k, b, "f64", blocks, src="f64", keep_state=False)
+    ref = oracle.single_pass_pca(split_blocks(A, blocks), Om, k, b)
+    assert out["paths"][0] == 1
+    assert out["rank"] == ref.rank == l
+    assert np.max(oracle.rel_sigma_error(out["S"], ref.S)) < 1e-8
+    assert oracle.sin_theta_max(ref.V, out["V"]) < 1e-6
+
+
 def test_zero_matrix(gpu_lib):
     A = np.zeros((300, 200))
     out = run_gpu(A, synth.gaussian_omega(200, 20, 1), 10, 10, "f32", [300], keep_state=False)
