@@ -37,6 +37,22 @@ __device__ __forceinline__ bool skip_iter(const Ctrl* ctrl, int iter) {
   return ctrl != nullptr && iter > ctrl->last_iter;
 }
 
+// 1/x and 1/sqrt(x) in FP64 from the hardware estimates, each refined by two Newton steps (the
+// estimates are good to about 2^-23, so two steps reach full FP64 precision).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
 // Sum of `cnt` per-thread values across a 256-thread block; result broadcast in out[0..cnt).
 template <int CMAX>
 __device__ __forceinline__ void block_sum(double (&v)[CMAX], int cnt, double* red, double* out) {
@@ -209,38 +225,54 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
   }
 }
 
-// out (p x q, row-major, leading dimension ldo) = sum of the chunk partials.  A workgroup owns 64
-// output entries (one per lane, consecutive in part, so the loads coalesce); its 16 waves take the
+// Sum of the chunk partials (chunk stride pq entries) for the entries e0 .. e0 + ecount - 1, entry
+// e = a q + c going to out[a * ldo + c] (row-major, leading dimension ldo).  A workgroup owns 64
+// entries (one per lane, consecutive in part, so the loads coalesce); its 16 waves take the
 // chunks in interleaved order and their partial sums are added in wave order through LDS, so the
 // summation order is fixed.
 constexpr int kTnFinalThreads = 1024;
+
+// This lane's sum over the chunks of wave `wave` (chunks wave, wave + NW, ...) for entry ec: eight
+// chunks per batch, all loads issued before the adds (clamped to the wave's first chunk, whose
+// value is then dropped), so a wave pays one memory latency per eight chunks.
+template <int NW>
+__device__ __forceinline__ double chunk_sum(const double* __restrict__ part, int nchunks,
+                                            int64_t pq, int64_t ec, int wave) {
+  double s = 0;
+  for (int ch0 = wave; ch0 < nchunks; ch0 += 8 * NW) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int ch = ch0 + u * NW;
+      v[u] = part[(int64_t)(ch < nchunks ? ch : ch0) * pq + ec];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ch0 + u * NW < nchunks) s += v[u];
+  }
+  return s;
+}
+
 __global__ __launch_bounds__(kTnFinalThreads) void k_tn_final(const double* __restrict__ part,
-                                                              int nchunks, int p, int q,
+                                                              int nchunks, int64_t pq, int64_t e0,
+                                                              int64_t ecount, int q,
                                                               double* __restrict__ out, int ldo,
                                                               const Ctrl* __restrict__ ctrl,
                                                               int iter) {
   constexpr int NW = kTnFinalThreads / 64;
   __shared__ double sm[NW * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t e = (int64_t)blockIdx.x * 64 + lane, pq = (int64_t)p * q;
-  const bool live = e < pq;
-  double s0 = 0, s1 = 0;
-  if (live) {
-    int ch = wave;
-    for (; ch + NW < nchunks; ch += 2 * NW) {
-      s0 += part[(int64_t)ch * pq + e];
-      s1 += part[(int64_t)(ch + NW) * pq + e];
-    }
-    if (ch < nchunks) s0 += part[(int64_t)ch * pq + e];
-  }
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = i < ecount;
+  const double s = chunk_sum<NW>(part, nchunks, pq, e0 + (live ? i : 0), wave);
   if (skip_iter(ctrl, iter)) return;      // after the loads (uniform over the workgroup)
-  sm[wave * 64 + lane] = s0 + s1;
+  sm[wave * 64 + lane] = s;
   __syncthreads();
   if (wave == 0 && live) {
-    double s = sm[lane];
-    for (int w = 1; w < NW; ++w) s += sm[w * 64 + lane];
-    const int a = (int)(e / q), c = (int)(e % q);
-    out[a * ldo + c] = s;
+    double t = sm[lane];
+    for (int w = 1; w < NW; ++w) t += sm[w * 64 + lane];
+    const int64_t e = e0 + i;
+    out[(e / q) * ldo + e % q] = t;
   }
 }
 
@@ -557,11 +589,7 @@ __global__ __launch_bounds__(TPB) void k_house_form(double* __restrict__ X, int6
 // R = R2 R1 (upper triangular), then the rank guard of the column-block loop.
 // Rank guard on the combined R_i (b x b, row-major): the leading columns whose diagonal exceeds
 // kGuardTau r0 are kept (r0 = R_0[0][0]); the first iteration that keeps fewer than b is the last.
-__device__ void guard_apply(const double* R, int b, int iter, Ctrl* ctrl) {
-  if (iter == 0) ctrl->r0 = R[0];
-  const double thr = kGuardTau * ctrl->r0;
-  int keep = 0;
-  while (keep < b && fabs(R[keep * b + keep]) > thr) ++keep;
+__device__ void guard_store(int keep, int b, int iter, Ctrl* ctrl) {
   if (keep < b) {
     ctrl->last_iter = iter;
     ctrl->keep_last = keep;
@@ -570,6 +598,13 @@ __device__ void guard_apply(const double* R, int b, int iter, Ctrl* ctrl) {
     ctrl->l_eff = (iter + 1) * b;
     ctrl->keep_last = b;
   }
+}
+__device__ void guard_apply(const double* R, int b, int iter, Ctrl* ctrl) {
+  if (iter == 0) ctrl->r0 = R[0];
+  const double thr = kGuardTau * ctrl->r0;
+  int keep = 0;
+  while (keep < b && fabs(R[keep * b + keep]) > thr) ++keep;
+  guard_store(keep, b, iter, ctrl);
 }
 
 __global__ void k_guard(const double* __restrict__ R1, const double* __restrict__ R2,
@@ -595,30 +630,241 @@ __global__ void k_guard(const double* __restrict__ R1, const double* __restrict_
 // flagged in ctrl->pad[0], and the host repeats the whole loop with Householder TSQR.
 constexpr double kCholQrPivot = 1e-10;
 
-// Y <- Y R^-1 in place for G = R^T R (b x b, row-major, leading dimension b, upper triangle read).
-// One wave per workgroup and 64 rows each: every workgroup factors G itself in LDS (b steps), so the
-// factorisation needs no launch of its own, all workgroups apply the same R^-1, and its barriers
-// are those of a single wave.  Workgroup 0 writes Rout = R Rprev (Rprev null: identity).  On the
-// last step (`last` set) every workgroup also takes the rank guard's decision from the diagonal of
-// R Rprev and writes zeros in place of the columns it drops (the basis vectors past the numerical
-// rank), and workgroup 0 records the decision in ctrl and forms Wn = T + W (p x b, the combined
-// weights of the numerator of Eq. 9).
-constexpr int kApplyThreads = 64;
+// The Gram matrix G = Y^T Y of a column block (b x b, entries e0 .. e0 + b^2 - 1 of the row
+// reduction's chunk partials, chunk stride pq) and its Cholesky factor, once, in one workgroup:
+// the 16 waves sum the chunks (fixed order, as k_tn_final), then wave 0 factors G in registers:
+// lane c holds column c of G (then of R, then of X = R^-1), takes the entries of other columns by
+// lane broadcasts, and G is padded with the identity to BMAX columns so that no loop tests a
+// bound (the padded factor is diag(R, I)).  Writes X (b x b, row-major) and Rout = R Rprev
+// (Rprev null: identity).  On the last step of a block (`last` set) it also applies the rank guard
+// to R Rprev and forms Wn = T + W (p x b, the combined weights of the numerator of Eq. 9).  A pivot
+// below kCholQrPivot G_jj, or a non-finite one, marks the block (ctrl->pad[0] = 1) instead.
+constexpr int kGramThreads = 512;     // the factoring wave needs up to 256 registers
 template <int BMAX>
-__global__ __launch_bounds__(kApplyThreads) void k_cholqr_apply(
+__global__ __launch_bounds__(kGramThreads) void k_gram_chol(
+    const double* __restrict__ part, int nchunks, int64_t pq, int64_t e0, int b,
+    const double* __restrict__ Rprev, double* __restrict__ Rout, double* __restrict__ Xout,
+    int last, const double* __restrict__ T, const double* __restrict__ Wt,
+    double* __restrict__ Wn, int p, Ctrl* __restrict__ ctrl, int iter) {
+  constexpr int NW = kGramThreads / 64;
+  __shared__ double sm[NW * 64];
+  __shared__ double gram[BMAX * BMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int bb = b * b;
+  for (int og = 0; og < bb; og += 64) {                      // uniform
+    const int idx = og + lane;
+    const bool live = idx < bb;
+    const double s = chunk_sum<NW>(part, nchunks, pq, e0 + (live ? idx : 0), wave);
+    sm[wave * 64 + lane] = s;
+    __syncthreads();
+    if (wave == 0 && live) {
+      double t = sm[lane];
+      for (int w = 1; w < NW; ++w) t += sm[w * 64 + lane];
+      gram[idx] = t;
+    }
+    __syncthreads();
+  }
+  if (skip_iter(ctrl, iter)) return;                         // uniform, after the loads
+  if (last)
+    for (int idx = threadIdx.x; idx < p * b; idx += kGramThreads) Wn[idx] = T[idx] + Wt[idx];
+  if (wave != 0) return;
+  const bool lcol = lane < b;
+  double a[BMAX], rpc[BMAX];
+#pragma unroll
+  for (int i = 0; i < BMAX; ++i) a[i] = (i < b && lcol) ? gram[i * b + lane] : (i == lane ? 1.0 : 0.0);
+  const double gdg = lcol ? gram[lane * b + lane] : 1.0;
+#pragma unroll
+  for (int k = 0; k < BMAX; ++k)                             // column of Rprev, or of I
+    rpc[k] = (Rprev != nullptr && k < b && lcol) ? Rprev[k * b + lane] : (k == lane ? 1.0 : 0.0);
+  // right-looking Cholesky, G = R^T R: lane c ends with R[i][c] (i <= c) in a[i]
+  bool bad = false;
+  double rinv[BMAX];                                         // 1 / R[j][j]
+#pragma unroll
+  for (int j = 0; j < BMAX; ++j) {
+    const double d = dpp::lane(a[j], j);
+    bad |= !(d > kCholQrPivot * dpp::lane(gdg, j)) || !(d < INFINITY);
+    // 1/sqrt(d) from the refined hardware estimate; R[j][j] = d / sqrt(d)
+    const double inv = rsq_nr(d), rj = d * inv;
+    rinv[j] = inv;
+    a[j] = (lane == j) ? rj : (lane > j ? a[j] * inv : a[j]);
+#pragma unroll
+    for (int i = j + 1; i < BMAX; ++i) {
+      const double rji = dpp::lane(a[j], i);                 // R[j][i]
+      a[i] = (lane >= i) ? fma(-rji, a[j], a[i]) : a[i];
+    }
+  }
+  if (bad) {
+    if (lane == 0) ctrl->pad[0] = 1;
+    return;
+  }
+  // X = R^-1 by columns: lane c solves R x = e_c from the bottom, x[i] = X[i][c]
+  double x[BMAX];
+#pragma unroll
+  for (int i = BMAX - 1; i >= 0; --i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = i + 1; k < BMAX; ++k) {
+      const double rik = dpp::lane(a[i], k);                 // R[i][k]
+      acc = (lane >= k) ? fma(rik, x[k], acc) : acc;
+    }
+    x[i] = (lane == i) ? rinv[i] : ((lane > i) ? -rinv[i] * acc : 0.0);
+  }
+  // Rout = R Rprev (upper triangular) and X: lane c writes column c
+#pragma unroll
+  for (int i = 0; i < BMAX; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = i; k < BMAX; ++k) s = (lane >= k) ? fma(dpp::lane(a[i], k), rpc[k], s) : s;
+    if (i < b && lcol) {
+      Rout[i * b + lane] = s;
+      Xout[i * b + lane] = x[i];
+    }
+  }
+  if (last) {
+    // the rank guard on diag(R Rprev) = diag(R) diag(Rprev)
+    const double r00 = dpp::lane(a[0], 0) * dpp::lane(rpc[0], 0);
+    const double thr = kGuardTau * (iter == 0 ? r00 : ctrl->r0);
+    int keep = b;
+#pragma unroll
+    for (int j = BMAX - 1; j >= 0; --j) {
+      const double djj = dpp::lane(a[j], j) * dpp::lane(rpc[j], j);
+      if (j < b && !(fabs(djj) > thr)) keep = j;             // first column at or below the threshold
+    }
+    if (lane == 0) {
+      if (iter == 0) ctrl->r0 = r00;
+      guard_store(keep, b, iter, ctrl);
+    }
+  }
+}
+
+// One Cholesky QR step for narrow blocks (b <= B <= 12): every lane factors the b x b Gram matrix
+// G (row-major, leading dimension b, upper triangle read, padded with the identity to B) in its own
+// registers, a few hundred FP64 operations with no communication, then solves x R = y for its
+// own row y of Y by forward substitution and writes x back (Y <- Y R^-1).  Workgroup 0 also writes
+// Rout = R Rprev (Rprev null: identity); on the last step (`last` set) every lane takes the rank
+// guard's decision from diag(R) diag(Rprev) and writes zeros in place of the dropped columns, and
+// workgroup 0 records the decision and forms Wn = T + W (p x b, the combined weights of the
+// numerator of Eq. 9).  A pivot below kCholQrPivot G_jj, or a non-finite one, marks the block
+// (ctrl->pad[0] = 1) and leaves Y as it was.
+template <int B>
+__host__ __device__ constexpr int upk(int i, int c) { return i * B - i * (i - 1) / 2 + (c - i); }
+
+constexpr int kLaneCholThreads = 256;
+template <int B>
+__global__ __launch_bounds__(kLaneCholThreads) void k_cholqr_lane(
     double* __restrict__ Y, int64_t ldy, int64_t rows, const double* __restrict__ G, int b,
     const double* __restrict__ Rprev, double* __restrict__ Rout, int last,
     const double* __restrict__ T, const double* __restrict__ Wt, double* __restrict__ Wn, int p,
     Ctrl* __restrict__ ctrl, int iter) {
-  constexpr int LS = BMAX + 1, SL = (BMAX + 7) / 8;   // SL: slots per lane of the 8 x 8 grid
-  __shared__ double a[BMAX * LS];     // G -> R (upper), R^-1 (strictly lower, transposed)
-  __shared__ double rd[BMAX], dinv[BMAX], gd[BMAX];
-  __shared__ double rp[BMAX * BMAX], rpv[BMAX * BMAX];   // R Rprev, Rprev
-  const int tid = threadIdx.x, ty = tid >> 3, tx = tid & 7;
-  const int64_t r = (int64_t)blockIdx.x * kApplyThreads + tid;
-  // this lane's row of Y, fetched before the factorisation so the load overlaps it
-  double y[BMAX];
+  constexpr int NU = B * (B + 1) / 2;
+  __shared__ double rs[B * B], rpv[B * B];
+  const int tid = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * kLaneCholThreads + tid;
   const int64_t rc = r < rows ? r : 0;
+  double y[B], R[NU], gd[B], pd[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    const double v = Y[(c < b ? c : 0) * ldy + rc];
+    y[c] = (c < b) ? v : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int c = i; c < B; ++c) {
+      const double v = G[(c < b ? i : 0) * b + (c < b ? c : 0)];
+      R[upk<B>(i, c)] = (c < b) ? v : (i == c ? 1.0 : 0.0);
+    }
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    gd[j] = R[upk<B>(j, j)];
+    const double v = (Rprev != nullptr) ? Rprev[(j < b ? j : 0) * (b + 1)] : 1.0;
+    pd[j] = (j < b) ? v : 1.0;
+  }
+  if (skip_iter(ctrl, iter)) return;
+  // right-looking Cholesky in place, G = R^T R
+  bool bad = false;
+  double rinv[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const double d = R[upk<B>(j, j)];
+    bad |= !(d > kCholQrPivot * gd[j]) || !(d < INFINITY);
+    const double inv = rsq_nr(d);                     // refined 1/sqrt(d); R[j][j] = d / sqrt(d)
+    rinv[j] = inv;
+    R[upk<B>(j, j)] = d * inv;
+#pragma unroll
+    for (int c = j + 1; c < B; ++c) R[upk<B>(j, c)] *= inv;
+#pragma unroll
+    for (int i = j + 1; i < B; ++i)
+#pragma unroll
+      for (int c = i; c < B; ++c)
+        R[upk<B>(i, c)] = fma(-R[upk<B>(j, i)], R[upk<B>(j, c)], R[upk<B>(i, c)]);
+  }
+  if (bad) {
+    if (blockIdx.x == 0 && tid == 0) ctrl->pad[0] = 1;
+    return;
+  }
+  // the rank guard's decision: diag(R Rprev) = diag(R) diag(Rprev)
+  const double r00 = R[upk<B>(0, 0)] * pd[0];
+  int keep = b;
+  if (last) {
+    const double thr = kGuardTau * (iter == 0 ? r00 : ctrl->r0);
+#pragma unroll
+    for (int j = B - 1; j >= 0; --j)
+      if (j < b && !(fabs(R[upk<B>(j, j)] * pd[j]) > thr)) keep = j;
+  }
+  // x R = y, forward substitution over the columns
+  if (r < rows) {
+    double x[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      double v = y[c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) v = fma(-x[k], R[upk<B>(k, c)], v);
+      x[c] = v * rinv[c];
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c)
+      if (c < b) Y[c * ldy + r] = (c < keep) ? x[c] : 0.0;
+  }
+  if (blockIdx.x != 0) return;
+  if (tid < b * b) rpv[tid] = (Rprev != nullptr) ? Rprev[tid] : 0.0;
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int c = 0; c < B; ++c) rs[i * B + c] = (c >= i) ? R[upk<B>(i, c)] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < b * b; idx += kLaneCholThreads) {
+    const int i = idx / b, c = idx % b;
+    double s = 0.0;
+    if (c >= i) {
+      if (Rprev == nullptr) s = rs[i * B + c];
+      else
+        for (int k = i; k <= c; ++k) s = fma(rs[i * B + k], rpv[k * b + c], s);
+    }
+    Rout[idx] = s;
+  }
+  if (!last) return;
+  for (int idx = tid; idx < p * b; idx += kLaneCholThreads) Wn[idx] = T[idx] + Wt[idx];
+  if (tid == 0) {
+    if (iter == 0) ctrl->r0 = r00;
+    guard_store(keep, b, iter, ctrl);
+  }
+}
+
+// Y <- Y X in place (X = R^-1 from k_gram_chol, b x b row-major, staged in LDS zero-padded to
+// BMAX).  On the last step of a block the columns the rank guard dropped are written as zeros.
+constexpr int kApplyThreads = 256;
+template <int BMAX>
+__global__ __launch_bounds__(kApplyThreads) void k_cholqr_apply(
+    double* __restrict__ Y, int64_t ldy, int64_t rows, const double* __restrict__ X, int b,
+    int last, const Ctrl* __restrict__ ctrl, int iter) {
+  __shared__ double xs[BMAX * BMAX];
+  const int tid = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * kApplyThreads + tid;
+  const int64_t rc = r < rows ? r : 0;
+  double y[BMAX];
 #pragma unroll
   for (int c = 0; c < BMAX; ++c) {
     const double v = Y[(c < b ? c : 0) * ldy + rc];
@@ -626,103 +872,21 @@ __global__ __launch_bounds__(kApplyThreads) void k_cholqr_apply(
   }
   stage8(BMAX * BMAX, tid, kApplyThreads,
          [&](int idx) {
-           const int i = idx / BMAX, c = idx % BMAX;
-           return (i < b && c < b) ? G[i * b + c] : 0.0;
+           const int k = idx / BMAX, c = idx % BMAX;
+           return (k < b && c < b) ? X[k * b + c] : 0.0;
          },
-         [&](int idx, double v) {
-           const int i = idx / BMAX, c = idx % BMAX;
-           a[i * LS + c] = (c >= i) ? v : 0.0;
-           if (i == c) gd[i] = v;
-         });
-  if (Rprev != nullptr)
-    stage8(b * b, tid, kApplyThreads, [&](int idx) { return Rprev[idx]; },
-           [&](int idx, double v) { rpv[idx] = v; });
-  if (skip_iter(ctrl, iter)) return;      // uniform; nothing has been written to global memory
+         [&](int idx, double v) { xs[idx] = v; });
+  if (skip_iter(ctrl, iter)) return;
+  const int keep = (last && ctrl != nullptr && iter == ctrl->last_iter) ? ctrl->keep_last : b;
   __syncthreads();
-  bool bad = false;
-  for (int j = 0; j < b; ++j) {
-    const double d = a[j * LS + j];
-    if (!(d > kCholQrPivot * gd[j]) || !(d < INFINITY)) { bad = true; break; }   // uniform
-    const double inv = 1.0 / sqrt(d);
-    if (tid == 0) rd[j] = sqrt(d);
-    if (j + 1 + tid < b) a[j * LS + j + 1 + tid] *= inv;
-    __syncthreads();
+  if (r >= rows) return;
 #pragma unroll
-    for (int m = 0; m < SL; ++m) {
-      const int i = j + 1 + ty + 8 * m;
-#pragma unroll
-      for (int n = 0; n < SL; ++n) {
-        const int c = j + 1 + tx + 8 * n;
-        if (i < b && c < b && c >= i) a[i * LS + c] = fma(-a[j * LS + i], a[j * LS + c], a[i * LS + c]);
-      }
-    }
-    __syncthreads();
-  }
-  if (bad) {
-    if (blockIdx.x == 0 && tid == 0) ctrl->pad[0] = 1;
-    return;
-  }
-  if (tid < b) dinv[tid] = 1.0 / rd[tid];
-  __syncthreads();
-  // R^-1 by back substitution from the bottom row; R^-1[k][c] (k < c) stored at a[c][k]
-  for (int i = b - 1; i >= 0; --i) {
-    if (i + 1 + tid < b) a[(i + 1 + tid) * LS + i] *= dinv[i];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < SL; ++m) {
-      const int k = ty + 8 * m;
-#pragma unroll
-      for (int n = 0; n < SL; ++n) {
-        const int c = i + tx + 8 * n;
-        if (k < i && c < b) {
-          const double xc = (c == i) ? dinv[i] : a[c * LS + i];
-          a[c * LS + k] = fma(-a[k * LS + i], xc, a[c * LS + k]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // the rank guard's decision on the last step: diag(R Rprev) = diag(R) diag(Rprev)
-  int keep = b;
-  if (last) {
-    const double r00 = rd[0] * (Rprev ? rpv[0] : 1.0);
-    const double thr = kGuardTau * (iter == 0 ? r00 : ctrl->r0);
-    keep = 0;
-    while (keep < b && fabs(rd[keep] * (Rprev ? rpv[keep * b + keep] : 1.0)) > thr) ++keep;
-  }
-  // out_c = sum_{k <= c} y_k R^-1[k][c]
-  if (r < rows) {
-    double o[BMAX];
-#pragma unroll
-    for (int c = 0; c < BMAX; ++c) o[c] = 0.0;
-#pragma unroll
-    for (int k = 0; k < BMAX; ++k) {
-      if (k < b) {
-#pragma unroll
-        for (int c = k; c < BMAX; ++c) o[c] = fma(y[k], (c == k) ? dinv[c] : a[c * LS + k], o[c]);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < BMAX; ++c)
-      if (c < b) Y[c * ldy + r] = (c < keep) ? o[c] : 0.0;
-  }
-  if (blockIdx.x != 0) return;
-  // Rout = R Rprev (upper triangular), then the guard and Wn on the last step
-  for (int idx = tid; idx < b * b; idx += kApplyThreads) {
-    const int i = idx / b, c = idx % b;
+  for (int c = 0; c < BMAX; ++c) {
     double s = 0.0;
-    if (c >= i) {
-      if (Rprev == nullptr) s = (c == i) ? rd[i] : a[i * LS + c];
-      else
-        for (int k = i; k <= c; ++k) s = fma(k == i ? rd[i] : a[i * LS + k], rpv[k * b + c], s);
-    }
-    rp[idx] = s;
-    Rout[idx] = s;
+#pragma unroll
+    for (int k = 0; k <= c; ++k) s = fma(y[k], xs[k * BMAX + c], s);
+    if (c < b) Y[c * ldy + r] = (c < keep) ? s : 0.0;
   }
-  if (!last) return;
-  for (int idx = tid; idx < p * b; idx += kApplyThreads) Wn[idx] = T[idx] + Wt[idx];
-  __syncthreads();
-  if (tid == 0) guard_apply(rp, b, iter, ctrl);
 }
 
 // out = A + B (p x q, row-major with leading dimension q)
@@ -935,21 +1099,6 @@ __device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
   if (p > q) { const int t = p; p = q; q = t; }
 }
 
-// 1/x and 1/sqrt(x) in FP64 from the hardware estimates, each refined by two Newton steps (the
-// estimates are good to about 2^-23, so two steps reach full FP64 precision).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = y * fma(-x, y, 2.0);
-  y = y * fma(-x, y, 2.0);
-  return y;
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
-}
 
 // 1/x from the hardware estimate and one Newton step (about 2^-46 relative): enough for a
 // rotation angle, which only steers convergence.
@@ -1258,10 +1407,11 @@ void tn_launch(Ctx& cx, int nq, dim3 grid, const double* X, int64_t ldx, const d
                        rch, part, ctrl, iter);
 }
 
-// out (p x q row-major, ldo) = X[:, 0:p]^T Y[:, 0:q] over `rows` rows (p <= 128, q <= 32).
-void tn(Ctx& cx, const double* X, int64_t ldx, const double* Y, int64_t ldy, int p, int q,
-        int64_t rows, double* part, double* out, int ldo, const Ctrl* ctrl, int iter) {
-  if (!cx.ok() || p == 0 || q == 0) return;
+// Chunk partials of X[:, 0:p]^T Y[:, 0:q] over `rows` rows (p <= 128, q <= 32) into `part`;
+// returns the number of chunks.
+int tn_partials(Ctx& cx, const double* X, int64_t ldx, const double* Y, int64_t ldy, int p, int q,
+                int64_t rows, double* part, const Ctrl* ctrl, int iter) {
+  if (!cx.ok() || p == 0 || q == 0) return 0;
   const int rch = tn_rows_per_chunk(rows);
   const int nch = (int)cdiv<int64_t>(rows, rch);
   const int mt = cdiv(p, 16), nq = cdiv(q, 16);
@@ -1277,10 +1427,23 @@ void tn(Ctx& cx, const double* X, int64_t ldx, const double* Y, int64_t ldy, int
     default: tn_launch<8>(cx, nq, grid, X, ldx, Y, ldy, p, q, rows, rch, part, ctrl, iter); break;
   }
   cx.chk();
-  if (!cx.ok()) return;
-  hipLaunchKernelGGL(k_tn_final, dim3(cdiv(p * q, 64)), dim3(kTnFinalThreads), 0, cx.s, part, nch,
-                     p, q, out, ldo, ctrl, iter);
+  return nch;
+}
+
+// Entries e0 .. e0 + ecount - 1 of the p x q product from its chunk partials, into out.
+void tn_final(Ctx& cx, const double* part, int nch, int p, int q, int64_t e0, int64_t ecount,
+              double* out, int ldo, const Ctrl* ctrl, int iter) {
+  if (!cx.ok() || ecount <= 0) return;
+  hipLaunchKernelGGL(k_tn_final, dim3((unsigned)cdiv<int64_t>(ecount, 64)), dim3(kTnFinalThreads),
+                     0, cx.s, part, nch, (int64_t)p * q, e0, ecount, q, out, ldo, ctrl, iter);
   cx.chk();
+}
+
+// out (p x q row-major, ldo) = X[:, 0:p]^T Y[:, 0:q] over `rows` rows (p <= 128, q <= 32).
+void tn(Ctx& cx, const double* X, int64_t ldx, const double* Y, int64_t ldy, int p, int q,
+        int64_t rows, double* part, double* out, int ldo, const Ctrl* ctrl, int iter) {
+  const int nch = tn_partials(cx, X, ldx, Y, ldy, p, q, rows, part, ctrl, iter);
+  if (nch > 0) tn_final(cx, part, nch, p, q, 0, (int64_t)p * q, out, ldo, ctrl, iter);
 }
 
 template <typename BT>
@@ -1365,7 +1528,7 @@ void tsqr(Ctx& cx, double* X, int64_t ldx, int64_t rows, int b, double* ws, doub
 
 // Small-buffer layout (doubles), see finalize_small_elems.
 struct Small {
-  double *W, *T, *C, *Wn, *R1, *R2, *R, *RB, *C1, *C2, *Jm, *Wm, *sig, *Jk, *Wk, *sgn;
+  double *W, *T, *C, *Wn, *R1, *R2, *R, *X, *RB, *C1, *C2, *Jm, *Wm, *sig, *Jk, *Wk, *sgn;
   int* perm; int* info;
 };
 Small carve_small(double* base, int l, int b) {
@@ -1374,7 +1537,7 @@ Small carve_small(double* base, int l, int b) {
   double* c = base;
   auto take = [&](int64_t cnt) { double* r = c; c += rup<int64_t>(cnt, 32); return r; };
   sm.W = take(P); sm.T = take(P); sm.C = take(P); sm.Wn = take(P);
-  sm.R1 = take(32 * 32); sm.R2 = take(32 * 32); sm.R = take(32 * 32);
+  sm.R1 = take(32 * 32); sm.R2 = take(32 * 32); sm.R = take(32 * 32); sm.X = take(32 * 32);
   sm.RB = take((int64_t)l * l); sm.C1 = take(P); sm.C2 = take(P);
   sm.Jm = take((int64_t)l * l + l); sm.Wm = take((int64_t)l * l); sm.sig = take(l);
   sm.Jk = take((int64_t)l * l); sm.Wk = take((int64_t)l * l); sm.sgn = take(l);
@@ -1383,21 +1546,59 @@ Small carve_small(double* base, int l, int b) {
   return sm;
 }
 
-// One Cholesky QR step of the column block Y (rows x b, in place), see k_cholqr_apply.
-void cholqr(Ctx& cx, double* Y, int64_t ldy, int64_t rows, const double* G, int b,
-            const double* Rprev, double* Rout, bool last, const Small& sm, int p, Ctrl* ctrl,
-            int iter) {
+// One Cholesky QR step of the column block Y (rows x b, in place): the Gram matrix from the row
+// reduction's chunk partials (entries e0 .. e0 + b^2 - 1, chunk stride pq) and its factor in one
+// workgroup (k_gram_chol), then Y <- Y R^-1 (k_cholqr_apply).
+void cholqr(Ctx& cx, double* Y, int64_t ldy, int64_t rows, const double* part, int nch,
+            int64_t pq, int64_t e0, int b, const double* Rprev, double* Rout, bool last,
+            const Small& sm, int p, Ctrl* ctrl, int iter) {
   if (!cx.ok()) return;
+  const dim3 g1(1), b1(kGramThreads);
   const dim3 g((unsigned)cdiv<int64_t>(rows, kApplyThreads)), blk(kApplyThreads);
   const int lf = last ? 1 : 0;
-  if (b <= 8)
-    hipLaunchKernelGGL(k_cholqr_apply<8>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
-                       sm.T, sm.W, sm.Wn, p, ctrl, iter);
-  else if (b <= 16)
-    hipLaunchKernelGGL(k_cholqr_apply<16>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
+  if (b <= 8) {
+    hipLaunchKernelGGL(k_gram_chol<8>, g1, b1, 0, cx.s, part, nch, pq, e0, b, Rprev, Rout, sm.X,
+                       lf, sm.T, sm.W, sm.Wn, p, ctrl, iter);
+    cx.chk();
+    if (cx.ok())
+      hipLaunchKernelGGL(k_cholqr_apply<8>, g, blk, 0, cx.s, Y, ldy, rows, sm.X, b, lf, ctrl, iter);
+  } else if (b <= 16) {
+    hipLaunchKernelGGL(k_gram_chol<16>, g1, b1, 0, cx.s, part, nch, pq, e0, b, Rprev, Rout, sm.X,
+                       lf, sm.T, sm.W, sm.Wn, p, ctrl, iter);
+    cx.chk();
+    if (cx.ok())
+      hipLaunchKernelGGL(k_cholqr_apply<16>, g, blk, 0, cx.s, Y, ldy, rows, sm.X, b, lf, ctrl, iter);
+  } else {
+    hipLaunchKernelGGL(k_gram_chol<32>, g1, b1, 0, cx.s, part, nch, pq, e0, b, Rprev, Rout, sm.X,
+                       lf, sm.T, sm.W, sm.Wn, p, ctrl, iter);
+    cx.chk();
+    if (cx.ok())
+      hipLaunchKernelGGL(k_cholqr_apply<32>, g, blk, 0, cx.s, Y, ldy, rows, sm.X, b, lf, ctrl, iter);
+  }
+  cx.chk();
+}
+
+// Blocks of at most this many columns take the per-lane factorisation (k_cholqr_lane).
+constexpr int kLaneCholMax = 12;
+
+// One Cholesky QR step of a narrow column block (b <= kLaneCholMax) from its Gram matrix G.
+void cholqr_lane(Ctx& cx, double* Y, int64_t ldy, int64_t rows, const double* G, int b,
+                 const double* Rprev, double* Rout, bool last, const Small& sm, int p, Ctrl* ctrl,
+                 int iter) {
+  if (!cx.ok()) return;
+  const dim3 g((unsigned)cdiv<int64_t>(rows, kLaneCholThreads)), blk(kLaneCholThreads);
+  const int lf = last ? 1 : 0;
+  if (b <= 4)
+    hipLaunchKernelGGL(k_cholqr_lane<4>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf, sm.T,
+                       sm.W, sm.Wn, p, ctrl, iter);
+  else if (b <= 8)
+    hipLaunchKernelGGL(k_cholqr_lane<8>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf, sm.T,
+                       sm.W, sm.Wn, p, ctrl, iter);
+  else if (b <= 10)
+    hipLaunchKernelGGL(k_cholqr_lane<10>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
                        sm.T, sm.W, sm.Wn, p, ctrl, iter);
   else
-    hipLaunchKernelGGL(k_cholqr_apply<32>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
+    hipLaunchKernelGGL(k_cholqr_lane<12>, g, blk, 0, cx.s, Y, ldy, rows, G, b, Rprev, Rout, lf,
                        sm.T, sm.W, sm.Wn, p, ctrl, iter);
   cx.chk();
 }
@@ -1495,7 +1696,7 @@ hipError_t finalize_prepare() {
 size_t finalize_small_elems(int l, int b) {
   (void)b;
   const int64_t P = (int64_t)l * 32;
-  int64_t e = 6 * rup<int64_t>(P, 32) + 3 * 1024 + 5 * rup<int64_t>((int64_t)l * l + l, 32) +
+  int64_t e = 6 * rup<int64_t>(P, 32) + 4 * 1024 + 5 * rup<int64_t>((int64_t)l * l + l, 32) +
               3 * rup<int64_t>(l, 32) + 32;
   return (size_t)e + 1024;
 }
@@ -1547,16 +1748,35 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
         nn<float>(cx, Qi, f.ldq, (const float*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
                   sm.W, b, b, m, -1.0, ctrl, i);
       if (chol) {
-        // [T; Y^T Y] = [Q, Y]^T Y in one reduction (Q and the slot of Q_i are adjacent)
-        tn(cx, f.Q, f.ldq, Qi, f.ldq, p + b, b, m, f.red_ws, sm.T, b, ctrl, i);
-        cholqr(cx, Qi, f.ldq, m, sm.T + (int64_t)p * b, b, nullptr, sm.R1, false, sm, p, ctrl, i);
-        // C = Q^T Q_i; Z = Q_i - Q C; two Cholesky QR steps on Z
-        tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
-        nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
-        tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C1, b, ctrl, i);
-        cholqr(cx, Qi, f.ldq, m, sm.C1, b, sm.R1, sm.R2, false, sm, p, ctrl, i);
-        tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C2, b, ctrl, i);
-        cholqr(cx, Qi, f.ldq, m, sm.C2, b, sm.R2, sm.R, true, sm, p, ctrl, i);
+        // [T; Y^T Y] = [Q, Y]^T Y in one row reduction (Q and the slot of Q_i are adjacent): T
+        // from the first p b entries, the Gram matrix of Y from the last b^2
+        int nch = tn_partials(cx, f.Q, f.ldq, Qi, f.ldq, p + b, b, m, f.red_ws, ctrl, i);
+        if (b <= kLaneCholMax) {
+          // narrow blocks: the Gram matrices in full, each factored by every lane of the apply
+          tn_final(cx, f.red_ws, nch, p + b, b, 0, (int64_t)(p + b) * b, sm.T, b, ctrl, i);
+          cholqr_lane(cx, Qi, f.ldq, m, sm.T + (int64_t)p * b, b, nullptr, sm.R1, false, sm, p,
+                      ctrl, i);
+          // C = Q^T Q_i; Z = Q_i - Q C; two Cholesky QR steps on Z
+          tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
+          nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+          tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C1, b, ctrl, i);
+          cholqr_lane(cx, Qi, f.ldq, m, sm.C1, b, sm.R1, sm.R2, false, sm, p, ctrl, i);
+          tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C2, b, ctrl, i);
+          cholqr_lane(cx, Qi, f.ldq, m, sm.C2, b, sm.R2, sm.R, true, sm, p, ctrl, i);
+        } else {
+          // wider blocks: the Gram matrix and its factor once, in one workgroup
+          tn_final(cx, f.red_ws, nch, p + b, b, 0, (int64_t)p * b, sm.T, b, ctrl, i);
+          cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)(p + b) * b, (int64_t)p * b, b,
+                 nullptr, sm.R1, false, sm, p, ctrl, i);
+          tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
+          nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+          nch = tn_partials(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, ctrl, i);
+          cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)b * b, 0, b, sm.R1, sm.R2, false, sm,
+                 p, ctrl, i);
+          nch = tn_partials(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, ctrl, i);
+          cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)b * b, 0, b, sm.R2, sm.R, true, sm, p,
+                 ctrl, i);
+        }
         if (!cx.ok()) break;
       } else {
         // T = Q^T Y
