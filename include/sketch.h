@@ -142,15 +142,16 @@ sketch_status sketch_get_omega(sketch_t h, double* omega_dev, int64_t ld);
 /* Which orthonormalisation the last sketch_finalize used (host integers, either pointer may be
  * NULL).  *loop_path: 0 = Cholesky QR of each column block of the loop of Alg. 4 steps 9-15
  * (Sec. 3.2, Eqs. 7-9), 1 = Householder TSQR (taken when a block's Gram matrix is too
- * ill-conditioned for Cholesky QR, or a block is rank deficient).  *rb_path: 0 = shifted Cholesky
- * QR3 of B^T before the SVD of Alg. 4 steps 16-19, 1 = block Gram-Schmidt with TSQR.  -1 when the
- * sketch was empty.  E_STATE before finalize. */
+ * ill-conditioned for Cholesky QR, or a block is rank deficient).  *rb_path, for R_B of B^T before
+ * the SVD of Alg. 4 steps 16-19: 0 = Cholesky QR2 (B well conditioned), 2 = shifted Cholesky QR3,
+ * 1 = block Gram-Schmidt with TSQR.  -1 when the sketch was empty.  E_STATE before finalize. */
 sketch_status sketch_finalize_paths(sketch_t h, int32_t* loop_path, int32_t* rb_path);
 
-/* Test hook: with a nonzero flag the next sketch_finalize takes the Householder path directly
- * (loop_householder: TSQR for every column block; rb_householder: Gram-Schmidt + TSQR for R_B),
- * without trying Cholesky QR first.  Both paths compute the same factorisation. */
-sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_householder);
+/* Test hook for the next sketch_finalize: loop_householder nonzero takes TSQR for every column
+ * block without trying Cholesky QR; rb_mode 1 takes Gram-Schmidt + TSQR for R_B, 2 shifted Cholesky
+ * QR3 directly, 0 the normal order.  All paths compute the same factorisation.  E_INVAL for another
+ * rb_mode. */
+sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_mode);
 
 /* Copies the pass state as FP64 into device memory: G (rows x l, row-major, ld = l) and
  * H (n x l, row-major, ld = l); either pointer may be NULL.  *rows_out = rows ingested. */

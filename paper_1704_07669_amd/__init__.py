@@ -188,8 +188,8 @@ def sketch_finalize_paths(h):
     return a.value, b.value
 
 
-def sketch_debug_force_paths(h, loop_householder, rb_householder):
-    _check(load_library().sketch_debug_force_paths(h, int(loop_householder), int(rb_householder)))
+def sketch_debug_force_paths(h, loop_householder, rb_mode):
+    _check(load_library().sketch_debug_force_paths(h, int(loop_householder), int(rb_mode)))
 
 
 def sketch_get_omega(h, out):
@@ -282,8 +282,8 @@ class Sketch:
     def finalize_paths(self):
         return sketch_finalize_paths(self.h)
 
-    def force_paths(self, loop_householder, rb_householder):
-        sketch_debug_force_paths(self.h, loop_householder, rb_householder)
+    def force_paths(self, loop_householder, rb_mode):
+        sketch_debug_force_paths(self.h, loop_householder, rb_mode)
 
     def rows_capacity_used(self):
         import torch

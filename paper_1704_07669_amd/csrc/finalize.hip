@@ -946,6 +946,8 @@ size_t chol_lds_bytes(int L) { return ((size_t)L * (L + 1) + 2 * (size_t)L) * si
 // with a positive diagonal; s = shift_rel tr(Gm) when shift_rel > 0, else 0.  Writes R and, when
 // Rinv is non-null, R^-1 (row-major, leading dimension ldr, zeros below the diagonal).  A pivot that
 // is not positive and finite sets *fail (left as it was otherwise) and the outputs are unspecified.
+// Conditioning tests, each setting *ill: ill_rel > 0, a pivot below ill_rel times the diagonal
+// entry of Gm it started from; dev_rel > 0, an entry of R farther than dev_rel from the identity.
 // One workgroup, threads in a 32 x 32 grid, each owning rows ty + 32 m and columns tx + 32 n of the
 // trailing block.  Right-looking factorisation in LDS, one row of R per step (rank-1 update of the
 // trailing upper triangle); then R^-1 by right-looking back substitution on the identity, one row
@@ -955,7 +957,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
                                                        int L, double shift_rel,
                                                        double* __restrict__ R,
                                                        double* __restrict__ Rinv, int ldr,
-                                                       int* __restrict__ fail) {
+                                                       int* __restrict__ fail, double ill_rel,
+                                                       double dev_rel, int* __restrict__ ill) {
   extern __shared__ double a[];     // L x (L + 1), then rd[L] (diag of R), dinv[L] (its inverse)
   const int LS = L + 1, tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
   double* rd = a + (int64_t)L * LS;
@@ -980,8 +983,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     for (int i = tid; i < L; i += kCholThreads) a[i * LS + i] += sh;
     __syncthreads();
   }
+  // the diagonal of G, for the conditioning test (dinv is filled only after the factorisation)
+  for (int i = tid; i < L; i += kCholThreads) dinv[i] = a[i * LS + i];
+  __syncthreads();
   for (int j = 0; j < L; ++j) {
     const double d = a[j * LS + j];            // same value in every thread: uniform exit
+    if (tid == 0 && ill_rel > 0.0 && !(d >= ill_rel * dinv[j])) *ill = 1;
     if (!(d > 0.0) || !(d < INFINITY)) {
       if (tid == 0) *fail = 1;
       return;
@@ -1052,11 +1059,15 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
       __syncthreads();
     }
   }
+  bool dev = false;
   for (int idx = tid; idx < L * L; idx += kCholThreads) {
     const int i = idx / L, c = idx % L;
-    R[(int64_t)i * ldr + c] = c > i ? a[i * LS + c] : (c == i ? rd[i] : 0.0);
+    const double v = c > i ? a[i * LS + c] : (c == i ? rd[i] : 0.0);
+    R[(int64_t)i * ldr + c] = v;
+    dev |= dev_rel > 0.0 && !(fabs(v - (c == i ? 1.0 : 0.0)) <= dev_rel);
     if (Rinv != nullptr) Rinv[(int64_t)i * ldr + c] = c > i ? a[c * LS + i] : (c == i ? dinv[i] : 0.0);
   }
+  if (dev) *ill = 1;                             // every writer stores the same value
 }
 
 // out = X Y for upper triangular L x L X and Y (row-major, leading dimension L); out must not
@@ -1624,17 +1635,54 @@ void right_trmul(Ctx& cx, double* Y, int64_t ldy, const double* X, int64_t ldx, 
   }
 }
 
-void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double* Rinv, int* fail) {
+void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double* Rinv, int* fail,
+          double ill_rel = 0.0, double dev_rel = 0.0, int* ill = nullptr) {
   if (!cx.ok()) return;
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), chol_lds_bytes(L), cx.s, Gm, L, L,
-                     shift_rel, R, Rinv, L, fail);
+                     shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill);
   cx.chk();
 }
 
-// R_B of B^T = Q_B R_B by shifted Cholesky QR3 (see k_chol).  Returns the device matrix holding R_B
-// (row-major L x L), or nullptr when a pivot failed (then the caller factors B^T another way).
-// Q1 goes to the Q_B storage and Q2 to the H storage (H is no longer needed at this point).
-const double* chol_qr3(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
+// R_B of B^T = Q_B R_B by Cholesky QR: two unshifted passes when B is well enough conditioned for
+// them (tested on the device, read back with the one wait this needs), else shifted Cholesky QR3
+// (see k_chol).  Returns the device matrix holding R_B (row-major L x L), or nullptr when a pivot
+// failed (then the caller factors B^T another way).  Q1 goes to the Q_B storage and Q2 to the H
+// storage (H is no longer needed at this point).
+const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L);
+
+const double* chol_qr(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
+  const int64_t n = f.n;
+  double* Gm = sm.Jm;
+  double* Rs = sm.Wm;
+  double* Ri = sm.Jk;
+  double* Racc = sm.Wk;
+  double* Q2 = const_cast<double*>(f.H);
+  int* fail = sm.info + 1;
+  int* ill = sm.info + 2;
+  int hflags[2] = {1, 1};
+  // Cholesky QR2 without a shift first: accurate when no pivot of B B^T falls below 1e-8 of its
+  // diagonal entry (cond(B) up to about 1e4) and the second factor is within 1e-6 of I (Q1 was
+  // orthonormal to about 1e-6, so Q2 is to working precision)
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, fail, 0);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, ill, 0);
+  cx.chk();
+  gram_upper(cx, f.Bt, f.ldb, n, L, f.red_ws, Gm);
+  chol(cx, Gm, L, 0.0, Racc, Ri, fail, 1e-8, 0.0, ill);
+  right_trmul(cx, f.Qb, f.ldb, f.Bt, f.ldb, n, L, Ri);
+  gram_upper(cx, f.Qb, f.ldb, n, L, f.red_ws, Gm);
+  chol(cx, Gm, L, 0.0, Rs, nullptr, fail, 0.0, 1e-6, ill);
+  if (!cx.ok()) return nullptr;
+  hipLaunchKernelGGL(k_trmm_upper, dim3(L), dim3(JMAX), 0, cx.s, Rs, Racc, sm.RB, L);
+  cx.chk();
+  if (cx.ok()) cx.err = hipMemcpyAsync(hflags, fail, 2 * sizeof(int), hipMemcpyDeviceToHost, cx.s);
+  if (cx.ok()) cx.err = hipStreamSynchronize(cx.s);
+  if (!cx.ok()) return nullptr;
+  if (hflags[0] == 0 && hflags[1] == 0) return sm.RB;
+  return chol_qr3_shifted(cx, f, sm, L);
+}
+
+// Shifted Cholesky QR3 of B^T (see k_chol); R_B as chol_qr, or nullptr when a pivot failed.
+const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
   const int64_t n = f.n;
   double* Gm = sm.Jm;
   double* Rs = sm.Wm;
@@ -1644,6 +1692,7 @@ const double* chol_qr3(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
   int* fail = sm.info + 1;
   const double u = 1.1102230246251565e-16;     // 2^-53
   const double shift_rel = 11.0 * ((double)n * L + (double)L * (L + 1)) * u;
+  // shifted Cholesky QR3
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, fail, 0);
   cx.chk();
   // pass 1: B^T = Q1 R1 (shifted)
@@ -1826,9 +1875,11 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
 
   if (L > 0) {
     // ---------------- R_B: shifted Cholesky QR3 of B^T; Gram-Schmidt + TSQR if a pivot fails
-    const double* RBp = f.force_rb ? nullptr : chol_qr3(cx, f, sm, L);
+    const double* RBp = f.force_rb == 1 ? nullptr
+                        : f.force_rb == 2 ? chol_qr3_shifted(cx, f, sm, L)
+                                          : chol_qr(cx, f, sm, L);
     if (!cx.ok()) return cx.err;
-    f.path_rb = (RBp == nullptr) ? 1 : 0;
+    f.path_rb = (RBp == nullptr) ? 1 : (RBp == sm.RB ? 0 : 2);
     if (RBp == nullptr) {
       RBp = sm.RB;
       cx.err = launch_fill_f64(sm.RB, (int64_t)L * L, 0.0, stream);

@@ -533,8 +533,9 @@ sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t 
 
 sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_householder) {
   if (sketch_status st = check_handle(h)) return st;
+  if (rb_householder < 0 || rb_householder > 2) return fail(SKETCH_E_INVAL, "rb mode must be 0, 1 or 2");
   h->force_loop = loop_householder ? 1 : 0;
-  h->force_rb = rb_householder ? 1 : 0;
+  h->force_rb = rb_householder;
   return SKETCH_OK;
 }
 

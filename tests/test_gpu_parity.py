@@ -132,10 +132,11 @@ def test_rank_guard(gpu_lib, rank):
     assert oracle.sin_theta_max(V[:, :kk], out["V"][:, :kk]) < 1e-8
 
 
-@pytest.mark.parametrize("force", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("force", [(0, 0), (1, 0), (0, 1), (0, 2), (1, 1)])
 def test_finalize_paths_agree(gpu_lib, ragged, force):
-    """Cholesky QR and the Householder fallback (forced through the test hook) both match the
-    reference on the same sketch; without forcing, a well-conditioned sketch takes Cholesky QR."""
+    """Cholesky QR, shifted Cholesky QR3 for R_B and the Householder fallbacks (forced through the
+    test hook) all match the reference on the same sketch; without forcing, a well-conditioned
+    sketch takes Cholesky QR (QR2 for R_B)."""
     A, Om, blocks, k, b = ragged["A"], ragged["Om"], ragged["blocks"], ragged["k"], ragged["b"]
     out = run_gpu(A, Om, k, b, "f64", blocks, src="f64", keep_state=False, force=force)
     ref = oracle.single_pass_pca(split_blocks(A, blocks), Om, k, b)
