@@ -150,13 +150,26 @@ __device__ __forceinline__ void tn_fetch(const double* __restrict__ X, int64_t l
   }
 }
 
+//
+// Column slices (qtot > 0): workgroup row y = blockIdx.y takes columns y q .. of Y (qtot in all),
+// only the rows a < (y + 1) q of X (the upper triangle of a Gram matrix X = Y), and writes its
+// partials to the slice's own region part + y * gridDim.x * p * q in the same layout.
 template <int MT, int NQ>
 __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, int64_t ldx,
                                                  const double* __restrict__ Y, int64_t ldy, int p,
                                                  int q, int64_t rows, int RCH,
                                                  double* __restrict__ part,
-                                                 const Ctrl* __restrict__ ctrl, int iter) {
+                                                 const Ctrl* __restrict__ ctrl, int iter,
+                                                 int qtot = 0) {
   __shared__ double red[(TPB / 64 - 1) * MT * NQ * 4 * 64];
+  const int P = p, Q = q;                                    // layout of the partials
+  if (qtot > 0) {
+    const int y = blockIdx.y;
+    Y += (int64_t)y * q * ldy;
+    part += (int64_t)y * gridDim.x * p * q;
+    p = min(p, (y + 1) * q);
+    q = min(q, qtot - y * q);
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
   const int64_t r_begin = (int64_t)blockIdx.x * RCH;
   const int64_t r_end = min<int64_t>(rows, r_begin + RCH);
@@ -220,7 +233,7 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
           double s = acc[mt][nt][i];
           for (int w = 1; w < TPB / 64; ++w) s += red[((((w - 1) * MT + mt) * NQ + nt) * 4 + i) * 64 + lane];
           const int a = mt * 16 + acc_row<double>(g, i), c = nt * 16 + r16;
-          if (a < p && c < q) part[((int64_t)blockIdx.x * p + a) * q + c] = s;
+          if (a < p && c < q) part[((int64_t)blockIdx.x * P + a) * Q + c] = s;
         }
   }
 }
@@ -276,6 +289,32 @@ __global__ __launch_bounds__(kTnFinalThreads) void k_tn_final(const double* __re
   }
 }
 
+// The upper triangle of an L x L Gram matrix from the column-sliced chunk partials of k_tn_mfma
+// (slices of 32 columns, ny of them): out[a * ldo + 32 y + c] for a < min(L, 32 (y + 1)).
+__global__ __launch_bounds__(kTnFinalThreads) void k_tn_final_gram(const double* __restrict__ part,
+                                                                   int nchunks, int L, int ny,
+                                                                   double* __restrict__ out,
+                                                                   int ldo) {
+  constexpr int NW = kTnFinalThreads / 64;
+  __shared__ double sm[NW * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t per = (int64_t)L * 32;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = i < per * ny;
+  const int64_t ic = live ? i : 0;
+  const int y = (int)(ic / per);
+  const int64_t rem = ic - y * per;
+  const double s = chunk_sum<NW>(part + (int64_t)y * nchunks * per, nchunks, per, rem, wave);
+  sm[wave * 64 + lane] = s;
+  __syncthreads();
+  if (wave == 0 && live) {
+    double t = sm[lane];
+    for (int w = 1; w < NW; ++w) t += sm[w * 64 + lane];
+    const int a = (int)(rem / 32), c = 32 * y + (int)(rem % 32);
+    if (a < min(L, 32 * (y + 1)) && c < L) out[a * ldo + c] = t;
+  }
+}
+
 // out[c][r] = base[c][r] + alpha * sum_a X[a][r] W[a][c]  (W row-major p x q, ldw); base may be
 // null (taken as 0) and may alias out.  A workgroup owns 64 rows; its four waves take interleaved
 // ranges of a, and their partial sums are added in wave order through LDS.  W is staged in LDS
@@ -292,7 +331,17 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
                                                    int p, const double* __restrict__ W, int ldw,
                                                    int q, int64_t rows, double alpha,
                                                    const Ctrl* __restrict__ ctrl, int iter,
-                                                   const double* __restrict__ Rs = nullptr) {
+                                                   const double* __restrict__ Rs = nullptr,
+                                                   int qtot = 0) {
+  if (qtot > 0) {
+    // column slices: workgroup row y = blockIdx.y takes output columns y q .. (qtot in all) with
+    // the rows a < (y + 1) q of W (an upper triangular W)
+    const int y = blockIdx.y;
+    out += (int64_t)y * q * ldo;
+    W += y * q;
+    p = min(p, (y + 1) * q);
+    q = min(q, qtot - y * q);
+  }
   extern __shared__ double ws[];              // p x QMAX, then 3 x QMAX x 64 partials
   double* part = ws + p * QMAX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1409,13 +1458,13 @@ inline int tn_rows_per_chunk(int64_t rows) {
 template <int MT>
 void tn_launch(Ctx& cx, int nq, dim3 grid, const double* X, int64_t ldx, const double* Y,
                int64_t ldy, int p, int q, int64_t rows, int rch, double* part, const Ctrl* ctrl,
-               int iter) {
+               int iter, int qtot = 0) {
   if (nq == 1)
     hipLaunchKernelGGL((k_tn_mfma<MT, 1>), grid, dim3(TPB), 0, cx.s, X, ldx, Y, ldy, p, q, rows,
-                       rch, part, ctrl, iter);
+                       rch, part, ctrl, iter, qtot);
   else
     hipLaunchKernelGGL((k_tn_mfma<MT, 2>), grid, dim3(TPB), 0, cx.s, X, ldx, Y, ldy, p, q, rows,
-                       rch, part, ctrl, iter);
+                       rch, part, ctrl, iter, qtot);
 }
 
 // Chunk partials of X[:, 0:p]^T Y[:, 0:q] over `rows` rows (p <= 128, q <= 32) into `part`;
@@ -1618,21 +1667,40 @@ void cholqr_lane(Ctx& cx, double* Y, int64_t ldy, int64_t rows, const double* G,
 // column-major X, in column slices of at most 32.
 void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, double* red_ws,
                 double* Gm) {
-  for (int c0 = 0; c0 < L && cx.ok(); c0 += 32) {
-    const int w = (L - c0 < 32) ? (L - c0) : 32;
-    tn(cx, X, ldx, X + (int64_t)c0 * ldx, ldx, c0 + w, w, rows, red_ws, Gm + c0, L, nullptr, 0);
+  if (!cx.ok() || L <= 0) return;
+  const int rch = tn_rows_per_chunk(rows);
+  const int nch = (int)cdiv<int64_t>(rows, rch);
+  const int ny = cdiv(L, 32), mt = cdiv(L, 16);
+  const dim3 grid(nch, ny);
+  switch (mt) {
+    case 1: tn_launch<1>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
+    case 2: tn_launch<2>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
+    case 3: tn_launch<3>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
+    case 4: tn_launch<4>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
+    case 5: tn_launch<5>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
+    case 6: tn_launch<6>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
+    case 7: tn_launch<7>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
+    default: tn_launch<8>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
   }
+  cx.chk();
+  if (!cx.ok()) return;
+  hipLaunchKernelGGL(k_tn_final_gram, dim3((unsigned)cdiv<int64_t>((int64_t)ny * L * 32, 64)),
+                     dim3(kTnFinalThreads), 0, cx.s, red_ws, nch, L, ny, Gm, L);
+  cx.chk();
 }
 
 // Y = X R^-1 for the n x L column-major X and upper triangular R^-1 (row-major, leading dimension
 // L), in column slices of at most 32 (slice c0..c0+w-1 only needs rows 0..c0+w-1 of R^-1).
 void right_trmul(Ctx& cx, double* Y, int64_t ldy, const double* X, int64_t ldx, int64_t rows,
                  int L, const double* Rinv) {
-  for (int c0 = 0; c0 < L && cx.ok(); c0 += 32) {
-    const int w = (L - c0 < 32) ? (L - c0) : 32;
-    nn<double>(cx, Y + (int64_t)c0 * ldy, ldy, (const double*)nullptr, 0, X, ldx, c0 + w,
-               Rinv + c0, L, w, rows, 1.0, nullptr, 0);
-  }
+  if (!cx.ok() || L <= 0 || rows <= 0) return;
+  const int ny = cdiv(L, 32);
+  const size_t shm = (size_t)(L * 32 + 3 * 32 * 64) * sizeof(double);
+  const dim3 g((unsigned)cdiv<int64_t>(rows, 64), ny), blk(TPB);
+  hipLaunchKernelGGL((k_nn_update<double, 32>), g, blk, shm, cx.s, Y, ldy, (const double*)nullptr,
+                     0, X, ldx, L, Rinv, L, 32, rows, 1.0, (const Ctrl*)nullptr, 0,
+                     (const double*)nullptr, L);
+  cx.chk();
 }
 
 void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double* Rinv, int* fail,
@@ -1765,10 +1833,11 @@ size_t tsqr_workspace_elems(int64_t rows, int b) {
 
 size_t reduce_workspace_elems(int64_t rows, int p, int q) {
   (void)q;
-  // any row count up to `rows` splits into at most this many chunks (chunks hold >= 64 rows)
+  // any row count up to `rows` splits into at most this many chunks (chunks hold >= 64 rows); the
+  // p x p Gram matrices take cdiv(p, 32) column slices of 32
   const int64_t c64 = cdiv<int64_t>(rows, 64);
   const int64_t nch = c64 < kTnChunks ? c64 : kTnChunks;
-  return (size_t)(nch * p * 32) + 64;
+  return (size_t)(nch * p * 32 * cdiv(p, 32)) + 64;
 }
 
 hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
