@@ -1001,7 +1001,8 @@ size_t chol_lds_bytes(int L) { return ((size_t)L * (L + 1) + 2 * (size_t)L) * si
 // trailing block.  Right-looking factorisation in LDS, one row of R per step (rank-1 update of the
 // trailing upper triangle); then R^-1 by right-looking back substitution on the identity, one row
 // per step from the bottom, with R^-1[k][c] (k < c) kept in the strictly lower triangle at [c][k].
-// Every step loads its operands into registers before it stores, so the loads overlap.
+// Every step loads its operands into registers before it stores, so the loads overlap, and ends
+// with its only barrier (scalings are deferred or applied where the values are read).
 __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict__ Gm, int ldg,
                                                        int L, double shift_rel,
                                                        double* __restrict__ R,
@@ -1042,11 +1043,10 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
       if (tid == 0) *fail = 1;
       return;
     }
-    const double inv = 1.0 / sqrt(d);
     if (tid == 0) rd[j] = sqrt(d);
-    for (int c = j + 1 + tid; c < L; c += kCholThreads) a[j * LS + c] *= inv;
-    __syncthreads();
-    // a[i][c] -= a[j][i] a[j][c] for j < i <= c < L
+    // a[i][c] -= (a[j][i] / d) a[j][c] for j < i <= c < L, with row j left unscaled (it becomes
+    // row j of R once divided by sqrt(d) below), so a step needs one barrier
+    const double dinvj = 1.0 / d;
     double rc[kCholSlots];
 #pragma unroll
     for (int n = 0; n < kCholSlots; ++n) {
@@ -1057,7 +1057,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     for (int m = 0; m < kCholSlots; ++m) {
       const int i = j + 1 + ty + 32 * m;
       if (i < L) {
-        const double ri = a[j * LS + i];
+        const double ri = a[j * LS + i] * dinvj;
         double v[kCholSlots];
 #pragma unroll
         for (int n = 0; n < kCholSlots; ++n) {
@@ -1075,17 +1075,23 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
   }
   for (int i = tid; i < L; i += kCholThreads) dinv[i] = 1.0 / rd[i];
   __syncthreads();
+  for (int idx = tid; idx < L * L; idx += kCholThreads) {   // rows of R: row i over sqrt(d_i)
+    const int i = idx / L, c = idx % L;
+    if (c > i) a[i * LS + c] *= dinv[i];
+  }
+  __syncthreads();
   if (Rinv != nullptr) {
     // Solve R X = I from the bottom: row i of X is final once rows i+1.. have been subtracted from
-    // it; X[i][c] = rhs[i][c] / R_ii, then rhs[k][c] -= R[k][i] X[i][c] for k < i, c >= i.
+    // it; X[i][c] = rhs[i][c] / R_ii, then rhs[k][c] -= R[k][i] X[i][c] for k < i, c >= i.  The
+    // right-hand sides stay unscaled in the strictly lower triangle (rhs[i][c] at [c][i]); X[i][c]
+    // is formed where it is used, so a step needs one barrier.
     for (int i = L - 1; i >= 0; --i) {
-      for (int c = i + 1 + tid; c < L; c += kCholThreads) a[c * LS + i] *= dinv[i];
-      __syncthreads();
+      const double di = dinv[i];
       double xc[kCholSlots];
 #pragma unroll
       for (int n = 0; n < kCholSlots; ++n) {
         const int c = i + tx + 32 * n;
-        xc[n] = c < L ? (c == i ? dinv[i] : a[c * LS + i]) : 0.0;
+        xc[n] = c < L ? (c == i ? di : a[c * LS + i] * di) : 0.0;
       }
 #pragma unroll
       for (int m = 0; m < kCholSlots; ++m) {
@@ -1114,7 +1120,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     const double v = c > i ? a[i * LS + c] : (c == i ? rd[i] : 0.0);
     R[(int64_t)i * ldr + c] = v;
     dev |= dev_rel > 0.0 && !(fabs(v - (c == i ? 1.0 : 0.0)) <= dev_rel);
-    if (Rinv != nullptr) Rinv[(int64_t)i * ldr + c] = c > i ? a[c * LS + i] : (c == i ? dinv[i] : 0.0);
+    if (Rinv != nullptr)
+      Rinv[(int64_t)i * ldr + c] = c > i ? a[c * LS + i] * dinv[i] : (c == i ? dinv[i] : 0.0);
   }
   if (dev) *ill = 1;                             // every writer stores the same value
 }

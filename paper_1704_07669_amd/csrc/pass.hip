@@ -763,10 +763,12 @@ __device__ __forceinline__ GFrag<MODE> lds_gfrag(const u32x4* gl, int NTt, int t
 
 // The step loop of k_gemm2w.  Steps s of KR rows: a(s) sits in registers ab[s % DEPTH] and G(s)
 // in gr[s % DEPTH] until it is stored to LDS half s & 1 at the end of step s - 1.  a and G of step
-// s + DEPTH are issued together right after step s's matrix-core work (past the last step they
-// re-read it, unused), so every step issues the same loads and waiting for G(s + 1) leaves the
-// loads of DEPTH - 1 later steps in flight.  VEC: aligned rows, n a multiple of 4; otherwise the
-// masked element loads serve.
+// s + DEPTH are issued together (past the last step they re-read it, unused), so every step issues
+// the same loads and waiting for G(s + 1) leaves the loads of DEPTH - 1 later steps in flight.
+// Where a(s) is converted to BF16 operands, they are issued as soon as it has been, before step
+// s's matrix-core work, which then runs with DEPTH steps in flight; FP32 operands are a(s)'s own
+// registers, so there they follow the matrix-core work (issued earlier they cost registers and
+// time).  VEC: aligned rows, n a multiple of 4; otherwise the masked element loads serve.
 template <typename Src, int MODE, int NT, int DEPTH, bool VEC>
 __device__ __forceinline__ void g2w_steps(const SK_GLOBAL Src* __restrict__ A, int64_t lda,
                                           int64_t n, const SK_GLOBAL uint8_t* __restrict__ gop,
@@ -778,6 +780,7 @@ __device__ __forceinline__ void g2w_steps(const SK_GLOBAL Src* __restrict__ A, i
   constexpr int PIECES = G2W<MODE>::HALVES * NT * 64;
   constexpr int GPT = (PIECES + 255) / 256;
   const int64_t colc = VEC ? min(col, n - VC) : col;
+  constexpr bool kEarly = (MODE != M_F32);
   Src ab[DEPTH][V2][VC];
   u32x4 gr[DEPTH][GPT];
   auto load_step = [&](int s, int d) {
@@ -802,6 +805,7 @@ __device__ __forceinline__ void g2w_steps(const SK_GLOBAL Src* __restrict__ A, i
         AFrag2<MODE> af[VC];
 #pragma unroll
         for (int j = 0; j < VC; ++j) af[j] = make_a2<MODE, Src, V2, VC>(ab[d], j);
+        if constexpr (kEarly) load_step(s + DEPTH, d);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const GFrag<MODE> gq = lds_gfrag<MODE>(gb, NT, t, g, r16);
@@ -809,7 +813,7 @@ __device__ __forceinline__ void g2w_steps(const SK_GLOBAL Src* __restrict__ A, i
           for (int j = 0; j < VC; ++j) acc[t][j] = mma2(gq, af[j], acc[t][j]);
         }
       }
-      load_step(s + DEPTH, d);
+      if (!kEarly || s >= nsteps) load_step(s + DEPTH, d);
       if (s + 1 < nsteps)
         store_gstep<MODE, NT, GPT>(gl + ((s + 1) & 1) * PIECES, gr[(d + 1) % DEPTH], tid,
                                    row_lo + (s + 1) * KR, row_hi);
@@ -896,12 +900,13 @@ __global__ __launch_bounds__(256) void k_gemm2w(const PassItem one,
 }
 
 // H += scale * (sum over row splits, in split order, of the FP32 partials), in FP64.  One thread
-// per 4 consecutive columns of one sketch row of one strip.
+// per 4 consecutive columns of one sketch row of one strip.  The H loads and the partial loads of
+// up to four splits are issued together, so a thread waits for memory once per four splits.
 __global__ __launch_bounds__(256) void k_hsum(const PassItem one, const PassItem* __restrict__ grp,
                                               int count, int LP) {
   const PassItem it = item_of(one, grp, count, blockIdx.x, &PassItem::wgh);
   if (it.rsplit <= 1) return;
-  constexpr int SW = 256;
+  constexpr int SW = 256, U = 4;
   const int64_t q = (int64_t)(blockIdx.x - it.wgh) * 256 + threadIdx.x;   // group of 4 columns
   const int64_t per_strip = (int64_t)LP * (SW / 4);
   if (q >= per_strip * it.strips) return;
@@ -912,22 +917,42 @@ __global__ __launch_bounds__(256) void k_hsum(const PassItem one, const PassItem
   const int64_t col = strip * SW + cc;
   if (col >= it.n) return;
   const int64_t pstride = (int64_t)LP * SW;
+  const int rsplit = it.rsplit;
   const SK_GLOBAL float* base = gptr(reinterpret_cast<const float*>(it.P2)) +
-                                strip * it.rsplit * pstride + (int64_t)lidx * SW + cc;
-  double sm[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int r = 0; r < it.rsplit; ++r) {
-    const f32x4 v = *reinterpret_cast<const SK_GLOBAL f32x4*>(base + r * pstride);
+                                strip * rsplit * pstride + (int64_t)lidx * SW + cc;
+  SK_GLOBAL double* h = gptr(it.H) + (int64_t)lidx * it.ldh + col;
+  const bool full = (col + 4 <= it.n) && ((reinterpret_cast<uintptr_t>(h) & 15) == 0);
+  double hv[4];
+  if (full) {
+    const SK_GLOBAL f64x2* h2 = reinterpret_cast<const SK_GLOBAL f64x2*>(h);
+    const f64x2 x0 = h2[0], x1 = h2[1];
+    hv[0] = x0[0]; hv[1] = x0[1]; hv[2] = x1[0]; hv[3] = x1[1];
+  } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) sm[j] += (double)v[j];
+    for (int j = 0; j < 4; ++j) hv[j] = (col + j < it.n) ? h[j] : 0.0;
+  }
+  double sm[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 0; r0 < rsplit; r0 += U) {
+    f32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)   // clamped: splits past the last re-read it and are not added
+      v[u] = *reinterpret_cast<const SK_GLOBAL f32x4*>(base + min(r0 + u, rsplit - 1) * pstride);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (r0 + u < rsplit)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sm[j] += (double)v[u][j];
   }
   const double scale = it.fp8_exp ? ldexp(1.0, -(*gptr(it.fp8_exp))) : 1.0;
-  SK_GLOBAL double* h = gptr(it.H) + (int64_t)lidx * it.ldh + col;
-  double hv[4];
+  if (full) {
+    SK_GLOBAL f64x2* h2 = reinterpret_cast<SK_GLOBAL f64x2*>(h);
+    h2[0] = f64x2{hv[0] + scale * sm[0], hv[1] + scale * sm[1]};
+    h2[1] = f64x2{hv[2] + scale * sm[2], hv[3] + scale * sm[3]};
+  } else {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) hv[j] = (col + j < it.n) ? h[j] : 0.0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (col + j < it.n) h[j] = hv[j] + scale * sm[j];
+    for (int j = 0; j < 4; ++j)
+      if (col + j < it.n) h[j] = hv[j] + scale * sm[j];
+  }
 }
 
 // ---------------------------------------------------------------- FP8 block quantisation
