@@ -194,10 +194,11 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
                        xa1, yb1);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
+      if (mt * 16 < p)                            // uniform: tiles past p only in a slice
 #pragma unroll
-      for (int nt = 0; nt < NQ; ++nt)
+        for (int nt = 0; nt < NQ; ++nt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[mt][nt] = mma_f64(xa0[mt][j], yb0[nt][j], acc[mt][nt]);
+          for (int j = 0; j < 4; ++j) acc[mt][nt] = mma_f64(xa0[mt][j], yb0[nt][j], acc[mt][nt]);
     mfma_drain();
     if (r2 < r_end)
       tn_fetch<MT, NQ>(X, ldx, Y, ldy, p, q, r2 + 4 * g, r_end, r16, aligned && r2 + 16 <= r_end,
@@ -205,10 +206,12 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
     if (r1 < r_end) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
+        if (mt * 16 < p)
 #pragma unroll
-        for (int nt = 0; nt < NQ; ++nt)
+          for (int nt = 0; nt < NQ; ++nt)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[mt][nt] = mma_f64(xa1[mt][j], yb1[nt][j], acc[mt][nt]);
+            for (int j = 0; j < 4; ++j)
+              acc[mt][nt] = mma_f64(xa1[mt][j], yb1[nt][j], acc[mt][nt]);
       mfma_drain();
     }
   }
@@ -316,23 +319,30 @@ __global__ __launch_bounds__(kTnFinalThreads) void k_tn_final_gram(const double*
 }
 
 // out[c][r] = base[c][r] + alpha * sum_a X[a][r] W[a][c]  (W row-major p x q, ldw); base may be
-// null (taken as 0) and may alias out.  A workgroup owns 64 rows; its four waves take interleaved
-// ranges of a, and their partial sums are added in wave order through LDS.  W is staged in LDS
-// zero-padded to QMAX columns, so the inner loop has no per-column conditions.
+// null (taken as 0) and may alias out.  One lane per row, kNnThreads rows per workgroup.  W is
+// staged in LDS, zero-padded to QMAX >= q columns and to whole chunks of rows; each lane reads its
+// row of X in chunks of kNnChunk entries, all loads of a chunk in flight together, and accumulates
+// the QMAX columns in registers (rows a >= p of a chunk read X's last row and count as zero).  The
+// first chunk and the base entries are fetched before the iteration check and the staging stores,
+// so their latencies overlap.
 //
 // With Rs non-null (q x q upper triangular, row-major, leading dimension q) each row v of the
 // result is replaced by the solution x of x Rs = v (forward substitution) before it is written, and
 // only the first `keep` entries are solved (keep = ctrl->keep_last on the iteration the rank guard
 // stopped at, q otherwise); the others are written as zero.
+constexpr int kNnChunk = 32;
+constexpr int kNnThreads = 128;
+
 template <typename BT, int QMAX>
-__global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int64_t ldo,
-                                                   const BT* base, int64_t ldb,
-                                                   const double* __restrict__ X, int64_t ldx,
-                                                   int p, const double* __restrict__ W, int ldw,
-                                                   int q, int64_t rows, double alpha,
-                                                   const Ctrl* __restrict__ ctrl, int iter,
-                                                   const double* __restrict__ Rs = nullptr,
-                                                   int qtot = 0) {
+__global__ __launch_bounds__(kNnThreads) void k_nn_update(double* __restrict__ out, int64_t ldo,
+                                                          const BT* base, int64_t ldb,
+                                                          const double* __restrict__ X,
+                                                          int64_t ldx, int p,
+                                                          const double* __restrict__ W, int ldw,
+                                                          int q, int64_t rows, double alpha,
+                                                          const Ctrl* __restrict__ ctrl, int iter,
+                                                          const double* __restrict__ Rs = nullptr,
+                                                          int qtot = 0) {
   if (qtot > 0) {
     // column slices: workgroup row y = blockIdx.y takes output columns y q .. (qtot in all) with
     // the rows a < (y + 1) q of W (an upper triangular W)
@@ -342,88 +352,74 @@ __global__ __launch_bounds__(TPB) void k_nn_update(double* __restrict__ out, int
     p = min(p, (y + 1) * q);
     q = min(q, qtot - y * q);
   }
-  extern __shared__ double ws[];              // p x QMAX, then 3 x QMAX x 64 partials
-  double* part = ws + p * QMAX;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int SMAX = JMAX / 4;
-  double x[SMAX];
-  {
-    // all loads first (clamped to W[0], which always exists), then the LDS stores
-    constexpr int FILL = (JMAX * QMAX + TPB - 1) / TPB;
-    const int np = p * QMAX;
-    double wv[FILL];
+  constexpr int CH = kNnChunk;
+  constexpr int FILL = (JMAX * QMAX + kNnThreads - 1) / kNnThreads;
+  __shared__ double ws[JMAX * QMAX];           // W, rows rounded up to whole chunks
+  const int tid = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * kNnThreads + tid;
+  const int64_t rc = r < rows ? r : rows - 1;
+  const int qc = q - 1, plast = p > 0 ? p - 1 : 0;
+  const int nw = ((p + CH - 1) / CH) * CH * QMAX;   // staged entries
+  double x[CH];
+  auto load_chunk = [&](int a0) {
 #pragma unroll
-    for (int u = 0; u < FILL; ++u) {
-      const int idx = threadIdx.x + u * TPB, a = idx / QMAX, c = idx % QMAX;
-      const bool in = idx < np && c < q;
-      const double v = W[in ? a * ldw + c : 0];
-      wv[u] = in ? v : 0.0;
-    }
-    // every X value this lane needs (a = wave + 4 s < p), fetched in the same batch with clamped
-    // addresses, then the iteration check, whose latency overlaps the loads
-    const int64_t r = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t rc = r < rows ? r : 0;
-    const int plast = p > 0 ? p - 1 : 0;
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      const int a = wave + 4 * s;
+    for (int s = 0; s < CH; ++s) {
+      const int a = a0 + s;
       const double v = X[(int64_t)(a < p ? a : plast) * ldx + rc];
       x[s] = a < p ? v : 0.0;
     }
-    if (skip_iter(ctrl, iter)) return;
+  };
+  // all loads first (W clamped to W[0], which always exists), then the check and the LDS stores
+  double wv[FILL];
 #pragma unroll
-    for (int u = 0; u < FILL; ++u) {
-      const int idx = threadIdx.x + u * TPB;
-      if (idx < np) ws[idx] = wv[u];
-    }
+  for (int u = 0; u < FILL; ++u) {
+    const int idx = tid + u * kNnThreads, a = idx / QMAX, c = idx % QMAX;
+    const bool in = a < p && c < q;
+    const double v = W[in ? a * ldw + c : 0];
+    wv[u] = in ? v : 0.0;
+  }
+  if (p > 0) load_chunk(0);
+  double bv[QMAX];
+#pragma unroll
+  for (int c = 0; c < QMAX; ++c)
+    bv[c] = base ? (double)base[(int64_t)(c < q ? c : qc) * ldb + rc] : 0.0;
+  if (skip_iter(ctrl, iter)) return;
+#pragma unroll
+  for (int u = 0; u < FILL; ++u) {
+    const int idx = tid + u * kNnThreads;
+    if (idx < nw) ws[idx] = wv[u];
   }
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
-  const bool live = r < rows;
   double acc[QMAX];
 #pragma unroll
   for (int c = 0; c < QMAX; ++c) acc[c] = 0.0;
+  for (int a0 = 0; a0 < p; a0 += CH) {
+    if (a0 > 0) load_chunk(a0);
+    const double* w = ws + a0 * QMAX;
 #pragma unroll
-  for (int s = 0; s < SMAX; ++s) {
-    const int a = wave + 4 * s;                 // uniform over the wave
-    if (a < p) {
+    for (int s = 0; s < CH; ++s)
 #pragma unroll
-      for (int c = 0; c < QMAX; ++c) acc[c] = fma(x[s], ws[a * QMAX + c], acc[c]);
-    }
+      for (int c = 0; c < QMAX; ++c) acc[c] = fma(x[s], w[s * QMAX + c], acc[c]);
   }
-  if (wave > 0) {
+  if (r >= rows) return;
+  if (Rs == nullptr) {
 #pragma unroll
-    for (int c = 0; c < QMAX; ++c) part[((wave - 1) * QMAX + c) * 64 + lane] = acc[c];
-  }
-  __syncthreads();
-  if (wave == 0 && live) {
-    if (Rs == nullptr) {
+    for (int c = 0; c < QMAX; ++c)
+      if (c < q) out[c * ldo + r] = bv[c] + alpha * acc[c];
+  } else {
+    const int keep = (ctrl != nullptr && iter == ctrl->last_iter) ? ctrl->keep_last : q;
+    double xs[QMAX];
 #pragma unroll
-      for (int c = 0; c < QMAX; ++c) {
-        if (c < q) {
-          double sum = acc[c];
-          for (int w = 1; w < TPB / 64; ++w) sum += part[((w - 1) * QMAX + c) * 64 + lane];
-          const double bv = base ? (double)base[c * ldb + r] : 0.0;
-          out[c * ldo + r] = bv + alpha * sum;
-        }
+    for (int c = 0; c < QMAX; ++c) {
+      double v = 0.0;
+      if (c < q) {
+        v = bv[c] + alpha * acc[c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) v = fma(-xs[k], Rs[k * q + c], v);
+        v = (c < keep) ? v / Rs[c * q + c] : 0.0;
       }
-    } else {
-      const int keep = (ctrl != nullptr && iter == ctrl->last_iter) ? ctrl->keep_last : q;
-      double x[QMAX];
-#pragma unroll
-      for (int c = 0; c < QMAX; ++c) {
-        double v = 0.0;
-        if (c < q) {
-          double sum = acc[c];
-          for (int w = 1; w < TPB / 64; ++w) sum += part[((w - 1) * QMAX + c) * 64 + lane];
-          v = (base ? (double)base[c * ldb + r] : 0.0) + alpha * sum;
-#pragma unroll
-          for (int k = 0; k < c; ++k) v = fma(-x[k], Rs[k * q + c], v);
-          v = (c < keep) ? v / Rs[c * q + c] : 0.0;
-        }
-        x[c] = v;
-        if (c < q) out[c * ldo + r] = v;
-      }
+      xs[c] = v;
+      if (c < q) out[c * ldo + r] = v;
     }
   }
 }
@@ -1457,6 +1453,8 @@ struct Ctx {
 // Row reductions: chunks of a multiple of 16 rows, at most kTnChunks of them (enough workgroups
 // to fill the chip; the partials stay small next to the rows read).
 constexpr int kTnChunks = 512;
+constexpr int kGramWgs = 256;   // workgroups of one l x l Gram matrix launch
+
 inline int tn_rows_per_chunk(int64_t rows) {
   const int64_t r = rup<int64_t>(cdiv<int64_t>(rows, kTnChunks), 16);
   return (int)(r < 64 ? 64 : r);
@@ -1518,18 +1516,16 @@ void nn(Ctx& cx, double* out, int64_t ldo, const BT* base, int64_t ldb, const do
         int64_t ldx, int p, const double* W, int ldw, int q, int64_t rows, double alpha,
         const Ctrl* ctrl, int iter, const double* Rs = nullptr) {
   if (!cx.ok() || q == 0 || rows == 0) return;
-  const int qmax = q <= 8 ? 8 : (q <= 16 ? 16 : 32);
-  const size_t shm = (size_t)(p * qmax + 3 * qmax * 64) * sizeof(double);
-  const dim3 g((unsigned)cdiv<int64_t>(rows, 64)), blk(TPB);
-  if (q <= 8)
-    hipLaunchKernelGGL((k_nn_update<BT, 8>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p, W,
-                       ldw, q, rows, alpha, ctrl, iter, Rs);
-  else if (q <= 16)
-    hipLaunchKernelGGL((k_nn_update<BT, 16>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p,
-                       W, ldw, q, rows, alpha, ctrl, iter, Rs);
-  else
-    hipLaunchKernelGGL((k_nn_update<BT, 32>), g, blk, shm, cx.s, out, ldo, base, ldb, X, ldx, p,
-                       W, ldw, q, rows, alpha, ctrl, iter, Rs);
+  const dim3 g((unsigned)cdiv<int64_t>(rows, kNnThreads)), blk(kNnThreads);
+#define SK_NN_LAUNCH(QM)                                                                        \
+  hipLaunchKernelGGL((k_nn_update<BT, QM>), g, blk, 0, cx.s, out, ldo, base, ldb, X, ldx, p, W, \
+                     ldw, q, rows, alpha, ctrl, iter, Rs, 0)
+  if (q <= 8) SK_NN_LAUNCH(8);
+  else if (q <= 10) SK_NN_LAUNCH(10);
+  else if (q <= 12) SK_NN_LAUNCH(12);
+  else if (q <= 16) SK_NN_LAUNCH(16);
+  else SK_NN_LAUNCH(32);
+#undef SK_NN_LAUNCH
   cx.chk();
 }
 
@@ -1675,9 +1671,14 @@ void cholqr_lane(Ctx& cx, double* Y, int64_t ldy, int64_t rows, const double* G,
 void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, double* red_ws,
                 double* Gm) {
   if (!cx.ok() || L <= 0) return;
-  const int rch = tn_rows_per_chunk(rows);
-  const int nch = (int)cdiv<int64_t>(rows, rch);
+  // about one workgroup per CU over all slices: a workgroup's share of the matrix-core work then
+  // outweighs its partial sums and their reduction, and the partials stay small
   const int ny = cdiv(L, 32), mt = cdiv(L, 16);
+  const int64_t want = std::max<int64_t>(1, kGramWgs / ny);
+  // (chunks of at least 64 rows and at most kTnChunks of them, as the workspace is sized for)
+  const int rch = (int)std::max<int64_t>(
+      tn_rows_per_chunk(rows), rup<int64_t>(cdiv<int64_t>(rows, want), 16));
+  const int nch = (int)cdiv<int64_t>(rows, rch);
   const dim3 grid(nch, ny);
   switch (mt) {
     case 1: tn_launch<1>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
@@ -1702,9 +1703,8 @@ void right_trmul(Ctx& cx, double* Y, int64_t ldy, const double* X, int64_t ldx, 
                  int L, const double* Rinv) {
   if (!cx.ok() || L <= 0 || rows <= 0) return;
   const int ny = cdiv(L, 32);
-  const size_t shm = (size_t)(L * 32 + 3 * 32 * 64) * sizeof(double);
-  const dim3 g((unsigned)cdiv<int64_t>(rows, 64), ny), blk(TPB);
-  hipLaunchKernelGGL((k_nn_update<double, 32>), g, blk, shm, cx.s, Y, ldy, (const double*)nullptr,
+  const dim3 g((unsigned)cdiv<int64_t>(rows, kNnThreads), ny), blk(kNnThreads);
+  hipLaunchKernelGGL((k_nn_update<double, 32>), g, blk, 0, cx.s, Y, ldy, (const double*)nullptr,
                      0, X, ldx, L, Rinv, L, 32, rows, 1.0, (const Ctrl*)nullptr, 0,
                      (const double*)nullptr, L);
   cx.chk();
@@ -1806,14 +1806,6 @@ hipError_t finalize_prepare() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)chol_lds_bytes(JMAX));
-  // W (p x 32, p <= JMAX) plus the partial sums exceed 64 KB for the widest products
-  const int nn32 = (int)((JMAX * 32 + 3 * 32 * 64) * sizeof(double));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_nn_update<double, 32>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, nn32);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_nn_update<float, 32>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, nn32);
   return e;
 }
 
