@@ -110,6 +110,12 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
   return (dpp::lane(v, 0) + dpp::lane(v, 16)) + (dpp::lane(v, 32) + dpp::lane(v, 48));
 }
 
+// Workgroup barrier that waits only for the wave's LDS operations: global loads issued for later
+// steps stay in flight across it (a plain __syncthreads also waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Pointers the compiler must treat as global memory.  Pointers read from a descriptor in memory
 // are generic, which makes every access a FLAT instruction; FLAT loads also count against the LDS
 // wait counter, so each LDS wait would drain all outstanding global prefetches.

@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kTnFinalThreads) void k_tn_final_gram(const double*
 // row of X in chunks of kNnChunk entries, all loads of a chunk in flight together, and accumulates
 // the QMAX columns in registers (rows a >= p of a chunk read X's last row and count as zero).  The
 // first chunk and the base entries are fetched before the iteration check and the staging stores,
-// so their latencies overlap.
+// so their latencies overlap; Rs, the same for every lane, is staged in LDS with W.
 //
 // With Rs non-null (q x q upper triangular, row-major, leading dimension q) each row v of the
 // result is replaced by the solution x of x Rs = v (forward substitution) before it is written, and
@@ -354,7 +354,9 @@ __global__ __launch_bounds__(kNnThreads) void k_nn_update(double* __restrict__ o
   }
   constexpr int CH = kNnChunk;
   constexpr int FILL = (JMAX * QMAX + kNnThreads - 1) / kNnThreads;
+  constexpr int RFILL = (QMAX * QMAX + kNnThreads - 1) / kNnThreads;
   __shared__ double ws[JMAX * QMAX];           // W, rows rounded up to whole chunks
+  __shared__ double rsh[QMAX * QMAX];          // Rs (zero-padded), when given
   const int tid = threadIdx.x;
   const int64_t r = (int64_t)blockIdx.x * kNnThreads + tid;
   const int64_t rc = r < rows ? r : rows - 1;
@@ -378,6 +380,15 @@ __global__ __launch_bounds__(kNnThreads) void k_nn_update(double* __restrict__ o
     const double v = W[in ? a * ldw + c : 0];
     wv[u] = in ? v : 0.0;
   }
+  double rv[RFILL];
+  if (Rs != nullptr) {
+#pragma unroll
+    for (int u = 0; u < RFILL; ++u) {
+      const int idx = tid + u * kNnThreads, a = idx / QMAX, c = idx % QMAX;
+      const double v = Rs[min(a, qc) * q + min(c, qc)];
+      rv[u] = (a < q && c < q) ? v : 0.0;
+    }
+  }
   if (p > 0) load_chunk(0);
   double bv[QMAX];
 #pragma unroll
@@ -388,6 +399,13 @@ __global__ __launch_bounds__(kNnThreads) void k_nn_update(double* __restrict__ o
   for (int u = 0; u < FILL; ++u) {
     const int idx = tid + u * kNnThreads;
     if (idx < nw) ws[idx] = wv[u];
+  }
+  if (Rs != nullptr) {
+#pragma unroll
+    for (int u = 0; u < RFILL; ++u) {
+      const int idx = tid + u * kNnThreads;
+      if (idx < QMAX * QMAX) rsh[idx] = rv[u];
+    }
   }
   __syncthreads();
   double acc[QMAX];
@@ -415,8 +433,8 @@ __global__ __launch_bounds__(kNnThreads) void k_nn_update(double* __restrict__ o
       if (c < q) {
         v = bv[c] + alpha * acc[c];
 #pragma unroll
-        for (int k = 0; k < c; ++k) v = fma(-xs[k], Rs[k * q + c], v);
-        v = (c < keep) ? v / Rs[c * q + c] : 0.0;
+        for (int k = 0; k < c; ++k) v = fma(-xs[k], rsh[k * QMAX + c], v);
+        v = (c < keep) ? v / rsh[c * QMAX + c] : 0.0;
       }
       xs[c] = v;
       if (c < q) out[c * ldo + r] = v;
@@ -806,24 +824,34 @@ __global__ __launch_bounds__(kLaneCholThreads) void k_cholqr_lane(
   const int tid = threadIdx.x;
   const int64_t r = (int64_t)blockIdx.x * kLaneCholThreads + tid;
   const int64_t rc = r < rows ? r : 0;
+  __shared__ double gsh[B * B + B];   // G identity-padded to B x B, then the Rprev diagonal
   double y[B], R[NU], gd[B], pd[B];
+  // the Gram matrix is the same for every lane: one entry per thread into LDS (issued before the
+  // row loads, so waiting for it leaves them in flight), then read back by every lane
+  // (every thread loads at a clamped address, without branches, so the row loads follow at once)
+  const int bl = b - 1;
+  const int gi = min(tid / B, B - 1), gc = tid % B, gj = min(max(tid - B * B, 0), B - 1);
+  const double* rpd = (Rprev != nullptr) ? Rprev : G;
+  const double* gp = (tid < B * B) ? G + min(gi, bl) * b + min(gc, bl) : rpd + min(gj, bl) * (b + 1);
+  const double gv = *gp;
 #pragma unroll
   for (int c = 0; c < B; ++c) {
     const double v = Y[(c < b ? c : 0) * ldy + rc];
     y[c] = (c < b) ? v : 0.0;
   }
+  if (tid < B * B)
+    gsh[tid] = (gi < b && gc < b) ? gv : (gi == gc ? 1.0 : 0.0);
+  else if (tid < B * B + B)
+    gsh[tid] = (gj < b && Rprev != nullptr) ? gv : 1.0;
+  lds_barrier();
 #pragma unroll
   for (int i = 0; i < B; ++i)
 #pragma unroll
-    for (int c = i; c < B; ++c) {
-      const double v = G[(c < b ? i : 0) * b + (c < b ? c : 0)];
-      R[upk<B>(i, c)] = (c < b) ? v : (i == c ? 1.0 : 0.0);
-    }
+    for (int c = i; c < B; ++c) R[upk<B>(i, c)] = gsh[i * B + c];
 #pragma unroll
   for (int j = 0; j < B; ++j) {
     gd[j] = R[upk<B>(j, j)];
-    const double v = (Rprev != nullptr) ? Rprev[(j < b ? j : 0) * (b + 1)] : 1.0;
-    pd[j] = (j < b) ? v : 1.0;
+    pd[j] = gsh[B * B + j];
   }
   if (skip_iter(ctrl, iter)) return;
   // right-looking Cholesky in place, G = R^T R

@@ -53,11 +53,6 @@ __device__ __forceinline__ PassItem item_of(const PassItem& one, const PassItem*
   return grp[i];
 }
 
-// Workgroup barrier that waits only for the wave's LDS operations: global loads issued for later
-// steps stay in flight across it (a plain __syncthreads also waits for them).
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
 
 // ---------------------------------------------------------------- operand fragments
 template <int MODE> struct Frag;
