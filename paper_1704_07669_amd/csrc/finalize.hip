@@ -342,14 +342,14 @@ __global__ __launch_bounds__(kNnThreads) void k_nn_update(double* __restrict__ o
                                                           int q, int64_t rows, double alpha,
                                                           const Ctrl* __restrict__ ctrl, int iter,
                                                           const double* __restrict__ Rs = nullptr,
-                                                          int qtot = 0) {
+                                                          int qtot = 0, int tri = 1) {
   if (qtot > 0) {
-    // column slices: workgroup row y = blockIdx.y takes output columns y q .. (qtot in all) with
-    // the rows a < (y + 1) q of W (an upper triangular W)
+    // column slices: workgroup row y = blockIdx.y takes output columns y q .. (qtot in all), with
+    // the rows a < (y + 1) q of W only when W is upper triangular (tri)
     const int y = blockIdx.y;
     out += (int64_t)y * q * ldo;
     W += y * q;
-    p = min(p, (y + 1) * q);
+    if (tri) p = min(p, (y + 1) * q);
     q = min(q, qtot - y * q);
   }
   constexpr int CH = kNnChunk;
@@ -1373,9 +1373,20 @@ __global__ __launch_bounds__(TPB) void k_signs(const double* __restrict__ V, int
   const int j = blockIdx.x;
   double best = -1.0;
   int64_t bidx = 0;
-  for (int64_t r = threadIdx.x; r < n; r += TPB) {
-    const double a = fabs(V[j * ldv + r]);
-    if (a > best) { best = a; bidx = r; }
+  // eight loads in flight per batch (at clamped addresses; rows past n are not compared), then
+  // the comparisons in row order, so ties keep the first index as before
+  for (int64_t r0 = threadIdx.x; r0 < n; r0 += 8 * TPB) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = r0 + (int64_t)u * TPB;
+      a[u] = fabs(V[j * ldv + (r < n ? r : n - 1)]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = r0 + (int64_t)u * TPB;
+      if (r < n && a[u] > best) { best = a[u]; bidx = r; }
+    }
   }
   bv[threadIdx.x] = best;
   bi[threadIdx.x] = bidx;
@@ -1726,14 +1737,14 @@ void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, doub
 }
 
 // Y = X R^-1 for the n x L column-major X and upper triangular R^-1 (row-major, leading dimension
-// L), in column slices of at most 32 (slice c0..c0+w-1 only needs rows 0..c0+w-1 of R^-1).
+// L), in column slices of at most 16 (slice c0..c0+w-1 only needs rows 0..c0+w-1 of R^-1).
 void right_trmul(Ctx& cx, double* Y, int64_t ldy, const double* X, int64_t ldx, int64_t rows,
                  int L, const double* Rinv) {
   if (!cx.ok() || L <= 0 || rows <= 0) return;
-  const int ny = cdiv(L, 32);
+  const int ny = cdiv(L, 16);
   const dim3 g((unsigned)cdiv<int64_t>(rows, kNnThreads), ny), blk(kNnThreads);
-  hipLaunchKernelGGL((k_nn_update<double, 32>), g, blk, 0, cx.s, Y, ldy, (const double*)nullptr,
-                     0, X, ldx, L, Rinv, L, 32, rows, 1.0, (const Ctrl*)nullptr, 0,
+  hipLaunchKernelGGL((k_nn_update<double, 16>), g, blk, 0, cx.s, Y, ldy, (const double*)nullptr,
+                     0, X, ldx, L, Rinv, L, 16, rows, 1.0, (const Ctrl*)nullptr, 0,
                      (const double*)nullptr, L);
   cx.chk();
 }
@@ -2020,11 +2031,13 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
     hipLaunchKernelGGL(k_gather, dim3(cdiv(L * kk, 256)), dim3(256), 0, stream, sm.Wm, L, L,
                        sm.perm, sm.sig, kk, sm.Jk, sm.Wk);
     cx.chk();
-    // V (column-major temp in the H storage) = B^T W S^-2, its signs, then the row-major outputs
+    // V (column-major temp in the H storage) = B^T W S^-2 in column slices of 16, its signs, then
+    // the row-major outputs
     double* Vt = const_cast<double*>(f.H);
-    const dim3 gv(grid_for(n, TPB, 4096), cdiv(kk, 16));
-    hipLaunchKernelGGL(k_write_rows, gv, dim3(TPB), (size_t)L * 16 * sizeof(double), stream,
-                       f.Bt, f.ldb, L, sm.Jk, kk, kk, (const double*)nullptr, n, Vt, f.ldh, 1);
+    const dim3 gv((unsigned)cdiv<int64_t>(n, kNnThreads), cdiv(kk, 16));
+    hipLaunchKernelGGL((k_nn_update<double, 16>), gv, dim3(kNnThreads), 0, stream, Vt, f.ldh,
+                       (const double*)nullptr, 0, f.Bt, f.ldb, L, sm.Jk, kk, 16, n, 1.0,
+                       (const Ctrl*)nullptr, 0, (const double*)nullptr, kk, 0);
     cx.chk();
     if (!cx.ok()) return cx.err;
     hipLaunchKernelGGL(k_signs, dim3(kk), dim3(TPB), 0, stream, Vt, f.ldh, n, sm.sgn);
