@@ -372,8 +372,18 @@ __global__ void k_reduce1(const PassItem one, const PassItem* __restrict__ grp, 
        q += (int64_t)it.red_wgs * blockDim.x) {
     const int c = (int)(q / nrows);
     const int r = (int)(q - (int64_t)c * nrows);
+    // the split partials in split order, eight loads in flight per batch (clamped to the last
+    // split, whose repeats are not added)
     acc_t s = 0;
-    for (int sp = 0; sp < splits; ++sp) s += P[((int64_t)sp * LP + c) * ldp + r];
+    for (int sp0 = 0; sp0 < splits; sp0 += 8) {
+      acc_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = P[((int64_t)min(sp0 + u, splits - 1) * LP + c) * ldp + r];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (sp0 + u < splits) s += v[u];
+    }
     s *= scale;
     bad |= !isfinite(s);
     G[(int64_t)c * ldg + g_row0 + r] = s;
