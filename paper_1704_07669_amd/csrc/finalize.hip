@@ -1887,6 +1887,7 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
 
   // ---------------- column-block loop (Alg. 4 steps 9-15).  Cholesky QR of the blocks first; if a
   // block was flagged as too ill-conditioned for it, the loop is repeated with Householder TSQR.
+  Ctrl hc{};
   for (int attempt = f.force_loop ? 1 : 0; attempt < 2 && cx.ok(); ++attempt) {
     const bool chol = (attempt == 0);
     hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l);
@@ -1914,7 +1915,8 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
                       ctrl, i);
           // C = Q^T Q_i; Z = Q_i - Q C; two Cholesky QR steps on Z
           tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
-          nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+          if (p > 0)   // (with p = 0 the projection leaves Z = Q_i)
+            nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
           tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C1, b, ctrl, i);
           cholqr_lane(cx, Qi, f.ldq, m, sm.C1, b, sm.R1, sm.R2, false, sm, p, ctrl, i);
           tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C2, b, ctrl, i);
@@ -1925,7 +1927,8 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
           cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)(p + b) * b, (int64_t)p * b, b,
                  nullptr, sm.R1, false, sm, p, ctrl, i);
           tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
-          nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+          if (p > 0)
+            nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
           nch = tn_partials(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, ctrl, i);
           cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)b * b, 0, b, sm.R1, sm.R2, false, sm,
                  p, ctrl, i);
@@ -1964,18 +1967,13 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
                  f.ldb, p, sm.Wn, b, b, n, -1.0, ctrl, i, sm.R);
     }
     f.path_loop = chol ? 0 : 1;
-    if (!chol || !cx.ok()) break;
-    int flagged = 1;
-    cx.err = hipMemcpyAsync(&flagged, &ctrl->pad[0], sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (!cx.ok()) break;
+    // one wait per loop: the rank decided on the device (it sizes the rest) and the Cholesky QR
+    // flag (pad[0]), which sends the loop round again with Householder TSQR
+    cx.err = hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
     if (cx.ok()) cx.err = hipStreamSynchronize(stream);
-    if (!cx.ok() || flagged == 0) break;
+    if (!chol || !cx.ok() || hc.pad[0] == 0) break;
   }
-  if (!cx.ok()) return cx.err;
-
-  // the rank decided on the device sizes the rest
-  Ctrl hc;
-  cx.err = hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
-  if (cx.ok()) cx.err = hipStreamSynchronize(stream);
   if (!cx.ok()) return cx.err;
   const int L = hc.l_eff;
   const int kk = (f.k < L) ? f.k : L;
