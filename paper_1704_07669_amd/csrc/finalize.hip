@@ -1060,43 +1060,90 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
   // the diagonal of G, for the conditioning test (dinv is filled only after the factorisation)
   for (int i = tid; i < L; i += kCholThreads) dinv[i] = a[i * LS + i];
   __syncthreads();
-  for (int j = 0; j < L; ++j) {
-    const double d = a[j * LS + j];            // same value in every thread: uniform exit
+  // Two pivots per step.  With t = a[j][j+1] / d0, row j+1 after pivot j is a[j+1][c] - t a[j][c]
+  // and d1 is its diagonal entry; every thread forms what it needs of that row, and the trailing
+  // rows take both rank-1 updates at once.  Row j+1 itself is stored one step later (by the
+  // threads of ty = 0), when no thread reads it any more, so a step still needs one barrier.
+  double w1[kCholSlots];                      // row j+1 of the previous step (ty == 0 threads)
+  int wrow = -1;
+  int j = 0;
+  for (; j + 1 < L; j += 2) {
+    if (ty == 0 && wrow >= 0) {
+#pragma unroll
+      for (int n = 0; n < kCholSlots; ++n) {
+        const int c = wrow + tx + 32 * n;
+        if (c < L) a[wrow * LS + c] = w1[n];
+      }
+    }
+    const double d0 = a[j * LS + j];           // same values in every thread: uniform exits
+    const double e01 = a[j * LS + j + 1];
+    const double tj = e01 / d0;
+    const double d1 = a[(j + 1) * LS + j + 1] - tj * e01;
+    if (tid == 0 && ill_rel > 0.0 && (!(d0 >= ill_rel * dinv[j]) || !(d1 >= ill_rel * dinv[j + 1])))
+      *ill = 1;
+    if (!(d0 > 0.0) || !(d0 < INFINITY) || !(d1 > 0.0) || !(d1 < INFINITY)) {
+      if (tid == 0) *fail = 1;
+      return;
+    }
+    if (tid == 0) { rd[j] = sqrt(d0); rd[j + 1] = sqrt(d1); }
+    const double i0 = 1.0 / d0, i1 = 1.0 / d1;
+    double c0[kCholSlots], c1[kCholSlots];
+#pragma unroll
+    for (int n = 0; n < kCholSlots; ++n) {
+      const int c = j + 2 + tx + 32 * n;
+      const double x0 = c < L ? a[j * LS + c] : 0.0;
+      const double x1 = c < L ? a[(j + 1) * LS + c] : 0.0;
+      c0[n] = x0;
+      c1[n] = x1 - tj * x0;
+    }
+    if (ty == 0) {
+#pragma unroll
+      for (int n = 0; n < kCholSlots; ++n) {
+        const int c = j + 1 + tx + 32 * n;
+        w1[n] = c < L ? a[(j + 1) * LS + c] - tj * a[j * LS + c] : 0.0;
+      }
+    }
+    wrow = j + 1;
+    // a[i][c] -= a[j][i] a[j][c] / d0 + a1[i] a1[c] / d1 for j + 1 < i <= c < L
+#pragma unroll
+    for (int m = 0; m < kCholSlots; ++m) {
+      const int i = j + 2 + ty + 32 * m;
+      if (i < L) {
+        const double x0 = a[j * LS + i];
+        const double r0 = x0 * i0;
+        const double r1 = (a[(j + 1) * LS + i] - tj * x0) * i1;
+        double v[kCholSlots];
+#pragma unroll
+        for (int n = 0; n < kCholSlots; ++n) {
+          const int c = j + 2 + tx + 32 * n;
+          v[n] = (c >= i && c < L) ? a[i * LS + c] : 0.0;
+        }
+#pragma unroll
+        for (int n = 0; n < kCholSlots; ++n) {
+          const int c = j + 2 + tx + 32 * n;
+          if (c >= i && c < L) a[i * LS + c] = fma(-r1, c1[n], fma(-r0, c0[n], v[n]));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (ty == 0 && wrow >= 0) {
+#pragma unroll
+    for (int n = 0; n < kCholSlots; ++n) {
+      const int c = wrow + tx + 32 * n;
+      if (c < L) a[wrow * LS + c] = w1[n];
+    }
+  }
+  if (j < L) {                                 // the last pivot of an odd L: nothing trails it
+    const double d = a[j * LS + j];
     if (tid == 0 && ill_rel > 0.0 && !(d >= ill_rel * dinv[j])) *ill = 1;
     if (!(d > 0.0) || !(d < INFINITY)) {
       if (tid == 0) *fail = 1;
       return;
     }
     if (tid == 0) rd[j] = sqrt(d);
-    // a[i][c] -= (a[j][i] / d) a[j][c] for j < i <= c < L, with row j left unscaled (it becomes
-    // row j of R once divided by sqrt(d) below), so a step needs one barrier
-    const double dinvj = 1.0 / d;
-    double rc[kCholSlots];
-#pragma unroll
-    for (int n = 0; n < kCholSlots; ++n) {
-      const int c = j + 1 + tx + 32 * n;
-      rc[n] = c < L ? a[j * LS + c] : 0.0;
-    }
-#pragma unroll
-    for (int m = 0; m < kCholSlots; ++m) {
-      const int i = j + 1 + ty + 32 * m;
-      if (i < L) {
-        const double ri = a[j * LS + i] * dinvj;
-        double v[kCholSlots];
-#pragma unroll
-        for (int n = 0; n < kCholSlots; ++n) {
-          const int c = j + 1 + tx + 32 * n;
-          v[n] = (c >= i && c < L) ? a[i * LS + c] : 0.0;
-        }
-#pragma unroll
-        for (int n = 0; n < kCholSlots; ++n) {
-          const int c = j + 1 + tx + 32 * n;
-          if (c >= i && c < L) a[i * LS + c] = fma(-ri, rc[n], v[n]);
-        }
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
   for (int i = tid; i < L; i += kCholThreads) dinv[i] = 1.0 / rd[i];
   __syncthreads();
   for (int idx = tid; idx < L * L; idx += kCholThreads) {   // rows of R: row i over sqrt(d_i)
