@@ -1156,34 +1156,63 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     // it; X[i][c] = rhs[i][c] / R_ii, then rhs[k][c] -= R[k][i] X[i][c] for k < i, c >= i.  The
     // right-hand sides stay unscaled in the strictly lower triangle (rhs[i][c] at [c][i]); X[i][c]
     // is formed where it is used, so a step needs one barrier.
-    for (int i = L - 1; i >= 0; --i) {
-      const double di = dinv[i];
-      double xc[kCholSlots];
+    // Two rows per step, i and i - 1: X[i-1][c] = (rhs[i-1][c] - R[i-1][i] X[i][c]) / R_{i-1,i-1}
+    // is formed where it is used, and the updated rhs[i-1][c] is stored one step later (by the
+    // threads of ty = 0), when no thread reads it any more.
+    double w1[kCholSlots];
+    int wcol = -1;                               // k of the stored-late entries rhs[k][c], c > k
+    int i = L - 1;
+    for (; i >= 1; i -= 2) {
+      if (ty == 0 && wcol >= 0) {
+#pragma unroll
+        for (int n = 0; n < kCholSlots; ++n) {
+          const int c = wcol + tx + 32 * n;
+          if (c > wcol && c < L) a[c * LS + wcol] = w1[n];
+        }
+      }
+      const int h = i - 1;
+      const double di = dinv[i], dh = dinv[h];
+      const double rhi = a[h * LS + i];          // R[i-1][i]
+      double xi[kCholSlots], xh[kCholSlots];
 #pragma unroll
       for (int n = 0; n < kCholSlots; ++n) {
-        const int c = i + tx + 32 * n;
-        xc[n] = c < L ? (c == i ? di : a[c * LS + i] * di) : 0.0;
+        const int c = h + tx + 32 * n;
+        const double yi = (c > i && c < L) ? a[c * LS + i] * di : (c == i ? di : 0.0);
+        const double rh = (c > h && c < L) ? a[c * LS + h] - rhi * yi : 0.0;
+        xi[n] = yi;
+        xh[n] = (c == h) ? dh : rh * dh;
+        if (ty == 0) w1[n] = rh;
       }
+      wcol = h;
 #pragma unroll
       for (int m = 0; m < kCholSlots; ++m) {
         const int k = ty + 32 * m;
-        if (k < i) {
-          const double rk = a[k * LS + i];
+        if (k < h) {
+          const double rki = a[k * LS + i], rkh = a[k * LS + h];
           double v[kCholSlots];
 #pragma unroll
           for (int n = 0; n < kCholSlots; ++n) {
-            const int c = i + tx + 32 * n;
+            const int c = h + tx + 32 * n;
             v[n] = c < L ? a[c * LS + k] : 0.0;
           }
 #pragma unroll
           for (int n = 0; n < kCholSlots; ++n) {
-            const int c = i + tx + 32 * n;
-            if (c < L) a[c * LS + k] = fma(-rk, xc[n], v[n]);
+            const int c = h + tx + 32 * n;
+            if (c < L) a[c * LS + k] = fma(-rkh, xh[n], fma(-rki, xi[n], v[n]));
           }
         }
       }
       __syncthreads();
     }
+    if (ty == 0 && wcol >= 0) {
+#pragma unroll
+      for (int n = 0; n < kCholSlots; ++n) {
+        const int c = wcol + tx + 32 * n;
+        if (c > wcol && c < L) a[c * LS + wcol] = w1[n];
+      }
+    }
+    // (with i = 0 left over, row 0 of X needs no further update: X[0][c] = rhs[0][c] / R_00)
+    __syncthreads();
   }
   bool dev = false;
   for (int idx = tid; idx < L * L; idx += kCholThreads) {
