@@ -1419,7 +1419,8 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
 // EPL (rows per lane) for L: LPAD = 8 EPL >= L.
 inline int jacobi_epl(int L) {
   const int need = cdiv(L, kJacobiLpp);
-  return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 14 ? 14 : 16;
+  return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 13 ? 13
+         : need <= 14 ? 14 : 16;
 }
 size_t jacobi_lds_bytes(int L) {
   const int N = (L + 1) & ~1, CS = jacobi_cs(kJacobiLpp * jacobi_epl(L));
@@ -1915,7 +1916,8 @@ hipError_t finalize_prepare() {
   hipError_t e = hipSuccess;
   for (const void* kj : {(const void*)k_jacobi<2>, (const void*)k_jacobi<4>,
                          (const void*)k_jacobi<8>, (const void*)k_jacobi<12>,
-                         (const void*)k_jacobi<14>, (const void*)k_jacobi<16>})
+                         (const void*)k_jacobi<13>, (const void*)k_jacobi<14>,
+                         (const void*)k_jacobi<16>})
     if (e == hipSuccess)
       e = hipFuncSetAttribute(kj, hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiLds);
   if (e == hipSuccess)
@@ -2093,6 +2095,8 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
         case 8: hipLaunchKernelGGL(k_jacobi<8>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info,
                                    sm.sig, sm.perm, sm.Jm); break;
         case 12: hipLaunchKernelGGL(k_jacobi<12>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
+                                    sm.info, sm.sig, sm.perm, sm.Jm); break;
+        case 13: hipLaunchKernelGGL(k_jacobi<13>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
                                     sm.info, sm.sig, sm.perm, sm.Jm); break;
         case 14: hipLaunchKernelGGL(k_jacobi<14>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
                                     sm.info, sm.sig, sm.perm, sm.Jm); break;
