@@ -149,8 +149,9 @@ sketch_status sketch_finalize_paths(sketch_t h, int32_t* loop_path, int32_t* rb_
 
 /* Test hook for the next sketch_finalize: loop_householder nonzero takes TSQR for every column
  * block without trying Cholesky QR; rb_mode 1 takes Gram-Schmidt + TSQR for R_B, 2 shifted Cholesky
- * QR3 directly, 0 the normal order.  All paths compute the same factorisation.  E_INVAL for another
- * rb_mode. */
+ * QR3 directly, 3 forms Cholesky QR2 and the results from it, then treats it as not accepted (so
+ * they are formed again from shifted Cholesky QR3, as for a rejected QR2), 0 the normal order.
+ * All paths compute the same factorisation.  E_INVAL for another rb_mode. */
 sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_mode);
 
 /* Copies the pass state as FP64 into device memory: G (rows x l, row-major, ld = l) and

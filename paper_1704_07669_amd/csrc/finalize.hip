@@ -1841,19 +1841,19 @@ void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double*
 // storage (H is no longer needed at this point).
 const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L);
 
-const double* chol_qr(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
+void chol_qr2(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
   const int64_t n = f.n;
   double* Gm = sm.Jm;
   double* Rs = sm.Wm;
   double* Ri = sm.Jk;
   double* Racc = sm.Wk;
-  double* Q2 = const_cast<double*>(f.H);
   int* fail = sm.info + 1;
   int* ill = sm.info + 2;
-  int hflags[2] = {1, 1};
-  // Cholesky QR2 without a shift first: accurate when no pivot of B B^T falls below 1e-8 of its
+  // Cholesky QR2 without a shift: accurate when no pivot of B B^T falls below 1e-8 of its
   // diagonal entry (cond(B) up to about 1e4) and the second factor is within 1e-6 of I (Q1 was
-  // orthonormal to about 1e-6, so Q2 is to working precision)
+  // orthonormal to about 1e-6, so Q2 is to working precision).  R_B goes to sm.RB; the two tests
+  // leave nonzero flags at sm.info[1] (a pivot failed) and sm.info[2] (a test failed), which the
+  // caller reads later.
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, fail, 0);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, ill, 0);
   cx.chk();
@@ -1862,14 +1862,9 @@ const double* chol_qr(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
   right_trmul(cx, f.Qb, f.ldb, f.Bt, f.ldb, n, L, Ri);
   gram_upper(cx, f.Qb, f.ldb, n, L, f.red_ws, Gm);
   chol(cx, Gm, L, 0.0, Rs, nullptr, fail, 0.0, 1e-6, ill);
-  if (!cx.ok()) return nullptr;
+  if (!cx.ok()) return;
   hipLaunchKernelGGL(k_trmm_upper, dim3(L), dim3(JMAX), 0, cx.s, Rs, Racc, sm.RB, L);
   cx.chk();
-  if (cx.ok()) cx.err = hipMemcpyAsync(hflags, fail, 2 * sizeof(int), hipMemcpyDeviceToHost, cx.s);
-  if (cx.ok()) cx.err = hipStreamSynchronize(cx.s);
-  if (!cx.ok()) return nullptr;
-  if (hflags[0] == 0 && hflags[1] == 0) return sm.RB;
-  return chol_qr3_shifted(cx, f, sm, L);
 }
 
 // Shifted Cholesky QR3 of B^T (see k_chol); R_B as chol_qr, or nullptr when a pivot failed.
@@ -2056,13 +2051,20 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   const int L = hc.l_eff;
   const int kk = (f.k < L) ? f.k : L;
 
-  if (L > 0) {
-    // ---------------- R_B: shifted Cholesky QR3 of B^T; Gram-Schmidt + TSQR if a pivot fails
-    const double* RBp = f.force_rb == 1 ? nullptr
-                        : f.force_rb == 2 ? chol_qr3_shifted(cx, f, sm, L)
-                                          : chol_qr(cx, f, sm, L);
+  // ---------------- R_B, then the Jacobi SVD and the outputs.  Cholesky QR2 first (rb_mode 0): its
+  // acceptance tests are read with the final wait, the SVD and the outputs being formed from its
+  // R_B meanwhile; in the rare case it is not accepted, all of it is formed again from shifted
+  // Cholesky QR3 (rb_mode 2), or from Gram-Schmidt + TSQR (rb_mode 1) if a pivot of that fails.
+  for (int rb_mode = (f.force_rb == 3) ? 0 : f.force_rb; L > 0;) {
+    const double* RBp = nullptr;
+    if (rb_mode == 0) {
+      chol_qr2(cx, f, sm, L);
+      RBp = sm.RB;
+    } else if (rb_mode == 2) {
+      RBp = chol_qr3_shifted(cx, f, sm, L);
+    }
     if (!cx.ok()) return cx.err;
-    f.path_rb = (RBp == nullptr) ? 1 : (RBp == sm.RB ? 0 : 2);
+    f.path_rb = (rb_mode == 0) ? 0 : (RBp == nullptr ? 1 : 2);
     if (RBp == nullptr) {
       RBp = sm.RB;
       cx.err = launch_fill_f64(sm.RB, (int64_t)L * L, 0.0, stream);
@@ -2133,7 +2135,16 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
     if (!cx.ok()) return cx.err;
     hipLaunchKernelGGL(k_write_s, dim3(1), dim3(256), 0, stream, sm.sig, kk, f.k, f.S);
     cx.chk();
-  } else {
+    if (!cx.ok()) return cx.err;
+    if (rb_mode != 0) break;
+    int hflags[2] = {1, 1};
+    cx.err = hipMemcpyAsync(hflags, sm.info + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+    if (!cx.ok()) return cx.err;
+    if (hflags[0] == 0 && hflags[1] == 0 && f.force_rb != 3) break;
+    rb_mode = 2;
+  }
+  if (L <= 0) {
     // rank 0: all outputs zero
     double zero_s = 0.0;
     (void)zero_s;

@@ -109,7 +109,8 @@ struct FinalizeArgs {
   Ctrl* ctrl;
   double* S; double* U; int64_t ldu; double* V; int64_t ldv;
   int32_t force_loop = 0;            // in: 1 takes the Householder TSQR path of the loop directly
-  int32_t force_rb = 0;              // in: 1 Gram-Schmidt + TSQR for R_B, 2 shifted Cholesky QR3
+  int32_t force_rb = 0;              // in: 1 Gram-Schmidt + TSQR for R_B, 2 shifted Cholesky QR3,
+                                     //     3 QR2 formed, then treated as not accepted
   int32_t path_loop = -1;            // out: 0 Cholesky QR of the blocks, 1 Householder TSQR
   int32_t path_rb = -1;              // out: 0 Cholesky QR2 of B^T, 2 shifted Cholesky QR3,
                                      //      1 Gram-Schmidt + TSQR

@@ -531,11 +531,11 @@ sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t 
   return SKETCH_OK;
 }
 
-sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_householder) {
+sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_mode) {
   if (sketch_status st = check_handle(h)) return st;
-  if (rb_householder < 0 || rb_householder > 2) return fail(SKETCH_E_INVAL, "rb mode must be 0, 1 or 2");
+  if (rb_mode < 0 || rb_mode > 3) return fail(SKETCH_E_INVAL, "rb mode must be 0, 1, 2 or 3");
   h->force_loop = loop_householder ? 1 : 0;
-  h->force_rb = rb_householder;
+  h->force_rb = rb_mode;
   return SKETCH_OK;
 }
 
