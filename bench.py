@@ -370,7 +370,7 @@ def host_workload(args, torch, sk):
             r["gate_1e3"] = bool(e[k - 1] <= 1e-3)
         rows_ref = sum(x.shape[0] for x in ref_blocks)
         cpu = dict(value=4.0 * m * n / (t_ref * m / rows_ref / len(res)) / 1e9, unit="GB/s",
-                   cores=int(os.cpu_count() or 1), kind="oracle",
+                   cores=host_cpu_info()[0], host_cores=host_cpu_info()[1], kind="oracle",
                    sample=f"FP64 reference pass over {rows_ref} rows with {len(res)} sketches of "
                           f"width {l} side by side ({t_ref:.1f} s), per sketch, scaled by "
                           f"m/{rows_ref}; finalize excluded")
@@ -455,40 +455,54 @@ def accuracy(A_host, K, res_modes, args):
     return out
 
 
-def cpu_baseline(A_host, args):
-    """The FP64 reference as it stands, timed on the host on a bounded sample: the pass over the
-    leading row blocks until the time budget is spent, then the finalize on that sample's sketch;
-    both are scaled linearly in m to the whole workload."""
-    import oracle
+def host_cpu_info():
+    """Threads the reference's BLAS runs with, and the host's logical / physical core counts."""
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 0) for d in threadpool_info()] or [os.cpu_count()])
+        threads = max([d.get("num_threads", 0) for d in threadpool_info()] or [os.cpu_count()])
     except Exception:
-        cores = os.cpu_count()
+        threads = os.cpu_count()
+    try:
+        import psutil
+        phys = psutil.cpu_count(logical=False)
+    except Exception:
+        phys = None
+    return int(threads), dict(logical=os.cpu_count(), physical=phys)
+
+
+def cpu_baseline(A_host, args):
+    """The FP64 reference as it stands, timed on the host on a bounded sample: its pass
+    (oracle.sketch_pass) over the leading row blocks until the time budget is spent, then its
+    column-block loop and SVD (oracle.qb_from_sketch, oracle.svd_from_qb) on that sample's sketch;
+    both are scaled linearly in m to the whole workload."""
+    import oracle
+    threads, host = host_cpu_info()
     m = A_host.shape[0]
     Om = oracle.gaussian_omega_philox(args.n, args.l, 2002)
     budget = args.cpu_seconds
+    seen = [0]
+
+    def sample_blocks(t_start):
+        while seen[0] < m and time.perf_counter() - t_start < budget * 0.7:
+            a = A_host[seen[0]:seen[0] + args.block]
+            seen[0] += a.shape[0]
+            yield a
+
     t0 = time.perf_counter()
-    import numpy as _np
-    H = _np.zeros((args.n, args.l))
-    Gs, rows = [], 0
-    while rows < m and time.perf_counter() - t0 < budget * 0.7:
-        a = _np.asarray(A_host[rows:rows + args.block], dtype=_np.float64)
-        g = a @ Om
-        Gs.append(g)
-        H += a.T @ g
-        rows += a.shape[0]
+    G, H = oracle.sketch_pass(sample_blocks(t0), Om)
     t_pass = time.perf_counter() - t0
+    rows = seen[0]
     t1 = time.perf_counter()
-    Q, B, r, _ = oracle.qb_from_sketch(_np.vstack(Gs), H, Om, args.b)
+    Q, B, _, _ = oracle.qb_from_sketch(G, H, Om, args.b)
     oracle.svd_from_qb(Q, B, args.k, want_u=False)
     t_fin = time.perf_counter() - t1
     scale = m / rows
     t_est = (t_pass + t_fin) * scale
-    return dict(value=4.0 * m * args.n / t_est / 1e9, unit="GB/s", cores=int(cores), kind="oracle",
-                sample=f"FP64 reference pass over the first {rows} of {m} rows ({rows // args.block}"
-                       f" blocks, {t_pass:.1f} s) plus its finalize ({t_fin:.1f} s), scaled by "
-                       f"m/{rows} to the whole workload")
+    return dict(value=4.0 * m * args.n / t_est / 1e9, unit="GB/s", cores=threads, kind="oracle",
+                host_cores=host,
+                sample=f"oracle.sketch_pass over the first {rows} of {m} rows ({rows // args.block}"
+                       f" blocks, {t_pass:.1f} s) plus qb_from_sketch and svd_from_qb on that "
+                       f"sketch ({t_fin:.1f} s), scaled by m/{rows}")
 
 
 def main():

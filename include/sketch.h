@@ -24,8 +24,9 @@
  *   - Kernels run on the caller's HIP stream given at init.  A handle is not thread-safe;
  *     distinct handles may be used concurrently.
  *   - Any HIP runtime error makes the handle sticky in SKETCH_E_DEVICE; only sketch_destroy is
- *     then valid.  A block holding a NaN or Inf makes it sticky in SKETCH_E_NONFINITE, reported
- *     by sketch_finalize, the first call that waits for the pass.
+ *     then valid.  A block holding a NaN or Inf makes it sticky in SKETCH_E_NONFINITE: the kernel
+ *     that sees it sets a host-mapped flag, so the first call made after that kernel ran reports
+ *     it (at the latest sketch_finalize, which waits for the pass).
  */
 #ifndef SKETCH_H
 #define SKETCH_H

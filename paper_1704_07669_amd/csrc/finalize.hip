@@ -18,6 +18,8 @@
 // SVD of B: B^T = Q_B R_B by the same block Gram-Schmidt-with-re-orthogonalisation + TSQR scheme,
 // then a one-sided (Hestenes) Jacobi SVD of R_B^T in one workgroup: R_B^T J = W with orthogonal
 // columns, so B = (W S^-1) S (Q_B J)^T, i.e. U~ = W S^-1, V = Q_B J, U = Q U~.
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -1018,7 +1020,7 @@ size_t chol_lds_bytes(int L) { return ((size_t)L * (L + 1) + 2 * (size_t)L) * si
 // Gm (upper triangle read, row-major, leading dimension ldg) + s I = R^T R with R upper triangular
 // with a positive diagonal; s = shift_rel tr(Gm) when shift_rel > 0, else 0.  Writes R and, when
 // Rinv is non-null, R^-1 (row-major, leading dimension ldr, zeros below the diagonal).  A pivot that
-// is not positive and finite sets *fail (left as it was otherwise) and the outputs are unspecified.
+// is not positive and finite sets *fail (left as it was otherwise) and writes identity factors.
 // Conditioning tests, each setting *ill: ill_rel > 0, a pivot below ill_rel times the diagonal
 // entry of Gm it started from; dev_rel > 0, an entry of R farther than dev_rel from the identity.
 // One workgroup, threads in a 32 x 32 grid, each owning rows ty + 32 m and columns tx + 32 n of the
@@ -1027,6 +1029,18 @@ size_t chol_lds_bytes(int L) { return ((size_t)L * (L + 1) + 2 * (size_t)L) * si
 // per step from the bottom, with R^-1[k][c] (k < c) kept in the strictly lower triangle at [c][k].
 // Every step loads its operands into registers before it stores, so the loads overlap, and ends
 // with its only barrier (scalings are deferred or applied where the values are read).
+// The outputs of a failed factorisation: identity factors, so that the kernels that consume them
+// before the host reads the failure flag work on defined, finite values.
+__device__ __forceinline__ void chol_write_identity(double* __restrict__ R,
+                                                    double* __restrict__ Rinv, int ldr, int L,
+                                                    int tid) {
+  for (int idx = tid; idx < L * L; idx += kCholThreads) {
+    const int i = idx / L, c = idx % L;
+    R[(int64_t)i * ldr + c] = (i == c) ? 1.0 : 0.0;
+    if (Rinv != nullptr) Rinv[(int64_t)i * ldr + c] = (i == c) ? 1.0 : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict__ Gm, int ldg,
                                                        int L, double shift_rel,
                                                        double* __restrict__ R,
@@ -1083,6 +1097,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
       *ill = 1;
     if (!(d0 > 0.0) || !(d0 < INFINITY) || !(d1 > 0.0) || !(d1 < INFINITY)) {
       if (tid == 0) *fail = 1;
+      chol_write_identity(R, Rinv, ldr, L, tid);
       return;
     }
     if (tid == 0) { rd[j] = sqrt(d0); rd[j + 1] = sqrt(d1); }
@@ -1139,6 +1154,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     if (tid == 0 && ill_rel > 0.0 && !(d >= ill_rel * dinv[j])) *ill = 1;
     if (!(d > 0.0) || !(d < INFINITY)) {
       if (tid == 0) *fail = 1;
+      chol_write_identity(R, Rinv, ldr, L, tid);
       return;
     }
     if (tid == 0) rd[j] = sqrt(d);
@@ -1403,10 +1419,15 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
     nrm[col] = sqrt(s);
   }
   __syncthreads();
+  // descending order with ties by index; a NaN norm (a non-finite R_B) ranks below every number,
+  // so the ranks stay a permutation whatever the input
   for (int col = threadIdx.x; col < L; col += kJacobiThreads) {
+    const double kc = (nrm[col] == nrm[col]) ? nrm[col] : -1.0;
     int rank = 0;
-    for (int o = 0; o < L; ++o)
-      rank += (nrm[o] > nrm[col]) || (nrm[o] == nrm[col] && o < col);
+    for (int o = 0; o < L; ++o) {
+      const double ko = (nrm[o] == nrm[o]) ? nrm[o] : -1.0;
+      rank += (ko > kc) || (ko == kc && o < col);
+    }
     sig[rank] = nrm[col];
     perm[rank] = col;
   }
@@ -1434,7 +1455,8 @@ __global__ void k_gather(const double* __restrict__ W, int ld, int L, const int*
                          double* __restrict__ Wk) {
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < L * kk; idx += gridDim.x * blockDim.x) {
     const int i = idx / kk, j = idx % kk;
-    const int col = perm[j];
+    const int pc = perm[j];
+    const int col = pc < 0 ? 0 : (pc >= L ? L - 1 : pc);
     const double sj = sig[j];
     Wk[idx] = sj > 0.0 ? W[i * ld + col] / sj : 0.0;
     Wv[idx] = sj > 0.0 ? W[i * ld + col] / (sj * sj) : 0.0;
@@ -1907,8 +1929,17 @@ const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, 
 
 }  // namespace
 
+// Raises the dynamic LDS limits of the kernels that need more than the default, once per device
+// (the attribute belongs to the device the call runs on), safely from any number of threads.
 hipError_t finalize_prepare() {
-  hipError_t e = hipSuccess;
+  static std::mutex mu;
+  static bool done[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done[dev]) return hipSuccess;
   for (const void* kj : {(const void*)k_jacobi<2>, (const void*)k_jacobi<4>,
                          (const void*)k_jacobi<8>, (const void*)k_jacobi<12>,
                          (const void*)k_jacobi<13>, (const void*)k_jacobi<14>,
@@ -1918,6 +1949,7 @@ hipError_t finalize_prepare() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)chol_lds_bytes(JMAX));
+  if (e == hipSuccess) done[dev] = true;
   return e;
 }
 

@@ -42,6 +42,8 @@ struct PassItem {
   int64_t ldh;
   const int* fp8_exp;  // device exponent e of the block scale 2^e (FP8 mode), else null
   Ctrl* ctrl;
+  int* nf_host;        // host-mapped flag also set when the block is non-finite (or null), so the
+                       //   host sees it without waiting for the stream
   void* P2;            // row-split partials of a^T g: strips x rsplit x LP x strip width
   unsigned* counters;  // one zero-initialised arrival counter per strip
   int32_t nrows, vec_ok, splits, row_tiles;
@@ -78,8 +80,10 @@ hipError_t launch_reduce1(const PassGroup& g, hipStream_t s);
 // a^T g, plus (for items split over rows) the fixed-order sum of the row-split partials into H
 hipError_t launch_gemm2(const PassGroup& g, hipStream_t s);
 // FP8 mode: amax of the block, then a' = e4m3(a 2^e) into `q` (nrows x ldq bytes).
+// A block whose amax is not finite sets *nonfinite (and *nf_host when not null).
 hipError_t launch_fp8_quantize(const float* A, int64_t lda, int nrows, int64_t n, uint32_t* amax,
-                               uint8_t* q, int64_t ldq, int* exp_out, hipStream_t s);
+                               uint8_t* q, int64_t ldq, int* exp_out, int* nonfinite, int* nf_host,
+                               hipStream_t s);
 
 // ---------------------------------------------------------------- small helpers
 hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s);
@@ -115,6 +119,8 @@ struct FinalizeArgs {
   int32_t path_rb = -1;              // out: 0 Cholesky QR2 of B^T, 2 shifted Cholesky QR3,
                                      //      1 Gram-Schmidt + TSQR
 };
+constexpr int kMaxDevices = 64;
+// Once per device and thread-safe: kernel attributes the finalize needs (call on the device used).
 hipError_t finalize_prepare();
 size_t finalize_small_elems(int l, int b);
 size_t tsqr_workspace_elems(int64_t rows, int b);

@@ -397,7 +397,10 @@ __global__ void k_reduce1(const PassItem one, const PassItem* __restrict__ grp, 
       reinterpret_cast<SK_GLOBAL acc_t*>(gop)[(int64_t)c * ldp + r] = s;
     }
   }
-  if (bad) gptr(it.ctrl)->nonfinite = 1;
+  if (bad) {
+    gptr(it.ctrl)->nonfinite = 1;
+    if (it.nf_host) *it.nf_host = 1;
+  }
 }
 
 // ---------------------------------------------------------------- H += a^T g
@@ -987,11 +990,21 @@ __device__ __forceinline__ int fp8_exponent(uint32_t amax_bits) {
   return (f <= 0.875f) ? (9 - ex) : (8 - ex);
 }
 
+// A NaN or Inf anywhere in the block makes amax (the largest |x| as bits; NaN and Inf order above
+// every finite value) non-finite: the block is flagged, since no scale could represent it.
 __global__ void k_quant_fp8(const float* __restrict__ A, int64_t lda, int nrows, int64_t n,
                             const uint32_t* __restrict__ amax, uint8_t* __restrict__ q,
-                            int64_t ldq, int* __restrict__ exp_out) {
-  const int e = fp8_exponent(*amax);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *exp_out = e;
+                            int64_t ldq, int* __restrict__ exp_out, int* __restrict__ nonfinite,
+                            int* __restrict__ nf_host) {
+  const uint32_t abits = *amax;
+  const int e = fp8_exponent(abits);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *exp_out = e;
+    if (abits >= 0x7f800000u) {
+      *nonfinite = 1;
+      if (nf_host) *nf_host = 1;
+    }
+  }
   const float sc = ldexpf(1.0f, e);
   const int64_t per_row = ldq / 4;
   const int64_t total = (int64_t)nrows * per_row;
@@ -1190,7 +1203,8 @@ inline int grid_for(int64_t work, int block = 256, int cap = 65536) {
 }  // namespace
 
 hipError_t launch_fp8_quantize(const float* A, int64_t lda, int nrows, int64_t n, uint32_t* amax,
-                               uint8_t* q, int64_t ldq, int* exp_out, hipStream_t s) {
+                               uint8_t* q, int64_t ldq, int* exp_out, int* nonfinite, int* nf_host,
+                               hipStream_t s) {
   hipError_t e = launch_fill_u32(amax, 1, 0u, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_amax, dim3(grid_for((int64_t)nrows * n, 256, 4096)), dim3(256), 0, s, A,
@@ -1198,7 +1212,8 @@ hipError_t launch_fp8_quantize(const float* A, int64_t lda, int nrows, int64_t n
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_quant_fp8, dim3(grid_for((int64_t)nrows * (ldq / 4), 256, 16384)),
-                     dim3(256), 0, s, A, lda, nrows, n, amax, q, ldq, exp_out);
+                     dim3(256), 0, s, A, lda, nrows, n, amax, q, ldq, exp_out, nonfinite,
+                     nf_host);
   return hipGetLastError();
 }
 

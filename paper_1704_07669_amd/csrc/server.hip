@@ -545,6 +545,11 @@ sketch_status sketch_server_create(sketch_server_t* out, const sketch_server_con
     e = hipEventCreateWithFlags(&s->table_ev[i], hipEventDisableTiming);
   if (e == hipSuccess)
     e = launch_fill_u32(s->at<uint32_t>(z.off_cnt), z.cnt_per_slot * cfg->max_group, 0u, s->stream);
+  // the finalize's small matrices start defined (no kernel reads them before writing, but a
+  // rejected factorisation must never meet uninitialised memory)
+  if (e == hipSuccess)
+    e = launch_fill_f64(s->at<double>(z.off_small), (int64_t)finalize_small_elems(cfg->l, 32), 0.0,
+                        s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
     const char* msg = hipGetErrorString(e);

@@ -159,6 +159,8 @@ struct sketch_s {
   int64_t rows = 0;
   int phase = 0;                    // 0: needs Omega, 1: ingesting, 2: finalized
   sketch_status sticky = SKETCH_OK;
+  int* nf_host = nullptr;           // host-mapped non-finite flag (host address), or null
+  int* nf_dev = nullptr;            // its device address
   int32_t path_loop = -1, path_rb = -1;   // QR methods the last finalize used
   int32_t force_loop = 0, force_rb = 0;   // test hook: take the Householder paths directly
   uint64_t next_ticket = 1;
@@ -196,6 +198,9 @@ namespace {
 
 sketch_status check_handle(sketch_t h) {
   if (!h) return fail(SKETCH_E_INVAL, "handle is NULL");
+  // a block the kernels found non-finite is reported by the first call after they ran
+  if (h->sticky == SKETCH_OK && h->nf_host && *reinterpret_cast<volatile int*>(h->nf_host) != 0)
+    h->sticky = SKETCH_E_NONFINITE;
   if (h->sticky != SKETCH_OK)
     return fail(h->sticky, "handle is in a sticky error state (%d)", (int)h->sticky);
   return SKETCH_OK;
@@ -268,11 +273,9 @@ sketch_status sketch_init(sketch_t* out, const sketch_config* cfg, void* dev_ws,
   if ((int64_t)ws_bytes < L.total)
     return fail(SKETCH_E_NOMEM, "workspace holds %zu bytes, %lld needed", ws_bytes,
                 (long long)L.total);
-  static bool prepared = false;
-  if (!prepared) {
+  {
     hipError_t e = finalize_prepare();
     if (e != hipSuccess) return fail(SKETCH_E_DEVICE, "kernel attributes: %s", hipGetErrorString(e));
-    prepared = true;
   }
   sketch_s* h = new sketch_s();
   h->cfg = *cfg;
@@ -288,9 +291,23 @@ sketch_status sketch_init(sketch_t* out, const sketch_config* cfg, void* dev_ws,
   }
   for (int i = 0; i < cfg->host_slots && e == hipSuccess; ++i)
     e = hipEventCreateWithFlags(&h->slot_consumed[i], hipEventDisableTiming);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&h->nf_host, 64, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) {
+    *reinterpret_cast<volatile int*>(h->nf_host) = 0;
+    e = hipHostGetDevicePointer((void**)&h->nf_dev, h->nf_host, 0);
+  }
   if (e != hipSuccess) {
     sketch_destroy(h);
     return fail(SKETCH_E_DEVICE, "stream/event creation: %s", hipGetErrorString(e));
+  }
+  // the finalize's small matrices start defined (no kernel reads them before writing, but a
+  // rejected factorisation must never meet uninitialised memory)
+  e = launch_fill_f64(h->at<double>(L.off_small), (int64_t)finalize_small_elems(cfg->l, cfg->b),
+                      0.0, h->stream);
+  if (e != hipSuccess) {
+    sketch_destroy(h);
+    return fail(SKETCH_E_DEVICE, "workspace clear: %s", hipGetErrorString(e));
   }
   sketch_status st = start_pass(h);
   if (st != SKETCH_OK) {
@@ -394,12 +411,14 @@ sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtyp
   it.ldh = L.NP;
   it.fp8_exp = nullptr;
   it.ctrl = h->ctrl();
+  it.nf_host = h->nf_dev;
   int src = src_dtype;
   if (c.compute == SKETCH_FP8_E4M3) {
     uint32_t* amax = h->at<uint32_t>(L.off_fp8);
     int* ex = reinterpret_cast<int*>(amax + 4);
     uint8_t* q = h->ws + L.off_fp8q;
-    e = launch_fp8_quantize((const float*)A, lda, (int)nrows, c.n, amax, q, L.NQ, ex, h->stream);
+    e = launch_fp8_quantize((const float*)A, lda, (int)nrows, c.n, amax, q, L.NQ, ex,
+                            &h->ctrl()->nonfinite, h->nf_dev, h->stream);
     if (e != hipSuccess) return h->dev_fail(e, "fp8 quantize");
     it.A = q;
     it.lda = L.NQ;
@@ -627,6 +646,7 @@ sketch_status sketch_destroy(sketch_t h) {
     if (r.c) (void)hipEventDestroy(r.c);
   }
   for (auto ev : h->ev_free) (void)hipEventDestroy(ev);
+  if (h->nf_host) (void)hipHostFree(h->nf_host);
   delete h;
   return SKETCH_OK;
 }
