@@ -167,3 +167,74 @@ def basic_randqb_svd(A, Omega, k, want_u=True):
     B = Q.T @ A
     S, U, V = svd_from_qb(Q, B, k, want_u)
     return PCAResult(S=S, V=V, U=U, rank=Q.shape[1], Q=Q, B=B)
+
+
+def power_omega(H):
+    """The power scheme with P = 1 for Algorithm 4 (Sec. 2.2, last paragraph of Sec. 3.3, and the
+    P = 1 runs after Table 1 in Sec. 4.2): the second pass uses Omega replaced by orth(H).
+
+    orth(H) is the Q factor of an economy QR of H (Sec. 2.2, diag R >= 0).  Reading: it is scaled
+    by sqrt(n), so its entries keep the unit variance of the Gaussian Omega; Algorithm 4 depends on
+    Omega only through its column span, so the scale changes no result in exact arithmetic.
+    """
+    H = np.asarray(H, dtype=np.float64)
+    Q, _ = _qr_nonneg(H)
+    return np.sqrt(H.shape[0]) * Q
+
+
+def single_pass_pca_power(blocks, Omega, k, b, tau=1e-10, want_u=True, keep_state=False):
+    """Algorithm 4 with one power iteration (P = 1): a first pass gives H = A^T A Omega, then the
+    pass and the column-block loop run again with Omega_2 = power_omega(H) (two passes over A in
+    all).  `blocks` is a list of row blocks (it is read twice).  The result carries Omega_2."""
+    blocks = list(blocks)
+    _, H1 = sketch_pass(blocks, Omega)
+    Om2 = power_omega(H1)
+    res = single_pass_pca(blocks, Om2, k, b, tau, want_u, keep_state)
+    res.Omega = Om2
+    return res
+
+
+def sketch_pass_centred(blocks, Omega):
+    """The single pass with the column sums needed for implicit centring (PCA of a centred A,
+    Sec. 2.1, where the data is assumed centred).  Besides G and H (Eq. 10) it returns
+    s_A = A^T 1 (n) and s_G = G^T 1 (l), both sums over all rows, and the row count m."""
+    blocks = [np.asarray(a, dtype=np.float64) for a in blocks]
+    G, H = sketch_pass(blocks, Omega)
+    n = np.asarray(Omega).shape[0]
+    s_A = np.zeros(n)
+    for a in blocks:
+        s_A += a.sum(axis=0)
+    s_G = G.sum(axis=0)
+    return G, H, s_A, s_G, G.shape[0]
+
+
+def centre_sketch(G, H, Omega, s_A, s_G, m):
+    """The sketch of the column-centred matrix A_c = A - 1 mu^T, mu = s_A / m, from the sketch of A:
+
+      G_c = A_c Omega   = G - 1 (Omega^T mu)^T
+      H_c = A_c^T G_c   = H - s_A w^T - mu s_G^T + m mu w^T = H - mu s_G^T   (w = Omega^T mu,
+                                                                             s_A = m mu)
+    so the centred PCA stays single-pass."""
+    Omega = np.asarray(Omega, dtype=np.float64)
+    mu = np.asarray(s_A, dtype=np.float64) / m
+    w = Omega.T @ mu
+    Gc = np.asarray(G, dtype=np.float64) - w[None, :]
+    Hc = np.asarray(H, dtype=np.float64) - np.outer(mu, np.asarray(s_G, dtype=np.float64))
+    return Gc, Hc, mu
+
+
+def single_pass_pca_centred(blocks, Omega, k, b, tau=1e-10, want_u=True, keep_state=False):
+    """Algorithm 4 on the column-centred matrix, centred implicitly: one pass with column sums,
+    the sketch corrected by centre_sketch, then the column-block loop and SVD as usual.  U holds
+    the left singular vectors of A_c.  The result carries mu."""
+    G, H, s_A, s_G, m = sketch_pass_centred(blocks, Omega)
+    if m == 0:
+        return single_pass_pca([], Omega, k, b, tau, want_u, keep_state)
+    Gc, Hc, mu = centre_sketch(G, H, Omega, s_A, s_G, m)
+    Q, B, rank, Rs = qb_from_sketch(Gc, Hc, Omega, b, tau)
+    S, U, V = svd_from_qb(Q, B, k, want_u)
+    res = PCAResult(S=S, V=V, U=U, rank=rank)
+    res.mu = mu
+    if keep_state:
+        res.G, res.H, res.Q, res.B, res.R = Gc, Hc, Q, B, Rs
+    return res
