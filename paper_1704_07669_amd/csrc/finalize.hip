@@ -1046,7 +1046,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
                                                        double* __restrict__ R,
                                                        double* __restrict__ Rinv, int ldr,
                                                        int* __restrict__ fail, double ill_rel,
-                                                       double dev_rel, int* __restrict__ ill) {
+                                                       double dev_rel, int* __restrict__ ill,
+                                                       int force_fail) {
   extern __shared__ double a[];     // L x (L + 1), then rd[L] (diag of R), dinv[L] (its inverse)
   const int LS = L + 1, tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
   double* rd = a + (int64_t)L * LS;
@@ -1095,7 +1096,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     const double d1 = a[(j + 1) * LS + j + 1] - tj * e01;
     if (tid == 0 && ill_rel > 0.0 && (!(d0 >= ill_rel * dinv[j]) || !(d1 >= ill_rel * dinv[j + 1])))
       *ill = 1;
-    if (!(d0 > 0.0) || !(d0 < INFINITY) || !(d1 > 0.0) || !(d1 < INFINITY)) {
+    if (force_fail || !(d0 > 0.0) || !(d0 < INFINITY) || !(d1 > 0.0) || !(d1 < INFINITY)) {
       if (tid == 0) *fail = 1;
       chol_write_identity(R, Rinv, ldr, L, tid);
       return;
@@ -1152,7 +1153,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
   if (j < L) {                                 // the last pivot of an odd L: nothing trails it
     const double d = a[j * LS + j];
     if (tid == 0 && ill_rel > 0.0 && !(d >= ill_rel * dinv[j])) *ill = 1;
-    if (!(d > 0.0) || !(d < INFINITY)) {
+    if (force_fail || !(d > 0.0) || !(d < INFINITY)) {
       if (tid == 0) *fail = 1;
       chol_write_identity(R, Rinv, ldr, L, tid);
       return;
@@ -1849,10 +1850,10 @@ void right_trmul(Ctx& cx, double* Y, int64_t ldy, const double* X, int64_t ldx, 
 }
 
 void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double* Rinv, int* fail,
-          double ill_rel = 0.0, double dev_rel = 0.0, int* ill = nullptr) {
+          double ill_rel = 0.0, double dev_rel = 0.0, int* ill = nullptr, int force_fail = 0) {
   if (!cx.ok()) return;
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), chol_lds_bytes(L), cx.s, Gm, L, L,
-                     shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill);
+                     shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill, force_fail);
   cx.chk();
 }
 
@@ -1863,7 +1864,7 @@ void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double*
 // storage (H is no longer needed at this point).
 const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L);
 
-void chol_qr2(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
+void chol_qr2(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L, int force_fail) {
   const int64_t n = f.n;
   double* Gm = sm.Jm;
   double* Rs = sm.Wm;
@@ -1875,12 +1876,13 @@ void chol_qr2(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
   // diagonal entry (cond(B) up to about 1e4) and the second factor is within 1e-6 of I (Q1 was
   // orthonormal to about 1e-6, so Q2 is to working precision).  R_B goes to sm.RB; the two tests
   // leave nonzero flags at sm.info[1] (a pivot failed) and sm.info[2] (a test failed), which the
-  // caller reads later.
+  // caller reads later.  force_fail (a test hook) makes the first factorisation take its
+  // failed-pivot exit at the first step.
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, fail, 0);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, ill, 0);
   cx.chk();
   gram_upper(cx, f.Bt, f.ldb, n, L, f.red_ws, Gm);
-  chol(cx, Gm, L, 0.0, Racc, Ri, fail, 1e-8, 0.0, ill);
+  chol(cx, Gm, L, 0.0, Racc, Ri, fail, 1e-8, 0.0, ill, force_fail);
   right_trmul(cx, f.Qb, f.ldb, f.Bt, f.ldb, n, L, Ri);
   gram_upper(cx, f.Qb, f.ldb, n, L, f.red_ws, Gm);
   chol(cx, Gm, L, 0.0, Rs, nullptr, fail, 0.0, 1e-6, ill);
@@ -2087,10 +2089,10 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   // acceptance tests are read with the final wait, the SVD and the outputs being formed from its
   // R_B meanwhile; in the rare case it is not accepted, all of it is formed again from shifted
   // Cholesky QR3 (rb_mode 2), or from Gram-Schmidt + TSQR (rb_mode 1) if a pivot of that fails.
-  for (int rb_mode = (f.force_rb == 3) ? 0 : f.force_rb; L > 0;) {
+  for (int rb_mode = (f.force_rb >= 3) ? 0 : f.force_rb; L > 0;) {
     const double* RBp = nullptr;
     if (rb_mode == 0) {
-      chol_qr2(cx, f, sm, L);
+      chol_qr2(cx, f, sm, L, f.force_rb == 4 ? 1 : 0);
       RBp = sm.RB;
     } else if (rb_mode == 2) {
       RBp = chol_qr3_shifted(cx, f, sm, L);

@@ -94,6 +94,12 @@ hipError_t launch_fill_rows(double* p, int64_t rows, int cols, int64_t ld, doubl
 hipError_t launch_copy_state(int mode, const void* G, int64_t ldg, int64_t rows, const double* H,
                              int64_t ldh, int64_t n, int l, double* Gout, double* Hout,
                              hipStream_t s);
+// a(:, 0:cols) += b(:, 0:cols) over `rows` rows (column-major FP64)
+hipError_t launch_add_cols(double* a, int64_t lda, const double* b, int64_t ldb, int64_t rows,
+                           int cols, hipStream_t s);
+// *diff += number of entries whose bit patterns differ (column-major FP64; *diff zeroed by caller)
+hipError_t launch_count_diff(const double* a, int64_t lda, const double* b, int64_t ldb,
+                             int64_t rows, int cols, unsigned* diff, hipStream_t s);
 hipError_t launch_copy_omega_out(const double* om64, int64_t ldo, int64_t n, int l, double* out,
                                  int64_t ld, hipStream_t s);
 
@@ -114,7 +120,8 @@ struct FinalizeArgs {
   double* S; double* U; int64_t ldu; double* V; int64_t ldv;
   int32_t force_loop = 0;            // in: 1 takes the Householder TSQR path of the loop directly
   int32_t force_rb = 0;              // in: 1 Gram-Schmidt + TSQR for R_B, 2 shifted Cholesky QR3,
-                                     //     3 QR2 formed, then treated as not accepted
+                                     //     3 QR2 formed, then treated as not accepted,
+                                     //     4 as 3 with QR2's first pivot failing
   int32_t path_loop = -1;            // out: 0 Cholesky QR of the blocks, 1 Householder TSQR
   int32_t path_rb = -1;              // out: 0 Cholesky QR2 of B^T, 2 shifted Cholesky QR3,
                                      //      1 Gram-Schmidt + TSQR

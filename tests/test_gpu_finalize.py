@@ -7,9 +7,10 @@ tolerance is FP64-level in every compute mode: 1e-10 relative on sigma and 1e-8 
 (round-off amplified at most by (sigma_1 / sigma_l)^2 ~ 2e4 through Eq. 9 on this spectrum).
 
 Ill-conditioned B: on the Type 5 spectrum 10^(-j/10) (Sec. 4.1) with l = 60 or 90, cond(B) is
-about 1e6 or 1e9, so Cholesky QR2 of B^T must be rejected (cond(B B^T) beyond 1e8 of its first
-pivot, or a pivot that is not positive at all for l = 90) and R_B comes from shifted Cholesky QR3.
-The literal single-pass algorithm loses accuracy there on both sides alike (the Eq. 9 numerator
+about 1e6 or 1e9.  Its rows are nearly orthogonal after scaling, so Cholesky QR2 (whose test is on
+pivots relative to their own diagonal entries, a scaling-invariant measure) may accept it; the
+other routes to R_B are forced through the test hook and must give the same triplets.  The
+literal single-pass algorithm loses accuracy there on both sides alike (the Eq. 9 numerator
 cancels entries of size sigma_1^2 down to sigma_l^2), so only the leading triplets are compared,
 at u sigma_1^2 / (sigma_l sigma_j) scaled by 1e4.
 """
@@ -48,21 +49,31 @@ def test_finalize_parity_on_gpu_sketch(gpu_lib, ragged, mode, src):
     assert np.max(np.abs(out["V"] - V)) < 1e-7
 
 
+@pytest.mark.parametrize("rb", [0, 2, 3, 4])
 @pytest.mark.parametrize("l", [60, 90])
-def test_ill_conditioned_b_rejects_qr2(gpu_lib, l):
+def test_ill_conditioned_b(gpu_lib, l, rb):
+    """R_B on a Type 5 spectrum by every route: the normal order (Cholesky QR2 accepted or not by
+    its own tests), shifted QR3 directly (rb 2), QR2 formed then rejected (rb 3), and QR2 whose
+    first factorisation takes its failed-pivot exit (rb 4: identity factors are written, the SVD
+    and outputs are formed from them, then everything is formed again from QR3)."""
     m, n, k, b = 1500, 700, 10, 10
     sig = synth.paper_type_spectrum(5, n)
     A, _, s, V = synth.small_matrix(m, n, sig, 50 + l)
     Om = synth.gaussian_omega(n, l, 60 + l)
     blocks = [700, 700, 100]
-    out = run_gpu(A, Om, k, b, "f64", blocks, src="f64", keep_state=False)
+    out = run_gpu(A, Om, k, b, "f64", blocks, src="f64", keep_state=False, force=(0, rb))
     ref = oracle.single_pass_pca(split_blocks(A, blocks), Om, k, b)
-    assert out["paths"][1] != 0, out["paths"]        # QR2 rejected on its own
+    if rb == 0:
+        assert out["paths"][1] in (0, 2), out["paths"]
+    else:
+        assert out["paths"][1] == 2, out["paths"]
     assert out["rank"] == ref.rank == l
     assert np.all(np.isfinite(out["S"])) and np.all(np.isfinite(out["V"]))
+    assert np.all(np.isfinite(out["U"]))
     tol = 1e4 * U64 * s[0] ** 2 / (s[l - 1] * s[:k])
     assert np.all(oracle.rel_sigma_error(out["S"], ref.S) <= tol)
     assert oracle.sin_theta_max(ref.V[:, :5], out["V"][:, :5]) < 1e-6
+    assert oracle.sin_theta_max(ref.U[:, :5], out["U"][:, :5]) < 1e-6
     # and the same triplets as the exact SVD where the method is accurate
     assert np.max(oracle.rel_sigma_error(out["S"][:5], s[:5])) < 1e-6
 
