@@ -137,6 +137,37 @@ sketch_status sketch_poll(sketch_t h, uint64_t ticket, int32_t* done);
 sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t ldu, double* V_dev,
                               int64_t ldv, int32_t* rank_out);
 
+/* ---------------------------------------------------------------- checkpoint, restore, merge
+ * The pass state after any number of ingested blocks is G (the rows seen so far), H and Omega'
+ * (Alg. 4 steps 3-8).  Eq. 10 makes it mergeable: the state of the rows of A_1 followed by those
+ * of A_2 is G = [G_1; G_2] and H = H_1 + H_2, given the same Omega'.  A checkpoint is a host byte
+ * image of the state: a header, H and G exactly as stored on the device (so a restored pass
+ * continues with the same bits), and Omega' itself only when it was supplied by sketch_set_omega
+ * (a seed-drawn Omega' is drawn again from the seed).  The calls below take any host memory
+ * (pinned or pageable), copy synchronously and return when done. */
+
+/* Bytes of a checkpoint of the handle's current state; 0 (with sketch_last_error set) before
+ * Omega is set, after finalize or in a sticky state. */
+size_t sketch_checkpoint_size(sketch_t h);
+
+/* Writes the current pass state to `buf` (host memory of `bytes` >= sketch_checkpoint_size bytes,
+ * owned by the caller).  Waits for the handle's stream.  E_STATE before Omega is set or after
+ * finalize; E_INVAL for a short buffer; E_NONFINITE if a block held NaN or Inf. */
+sketch_status sketch_checkpoint(sketch_t h, void* buf, size_t bytes);
+
+/* Replaces the handle's state by a checkpoint's (any previous rows are dropped) and leaves it
+ * ingesting: further blocks continue that pass.  The handle must have the checkpoint's n, l and
+ * compute mode (k, b, want_u, host staging and max_block_rows may differ) and m_capacity >= its
+ * rows (else E_CAPACITY); Omega' becomes the checkpoint's.  E_INVAL for a buffer that is not a
+ * checkpoint of this library version or does not fit the handle. */
+sketch_status sketch_restore(sketch_t h, const void* buf, size_t bytes);
+
+/* Adds a checkpointed sketch of further rows to the handle's (Eq. 10): H = H + H', and the
+ * checkpoint's G rows are appended after the rows ingested so far.  The checkpoint must have been
+ * taken with the same Omega' (checked bit for bit; E_INVAL otherwise) and the handle's n, l and
+ * compute mode; E_CAPACITY if the rows would exceed m_capacity; E_STATE after finalize. */
+sketch_status sketch_merge(sketch_t h, const void* buf, size_t bytes);
+
 /* Copies Omega' (n x l, FP64, row-major, leading dimension ld >= l) into device memory. */
 sketch_status sketch_get_omega(sketch_t h, double* omega_dev, int64_t ld);
 
@@ -151,8 +182,10 @@ sketch_status sketch_finalize_paths(sketch_t h, int32_t* loop_path, int32_t* rb_
 /* Test hook for the next sketch_finalize: loop_householder nonzero takes TSQR for every column
  * block without trying Cholesky QR; rb_mode 1 takes Gram-Schmidt + TSQR for R_B, 2 shifted Cholesky
  * QR3 directly, 3 forms Cholesky QR2 and the results from it, then treats it as not accepted (so
- * they are formed again from shifted Cholesky QR3, as for a rejected QR2), 0 the normal order.
- * All paths compute the same factorisation.  E_INVAL for another rb_mode. */
+ * they are formed again from shifted Cholesky QR3, as for a rejected QR2), 4 as 3 but with QR2's
+ * first Cholesky factorisation taking its failed-pivot exit (a non-positive pivot, simulated from
+ * the host), 0 the normal order.  All paths compute the same factorisation.  E_INVAL for another
+ * rb_mode. */
 sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_mode);
 
 /* Copies the pass state as FP64 into device memory: G (rows x l, row-major, ld = l) and

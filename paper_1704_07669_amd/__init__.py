@@ -24,7 +24,8 @@ EXPORTED = [
     "sketch_workspace_size", "sketch_init", "sketch_reset", "sketch_set_omega",
     "sketch_ingest_block", "sketch_poll", "sketch_finalize", "sketch_finalize_paths",
     "sketch_debug_force_paths",
-    "sketch_get_omega",
+    "sketch_get_omega", "sketch_checkpoint_size", "sketch_checkpoint", "sketch_restore",
+    "sketch_merge",
     "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
     "sketch_destroy", "sketch_last_error",
     "sketch_server_workspace_size", "sketch_server_stream_bytes", "sketch_server_create",
@@ -94,6 +95,10 @@ def load_library(path=None):
         "sketch_finalize_paths": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "sketch_debug_force_paths": (I32, [P, I32, I32]),
         "sketch_get_omega": (I32, [P, P, I64]),
+        "sketch_checkpoint_size": (ctypes.c_size_t, [P]),
+        "sketch_checkpoint": (I32, [P, P, ctypes.c_size_t]),
+        "sketch_restore": (I32, [P, P, ctypes.c_size_t]),
+        "sketch_merge": (I32, [P, P, ctypes.c_size_t]),
         "sketch_debug_state": (I32, [P, P, P, ctypes.POINTER(I64)]),
         "sketch_philox_words": (I32, [U64, U64, I64, P, P]),
         "sketch_profile_enable": (I32, [P, I32]),
@@ -190,6 +195,28 @@ def sketch_finalize_paths(h):
 
 def sketch_debug_force_paths(h, loop_householder, rb_mode):
     _check(load_library().sketch_debug_force_paths(h, int(loop_householder), int(rb_mode)))
+
+
+def sketch_checkpoint_size(h):
+    n = load_library().sketch_checkpoint_size(h)
+    if n == 0:
+        raise SketchError(-1, _lib.sketch_last_error().decode())
+    return n
+
+
+def sketch_checkpoint(h, buf):
+    """Writes the pass state into `buf` (a writable numpy uint8 array)."""
+    _check(load_library().sketch_checkpoint(h, buf.ctypes.data, buf.nbytes))
+
+
+def sketch_restore(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(load_library().sketch_restore(h, buf.ctypes.data, buf.nbytes))
+
+
+def sketch_merge(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(load_library().sketch_merge(h, buf.ctypes.data, buf.nbytes))
 
 
 def sketch_get_omega(h, out):
@@ -307,6 +334,18 @@ class Sketch:
 
     def reset(self, seed=None):
         sketch_reset(self.h, self.cfg.seed if seed is None else seed)
+
+    def checkpoint(self):
+        """The pass state as a host byte image (numpy uint8)."""
+        buf = np.empty(sketch_checkpoint_size(self.h), dtype=np.uint8)
+        sketch_checkpoint(self.h, buf)
+        return buf
+
+    def restore(self, buf):
+        sketch_restore(self.h, buf)
+
+    def merge(self, buf):
+        sketch_merge(self.h, buf)
 
     def profile(self, on=True):
         sketch_profile_enable(self.h, on)

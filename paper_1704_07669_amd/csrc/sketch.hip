@@ -552,7 +552,7 @@ sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t 
 
 sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_mode) {
   if (sketch_status st = check_handle(h)) return st;
-  if (rb_mode < 0 || rb_mode > 3) return fail(SKETCH_E_INVAL, "rb mode must be 0, 1, 2 or 3");
+  if (rb_mode < 0 || rb_mode > 4) return fail(SKETCH_E_INVAL, "rb mode must be 0 .. 4");
   h->force_loop = loop_householder ? 1 : 0;
   h->force_rb = rb_mode;
   return SKETCH_OK;
@@ -586,6 +586,210 @@ sketch_status sketch_debug_state(sketch_t h, double* G_dev, double* H_dev, int64
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return h->dev_fail(e, "debug state");
   if (rows_out) *rows_out = h->rows;
+  return SKETCH_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint, restore, merge
+}  // extern "C"
+
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x314b43414350534bull;   // "KSPCACK1" little-endian
+constexpr uint32_t kCkptVersion = 1;
+
+// Layout of a checkpoint in host memory: this header, then H (hcols columns of n FP64 values),
+// then G (l columns of `rows` values of g_bytes each), then Omega' (l columns of n FP64 values)
+// when it was supplied rather than drawn from the seed.  Every section starts 64-byte aligned.
+struct CkptHeader {
+  uint64_t magic;
+  uint32_t version, header_bytes;
+  int64_t n, rows;
+  int32_t l, compute, omega_from_seed, g_bytes;
+  int32_t hcols, pad0;
+  uint64_t seed;
+  int64_t off_H, off_G, off_om, total;
+  int64_t pad1[4];
+};
+
+CkptHeader ckpt_header(const sketch_s* h) {
+  CkptHeader c;
+  memset(&c, 0, sizeof(c));
+  c.magic = kCkptMagic;
+  c.version = kCkptVersion;
+  c.header_bytes = sizeof(CkptHeader);
+  c.n = h->cfg.n;
+  c.rows = h->rows;
+  c.l = h->cfg.l;
+  c.compute = h->cfg.compute;
+  c.omega_from_seed = h->cfg.omega_from_seed;
+  c.g_bytes = (h->cfg.compute == SKETCH_F64) ? 8 : 4;
+  c.hcols = h->cfg.l;
+  c.seed = h->cfg.seed;
+  int64_t off = rup<int64_t>(sizeof(CkptHeader), 64);
+  c.off_H = off;
+  off += rup<int64_t>((int64_t)c.hcols * c.n * 8, 64);
+  c.off_G = off;
+  off += rup<int64_t>((int64_t)c.l * c.rows * c.g_bytes, 64);
+  c.off_om = c.omega_from_seed ? 0 : off;
+  if (!c.omega_from_seed) off += rup<int64_t>((int64_t)c.l * c.n * 8, 64);
+  c.total = off;
+  return c;
+}
+
+// Checks a checkpoint against the handle it is read into; returns the header through *out.
+sketch_status ckpt_check(sketch_t h, const void* buf, size_t bytes, CkptHeader* out) {
+  if (!buf) return fail(SKETCH_E_INVAL, "checkpoint buffer is NULL");
+  if (bytes < sizeof(CkptHeader)) return fail(SKETCH_E_INVAL, "checkpoint buffer too small");
+  CkptHeader c;
+  memcpy(&c, buf, sizeof(c));
+  if (c.magic != kCkptMagic || c.version != kCkptVersion || c.header_bytes != sizeof(CkptHeader))
+    return fail(SKETCH_E_INVAL, "not a checkpoint of this library version");
+  if (c.n != h->cfg.n || c.l != h->cfg.l || c.compute != h->cfg.compute)
+    return fail(SKETCH_E_INVAL, "checkpoint of n=%lld l=%d compute=%d does not fit this handle",
+                (long long)c.n, c.l, c.compute);
+  if (c.rows < 0 || c.hcols != c.l || c.g_bytes != ((c.compute == SKETCH_F64) ? 8 : 4))
+    return fail(SKETCH_E_INVAL, "corrupt checkpoint header");
+  // recompute the section offsets from the header's own sizes
+  sketch_s tmp;
+  tmp.cfg = h->cfg;
+  tmp.cfg.omega_from_seed = c.omega_from_seed;
+  tmp.cfg.seed = c.seed;
+  tmp.rows = c.rows;
+  const CkptHeader e = ckpt_header(&tmp);
+  if (e.off_H != c.off_H || e.off_G != c.off_G || e.off_om != c.off_om || e.total != c.total)
+    return fail(SKETCH_E_INVAL, "corrupt checkpoint header");
+  if ((int64_t)bytes < c.total) return fail(SKETCH_E_INVAL, "checkpoint truncated");
+  *out = c;
+  return SKETCH_OK;
+}
+
+// Writes the checkpoint's Omega' (FP64, column-major, ld NP) to `dst` on the handle's stream; a
+// seed-drawn one is drawn and rounded again, its operand copy going to `omc_dst`.  A supplied one
+// is stored already rounded and is copied as it is.
+hipError_t ckpt_omega(sketch_t h, const CkptHeader& c, const uint8_t* buf, double* dst,
+                      void* omc_dst) {
+  const Layout& L = h->lay;
+  hipError_t e = launch_fill_f64(dst, (int64_t)L.LP * L.NP, 0.0, h->stream);
+  if (e != hipSuccess) return e;
+  if (c.omega_from_seed) {
+    e = launch_omega_philox(c.seed, c.n, c.l, dst, L.NP, h->stream);
+    if (e == hipSuccess)
+      e = launch_omega_quantize(h->cfg.compute, c.n, L.NP, c.l, L.LP, dst, omc_dst, h->stream);
+    return e;
+  }
+  return hipMemcpy2DAsync(dst, L.NP * 8, buf + c.off_om, c.n * 8, c.n * 8, c.l,
+                          hipMemcpyHostToDevice, h->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sketch_checkpoint_size(sketch_t h) {
+  if (check_handle(h) != SKETCH_OK) return 0;
+  if (h->phase != 1) {
+    fail(SKETCH_E_STATE, "no pass state to checkpoint");
+    return 0;
+  }
+  return (size_t)ckpt_header(h).total;
+}
+
+sketch_status sketch_checkpoint(sketch_t h, void* buf, size_t bytes) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (h->phase != 1) return fail(SKETCH_E_STATE, "no pass state to checkpoint");
+  if (!buf) return fail(SKETCH_E_INVAL, "checkpoint buffer is NULL");
+  const CkptHeader c = ckpt_header(h);
+  if ((int64_t)bytes < c.total)
+    return fail(SKETCH_E_INVAL, "checkpoint needs %lld bytes", (long long)c.total);
+  const Layout& L = h->lay;
+  uint8_t* out = (uint8_t*)buf;
+  memcpy(out, &c, sizeof(c));
+  hipError_t e = hipMemcpy2DAsync(out + c.off_H, c.n * 8, h->at<double>(L.off_H), L.NP * 8,
+                                  c.n * 8, c.hcols, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && c.rows > 0)
+    e = hipMemcpy2DAsync(out + c.off_G, c.rows * c.g_bytes, h->ws + L.off_G, L.MCAP * c.g_bytes,
+                         c.rows * c.g_bytes, c.l, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && !c.omega_from_seed)
+    e = hipMemcpy2DAsync(out + c.off_om, c.n * 8, h->at<double>(L.off_om64), L.NP * 8, c.n * 8,
+                         c.l, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "checkpoint");
+  // a block the kernels found non-finite must not be saved as a valid state
+  if (*reinterpret_cast<volatile int*>(h->nf_host) != 0) {
+    h->sticky = SKETCH_E_NONFINITE;
+    return fail(SKETCH_E_NONFINITE, "an ingested block held NaN or Inf");
+  }
+  return SKETCH_OK;
+}
+
+sketch_status sketch_restore(sketch_t h, const void* buf, size_t bytes) {
+  if (sketch_status st = check_handle(h)) return st;
+  CkptHeader c;
+  if (sketch_status st = ckpt_check(h, buf, bytes, &c)) return st;
+  if (c.rows > h->cfg.m_capacity)
+    return fail(SKETCH_E_CAPACITY, "checkpoint holds %lld rows, m_capacity is %lld",
+                (long long)c.rows, (long long)h->cfg.m_capacity);
+  const Layout& L = h->lay;
+  const uint8_t* in = (const uint8_t*)buf;
+  // a fresh pass (H = 0, counters and flags cleared), then the checkpoint's state over it
+  const int saved_seed_flag = h->cfg.omega_from_seed;
+  h->cfg.omega_from_seed = 0;            // start_pass must not draw an Omega of its own
+  sketch_status st = start_pass(h);
+  h->cfg.omega_from_seed = saved_seed_flag;
+  if (st != SKETCH_OK) return st;
+  hipError_t e = ckpt_omega(h, c, in, h->at<double>(L.off_om64), h->ws + L.off_omc);
+  if (e == hipSuccess && !c.omega_from_seed)
+    e = launch_omega_quantize(h->cfg.compute, c.n, L.NP, c.l, L.LP, h->at<double>(L.off_om64),
+                              h->ws + L.off_omc, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(h->at<double>(L.off_H), L.NP * 8, in + c.off_H, c.n * 8, c.n * 8, c.hcols,
+                         hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess && c.rows > 0)
+    e = hipMemcpy2DAsync(h->ws + L.off_G, L.MCAP * c.g_bytes, in + c.off_G, c.rows * c.g_bytes,
+                         c.rows * c.g_bytes, c.l, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "restore");
+  h->cfg.seed = c.seed;
+  h->rows = c.rows;
+  h->phase = 1;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_merge(sketch_t h, const void* buf, size_t bytes) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (h->phase != 1) return fail(SKETCH_E_STATE, "merge needs a handle that is ingesting");
+  CkptHeader c;
+  if (sketch_status st = ckpt_check(h, buf, bytes, &c)) return st;
+  if (h->rows + c.rows > h->cfg.m_capacity)
+    return fail(SKETCH_E_CAPACITY, "merged rows exceed m_capacity %lld",
+                (long long)h->cfg.m_capacity);
+  const Layout& L = h->lay;
+  const uint8_t* in = (const uint8_t*)buf;
+  double* tmp = h->at<double>(L.off_Bt);             // n-side scratch of the finalize
+  unsigned* diff = reinterpret_cast<unsigned*>(h->ws + L.off_fp8 + 32);
+  unsigned ndiff = 0;
+  // the two sketches must come from the same Omega' (Eq. 10 sums A_i^T A_i Omega)
+  hipError_t e = launch_fill_u32(diff, 1, 0u, h->stream);
+  if (e == hipSuccess) e = ckpt_omega(h, c, in, tmp, h->ws + L.off_Qb);
+  if (e == hipSuccess)
+    e = launch_count_diff(tmp, L.NP, h->at<double>(L.off_om64), L.NP, c.n, c.l, diff, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&ndiff, diff, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "merge");
+  if (ndiff != 0) return fail(SKETCH_E_INVAL, "checkpoint was taken with a different Omega");
+  // H = H + H', G = [G; G']
+  e = hipMemcpy2DAsync(tmp, L.NP * 8, in + c.off_H, c.n * 8, c.n * 8, c.hcols,
+                       hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = launch_add_cols(h->at<double>(L.off_H), L.NP, tmp, L.NP, c.n, c.hcols, h->stream);
+  if (e == hipSuccess && c.rows > 0)
+    e = hipMemcpy2DAsync(h->ws + L.off_G + h->rows * c.g_bytes, L.MCAP * c.g_bytes, in + c.off_G,
+                         c.rows * c.g_bytes, c.rows * c.g_bytes, c.l, hipMemcpyHostToDevice,
+                         h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "merge");
+  h->rows += c.rows;
   return SKETCH_OK;
 }
 

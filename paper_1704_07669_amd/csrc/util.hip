@@ -50,6 +50,29 @@ __global__ void k_fill_rows(double* __restrict__ p, int64_t rows, int cols, int6
   }
 }
 
+// a[c * lda + r] += b[c * ldb + r] for r < rows, c < cols (column-major FP64)
+__global__ void k_add_cols(double* __restrict__ a, int64_t lda, const double* __restrict__ b,
+                           int64_t ldb, int64_t rows, int cols) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < rows * cols;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = q / rows, r = q - c * rows;
+    a[c * lda + r] += b[c * ldb + r];
+  }
+}
+
+// *diff = number of (r, c) with the bit patterns of a and b differing (column-major FP64)
+__global__ void k_count_diff(const double* __restrict__ a, int64_t lda,
+                             const double* __restrict__ b, int64_t ldb, int64_t rows, int cols,
+                             unsigned* __restrict__ diff) {
+  unsigned d = 0;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < rows * cols;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = q / rows, r = q - c * rows;
+    d += (__double_as_longlong(a[c * lda + r]) != __double_as_longlong(b[c * ldb + r])) ? 1u : 0u;
+  }
+  if (d) atomicAdd(diff, d);
+}
+
 inline int grid_for(int64_t work) {
   int64_t g = cdiv<int64_t>(work, 256);
   return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
@@ -94,6 +117,22 @@ hipError_t launch_copy_omega_out(const double* om64, int64_t ldo, int64_t n, int
                                  int64_t ld, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_omega, dim3(grid_for(n * l)), dim3(256), 0, s, om64, ldo, n, l, out,
                      ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_cols(double* a, int64_t lda, const double* b, int64_t ldb, int64_t rows,
+                           int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_cols, dim3(grid_for(rows * cols)), dim3(256), 0, s, a, lda, b, ldb, rows,
+                     cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_diff(const double* a, int64_t lda, const double* b, int64_t ldb,
+                             int64_t rows, int cols, unsigned* diff, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_diff, dim3(grid_for(rows * cols)), dim3(256), 0, s, a, lda, b, ldb,
+                     rows, cols, diff);
   return hipGetLastError();
 }
 
