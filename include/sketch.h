@@ -212,6 +212,28 @@ sketch_status sketch_destroy(sketch_t h);
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* sketch_last_error(void);
 
+/* ================================================================ one call, no allocation
+ * For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the whole of Algorithm 4 on a device-resident A in one call, with the
+ * workspace taken from a fixed device array inside the library (64 MiB on each GPU, held until
+ * the process ends) instead of caller memory.  The call creates no stream, event or host
+ * allocation and calls no hipMalloc/hipFree.
+ *
+ * Equivalent to sketch_init(cfg) + sketch_ingest_block of consecutive blocks of
+ * cfg->max_block_rows rows (the last one shorter) + sketch_finalize, with the same kernels and
+ * bits.  cfg: as for sketch_init with host_slots = 0, omega_from_seed = 1 and m <= m_capacity;
+ * sketch_workspace_size(cfg) must not exceed 64 MiB (else E_CAPACITY, with the size in the
+ * message).  A_dev: device pointer, m x n row-major, leading dimension lda >= n, format src_dtype
+ * (F64, F32 or BF16 as the compute mode accepts).  Outputs as sketch_finalize (S_dev, V_dev
+ * required; U_dev optional, requires want_u).  Runs on hip_stream and waits for it.
+ * All calls on one GPU share its array, which keeps the last call's contents (each call clears
+ * what it reads before writing): calls that overlap on the same GPU race and must be serialised
+ * by the caller.  A NaN or Inf in A returns E_NONFINITE; E_DEVICE on a HIP error. */
+sketch_status sketch_pca_static(const sketch_config* cfg, const void* A_dev, int32_t src_dtype,
+                                int64_t m, int64_t lda, double* S_dev, double* U_dev,
+                                int64_t ldu, double* V_dev, int64_t ldv, int32_t* rank_out,
+                                void* hip_stream);
+
 /* ================================================================ serving
  * Many concurrent single-pass PCA streams on one GPU.  Each stream is one instance of Algorithm 4
  * (its Omega seed, G, H resident in device memory); the server admits streams while their state

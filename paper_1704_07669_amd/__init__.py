@@ -25,7 +25,7 @@ EXPORTED = [
     "sketch_ingest_block", "sketch_poll", "sketch_finalize", "sketch_finalize_paths",
     "sketch_debug_force_paths",
     "sketch_get_omega", "sketch_checkpoint_size", "sketch_checkpoint", "sketch_restore",
-    "sketch_merge",
+    "sketch_merge", "sketch_pca_static",
     "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
     "sketch_destroy", "sketch_last_error",
     "sketch_server_workspace_size", "sketch_server_stream_bytes", "sketch_server_create",
@@ -99,6 +99,8 @@ def load_library(path=None):
         "sketch_checkpoint": (I32, [P, P, ctypes.c_size_t]),
         "sketch_restore": (I32, [P, P, ctypes.c_size_t]),
         "sketch_merge": (I32, [P, P, ctypes.c_size_t]),
+        "sketch_pca_static": (I32, [cfgp, P, I32, I64, I64, P, P, I64, P, I64,
+                                    ctypes.POINTER(I32), P]),
         "sketch_debug_state": (I32, [P, P, P, ctypes.POINTER(I64)]),
         "sketch_philox_words": (I32, [U64, U64, I64, P, P]),
         "sketch_profile_enable": (I32, [P, I32]),
@@ -217,6 +219,19 @@ def sketch_restore(h, buf):
 def sketch_merge(h, buf):
     buf = np.ascontiguousarray(buf, dtype=np.uint8)
     _check(load_library().sketch_merge(h, buf.ctypes.data, buf.nbytes))
+
+
+def sketch_pca_static(cfg, A, S, U, V, stream=None):
+    """One call of the whole method on a device matrix A (torch CUDA tensor, row-major), with the
+    library's fixed device scratch as workspace; returns the rank."""
+    import torch
+    src = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[A.dtype]
+    rank = ctypes.c_int32()
+    _check(load_library().sketch_pca_static(
+        ctypes.byref(cfg), _ptr(A), src, A.shape[0], A.stride(0), _ptr(S),
+        _ptr(U) if U is not None else None, U.stride(0) if U is not None else 0, _ptr(V),
+        V.stride(0), ctypes.byref(rank), _stream_handle(stream)))
+    return rank.value
 
 
 def sketch_get_omega(h, out):

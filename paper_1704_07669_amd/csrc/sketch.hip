@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -237,6 +238,137 @@ sketch_status start_pass(sketch_t h) {
   return SKETCH_OK;
 }
 
+// Enqueues the pass kernels of one block (Alg. 4 steps 6-7) of device rows A (lda elements,
+// format src_dtype) at row h->rows of G; with `rec`, HIP events around the two products.
+hipError_t enqueue_pass(sketch_t h, const void* A, int64_t lda, int src_dtype, int64_t nrows,
+                        sketch_s::Rec* rec) {
+  const sketch_config& c = h->cfg;
+  const Layout& L = h->lay;
+  hipError_t e = hipSuccess;
+  PassItem it{};
+  it.A = A;
+  it.lda = lda;
+  it.nrows = (int)nrows;
+  it.n = c.n;
+  it.omc = h->ws + L.off_omc;
+  it.NP = L.NP;
+  it.P1 = h->ws + L.off_P1;
+  it.ldp = L.RBP;
+  it.Gop = h->ws + L.off_Gop;
+  it.P2 = h->ws + L.off_P2;
+  it.counters = h->at<unsigned>(L.off_cnt);
+  it.G = h->ws + L.off_G;
+  it.ldg = L.MCAP;
+  it.g_row0 = h->rows;
+  it.H = h->at<double>(L.off_H);
+  it.ldh = L.NP;
+  it.fp8_exp = nullptr;
+  it.ctrl = h->ctrl();
+  it.nf_host = h->nf_dev;
+  int src = src_dtype;
+  if (c.compute == SKETCH_FP8_E4M3) {
+    uint32_t* amax = h->at<uint32_t>(L.off_fp8);
+    int* ex = reinterpret_cast<int*>(amax + 4);
+    uint8_t* q = h->ws + L.off_fp8q;
+    e = launch_fp8_quantize((const float*)A, lda, (int)nrows, c.n, amax, q, L.NQ, ex,
+                            &h->ctrl()->nonfinite, h->nf_dev, h->stream);
+    if (e != hipSuccess) return e;
+    it.A = q;
+    it.lda = L.NQ;
+    src = SKETCH_FP8_E4M3;
+    it.fp8_exp = ex;
+  }
+  plan_item(it, c.compute, src, L.splits_max);
+  PassGroup a{};
+  a.mode = c.compute;
+  a.src = src;
+  a.LP = L.LP;
+  a.NT = L.NT;
+  plan_group(a, &it, 1);
+
+  if (rec) {
+    rec->a = h->take_event(); rec->b = h->take_event(); rec->c = h->take_event(); rec->kind = 0;
+    if (!rec->a || !rec->b || !rec->c) return hipErrorOutOfMemory;
+    e = hipEventRecord(rec->a, h->stream);
+  }
+  if (e == hipSuccess) e = launch_gemm1(a, h->stream);
+  if (e == hipSuccess) e = launch_reduce1(a, h->stream);
+  if (e == hipSuccess && rec) e = hipEventRecord(rec->b, h->stream);
+  if (e == hipSuccess) e = launch_gemm2(a, h->stream);
+  if (e == hipSuccess && rec) e = hipEventRecord(rec->c, h->stream);
+  return e;
+}
+
+// Alg. 4 steps 9-19 for a validated handle in the ingesting state; waits for the stream.
+sketch_status finalize_core(sketch_t h, double* S_dev, double* U_dev, int64_t ldu, double* V_dev,
+                            int64_t ldv, int32_t* rank_out) {
+  const sketch_config& c = h->cfg;
+  const Layout& L = h->lay;
+  hipError_t e = hipSuccess;
+  hipEvent_t fa = nullptr, fb = nullptr;
+  if (h->prof) {
+    fa = h->take_event(); fb = h->take_event();
+    e = hipEventRecord(fa, h->stream);
+  }
+  if (h->rows == 0) {
+    if (e == hipSuccess) e = launch_fill_f64(S_dev, c.k, 0.0, h->stream);
+    if (e == hipSuccess) e = launch_fill_rows(V_dev, c.n, c.k, ldv, 0.0, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->dev_fail(e, "finalize");
+    if (rank_out) *rank_out = 0;
+    h->phase = 2;
+    return SKETCH_OK;
+  }
+  FinalizeArgs f{};
+  f.mode = c.compute;
+  f.m = h->rows;
+  f.n = c.n;
+  f.k = c.k;
+  f.l = c.l;
+  f.b = c.b;
+  f.LP = L.LP;
+  f.G = h->ws + L.off_G;
+  f.ldg = L.MCAP;
+  f.H = h->at<double>(L.off_H);
+  f.ldh = L.NP;
+  f.om64 = h->at<double>(L.off_om64);
+  f.ldo = L.NP;
+  f.Q = h->at<double>(L.off_Q);
+  f.ldq = L.MCAP;
+  f.Bt = h->at<double>(L.off_Bt);
+  f.Qb = h->at<double>(L.off_Qb);
+  f.ldb = L.NP;
+  f.tsqr_ws = h->at<double>(L.off_tsqr);
+  f.tsqr_ws_elems = L.tsqr_elems;
+  f.red_ws = h->at<double>(L.off_red);
+  f.red_ws_elems = L.red_elems;
+  f.small = h->at<double>(L.off_small);
+  f.ctrl = h->ctrl();
+  f.S = S_dev;
+  f.U = U_dev;
+  f.ldu = ldu;
+  f.V = V_dev;
+  f.ldv = ldv;
+  f.force_loop = h->force_loop;
+  f.force_rb = h->force_rb;
+  if (e == hipSuccess) e = run_finalize(f, h->stream);
+  if (e == hipSuccess && h->prof) e = hipEventRecord(fb, h->stream);
+  Ctrl hc;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hc, h->ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "finalize");
+  if (h->prof) h->recs.push_back({fa, fb, nullptr, 2});
+  h->phase = 2;
+  h->path_loop = f.path_loop;
+  h->path_rb = f.path_rb;
+  if (hc.nonfinite) {
+    h->sticky = SKETCH_E_NONFINITE;
+    return fail(SKETCH_E_NONFINITE, "an ingested block held NaN or Inf");
+  }
+  if (rank_out) *rank_out = hc.l_eff;
+  return SKETCH_OK;
+}
+
 bool is_pinned_host(const void* p) {
   hipPointerAttribute_t at;
   memset(&at, 0, sizeof(at));
@@ -392,58 +524,9 @@ sketch_status sketch_ingest_block(sketch_t h, const void* rows, int32_t src_dtyp
     A = dst;
   }
 
-  PassItem it{};
-  it.A = A;
-  it.lda = lda;
-  it.nrows = (int)nrows;
-  it.n = c.n;
-  it.omc = h->ws + L.off_omc;
-  it.NP = L.NP;
-  it.P1 = h->ws + L.off_P1;
-  it.ldp = L.RBP;
-  it.Gop = h->ws + L.off_Gop;
-  it.P2 = h->ws + L.off_P2;
-  it.counters = h->at<unsigned>(L.off_cnt);
-  it.G = h->ws + L.off_G;
-  it.ldg = L.MCAP;
-  it.g_row0 = h->rows;
-  it.H = h->at<double>(L.off_H);
-  it.ldh = L.NP;
-  it.fp8_exp = nullptr;
-  it.ctrl = h->ctrl();
-  it.nf_host = h->nf_dev;
-  int src = src_dtype;
-  if (c.compute == SKETCH_FP8_E4M3) {
-    uint32_t* amax = h->at<uint32_t>(L.off_fp8);
-    int* ex = reinterpret_cast<int*>(amax + 4);
-    uint8_t* q = h->ws + L.off_fp8q;
-    e = launch_fp8_quantize((const float*)A, lda, (int)nrows, c.n, amax, q, L.NQ, ex,
-                            &h->ctrl()->nonfinite, h->nf_dev, h->stream);
-    if (e != hipSuccess) return h->dev_fail(e, "fp8 quantize");
-    it.A = q;
-    it.lda = L.NQ;
-    src = SKETCH_FP8_E4M3;
-    it.fp8_exp = ex;
-  }
-  plan_item(it, c.compute, src, L.splits_max);
-  PassGroup a{};
-  a.mode = c.compute;
-  a.src = src;
-  a.LP = L.LP;
-  a.NT = L.NT;
-  plan_group(a, &it, 1);
-
   sketch_s::Rec rec{};
-  if (h->prof) {
-    rec.a = h->take_event(); rec.b = h->take_event(); rec.c = h->take_event(); rec.kind = 0;
-    if (!rec.a || !rec.b || !rec.c) return h->dev_fail(hipErrorOutOfMemory, "profiling events");
-    e = hipEventRecord(rec.a, h->stream);
-  }
-  if (e == hipSuccess) e = launch_gemm1(a, h->stream);
-  if (e == hipSuccess) e = launch_reduce1(a, h->stream);
-  if (e == hipSuccess && h->prof) e = hipEventRecord(rec.b, h->stream);
-  if (e == hipSuccess) e = launch_gemm2(a, h->stream);
-  if (e == hipSuccess && h->prof) e = hipEventRecord(rec.c, h->stream);
+  if (e == hipSuccess) e = enqueue_pass(h, A, lda, src_dtype, nrows, h->prof ? &rec : nullptr);
+  if (e == hipErrorOutOfMemory) return h->dev_fail(e, "profiling events");
   if (e == hipSuccess) e = hipEventRecord(h->done_ev[ring], h->stream);
   if (e == hipSuccess && slot >= 0) {
     e = hipEventRecord(h->slot_consumed[slot], h->stream);
@@ -479,75 +562,12 @@ sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t 
                               double* V_dev, int64_t ldv, int32_t* rank_out) {
   if (sketch_status st = check_handle(h)) return st;
   const sketch_config& c = h->cfg;
-  const Layout& L = h->lay;
   if (h->phase != 1) return fail(SKETCH_E_STATE, h->phase == 2 ? "already finalized" : "Omega has not been supplied");
   if (!S_dev || !V_dev) return fail(SKETCH_E_INVAL, "S and V are required");
   if (ldv < c.k) return fail(SKETCH_E_INVAL, "ldv must be >= k");
   if (U_dev && !c.want_u) return fail(SKETCH_E_INVAL, "U requested but want_u = 0");
   if (U_dev && ldu < c.k) return fail(SKETCH_E_INVAL, "ldu must be >= k");
-  hipError_t e = hipSuccess;
-  hipEvent_t fa = nullptr, fb = nullptr;
-  if (h->prof) {
-    fa = h->take_event(); fb = h->take_event();
-    e = hipEventRecord(fa, h->stream);
-  }
-  if (h->rows == 0) {
-    if (e == hipSuccess) e = launch_fill_f64(S_dev, c.k, 0.0, h->stream);
-    if (e == hipSuccess) e = launch_fill_rows(V_dev, c.n, c.k, ldv, 0.0, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return h->dev_fail(e, "finalize");
-    if (rank_out) *rank_out = 0;
-    h->phase = 2;
-    return SKETCH_OK;
-  }
-  FinalizeArgs f{};
-  f.mode = c.compute;
-  f.m = h->rows;
-  f.n = c.n;
-  f.k = c.k;
-  f.l = c.l;
-  f.b = c.b;
-  f.LP = L.LP;
-  f.G = h->ws + L.off_G;
-  f.ldg = L.MCAP;
-  f.H = h->at<double>(L.off_H);
-  f.ldh = L.NP;
-  f.om64 = h->at<double>(L.off_om64);
-  f.ldo = L.NP;
-  f.Q = h->at<double>(L.off_Q);
-  f.ldq = L.MCAP;
-  f.Bt = h->at<double>(L.off_Bt);
-  f.Qb = h->at<double>(L.off_Qb);
-  f.ldb = L.NP;
-  f.tsqr_ws = h->at<double>(L.off_tsqr);
-  f.tsqr_ws_elems = L.tsqr_elems;
-  f.red_ws = h->at<double>(L.off_red);
-  f.red_ws_elems = L.red_elems;
-  f.small = h->at<double>(L.off_small);
-  f.ctrl = h->ctrl();
-  f.S = S_dev;
-  f.U = U_dev;
-  f.ldu = ldu;
-  f.V = V_dev;
-  f.ldv = ldv;
-  f.force_loop = h->force_loop;
-  f.force_rb = h->force_rb;
-  if (e == hipSuccess) e = run_finalize(f, h->stream);
-  if (e == hipSuccess && h->prof) e = hipEventRecord(fb, h->stream);
-  Ctrl hc;
-  if (e == hipSuccess) e = hipMemcpyAsync(&hc, h->ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return h->dev_fail(e, "finalize");
-  if (h->prof) h->recs.push_back({fa, fb, nullptr, 2});
-  h->phase = 2;
-  h->path_loop = f.path_loop;
-  h->path_rb = f.path_rb;
-  if (hc.nonfinite) {
-    h->sticky = SKETCH_E_NONFINITE;
-    return fail(SKETCH_E_NONFINITE, "an ingested block held NaN or Inf");
-  }
-  if (rank_out) *rank_out = hc.l_eff;
-  return SKETCH_OK;
+  return finalize_core(h, S_dev, U_dev, ldu, V_dev, ldv, rank_out);
 }
 
 sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_mode) {
@@ -856,3 +876,103 @@ sketch_status sketch_destroy(sketch_t h) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- single call, no allocation
+// The workspace of sketch_pca_static lives in this file-scope device array instead of caller
+// memory.  In host code `scratch` only names the symbol: its device address (one per GPU, each
+// GPU holding its own copy) comes from hipGetSymbolAddress, taken once per device with that
+// device current and kept in g_scratch_dev.
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t static_scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+bool is_device_memory(const void* p) {
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof(at));
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
+}  // namespace
+
+extern "C" {
+
+sketch_status sketch_pca_static(const sketch_config* cfg, const void* A_dev, int32_t src_dtype,
+                                int64_t m, int64_t lda, double* S_dev, double* U_dev,
+                                int64_t ldu, double* V_dev, int64_t ldv, int32_t* rank_out,
+                                void* hip_stream) {
+  if (const char* why = validate(cfg)) return fail(SKETCH_E_INVAL, "%s", why);
+  if (cfg->host_slots != 0) return fail(SKETCH_E_INVAL, "host_slots must be 0 (device rows only)");
+  if (!cfg->omega_from_seed) return fail(SKETCH_E_INVAL, "omega_from_seed must be 1");
+  if (!A_dev || !S_dev || !V_dev) return fail(SKETCH_E_INVAL, "A, S and V are required");
+  if (m < 1) return fail(SKETCH_E_INVAL, "m must be >= 1");
+  if (m > cfg->m_capacity)
+    return fail(SKETCH_E_CAPACITY, "m = %lld exceeds m_capacity %lld", (long long)m,
+                (long long)cfg->m_capacity);
+  if (lda < cfg->n) return fail(SKETCH_E_INVAL, "lda must be >= n");
+  if (ldv < cfg->k) return fail(SKETCH_E_INVAL, "ldv must be >= k");
+  if (U_dev && (!cfg->want_u || ldu < cfg->k))
+    return fail(SKETCH_E_INVAL, "U needs want_u = 1 and ldu >= k");
+  if (!mode_accepts(cfg->compute, src_dtype))
+    return fail(SKETCH_E_INVAL, "source format %d not supported by compute mode %d", src_dtype,
+                cfg->compute);
+  if (!is_device_memory(A_dev)) return fail(SKETCH_E_INVAL, "A must be device memory");
+  const Layout L = plan(cfg);
+  if ((size_t)L.total > kStaticScratchBytes)
+    return fail(SKETCH_E_CAPACITY,
+                "this configuration needs %lld bytes of workspace; the static scratch holds %zu",
+                (long long)L.total, kStaticScratchBytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(SKETCH_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SKETCH_E_DEVICE, "device %d out of range", dev);
+  void* ws = nullptr;
+  e = static_scratch_address(dev, &ws);
+  if (e != hipSuccess)
+    return fail(SKETCH_E_DEVICE, "static scratch address: %s", hipGetErrorString(e));
+  e = finalize_prepare();
+  if (e != hipSuccess) return fail(SKETCH_E_DEVICE, "kernel attributes: %s", hipGetErrorString(e));
+  // a handle on the stack over the static scratch: no events, no side stream, no mapped flag
+  // (a non-finite block is reported from the device control block at the end)
+  sketch_s h;
+  h.cfg = *cfg;
+  h.lay = L;
+  h.ws = (uint8_t*)ws;
+  h.stream = (hipStream_t)hip_stream;
+  h.device = dev;
+  // the scratch keeps the last call's contents: everything read before it is written is cleared
+  e = launch_fill_f64(h.at<double>(L.off_small), (int64_t)finalize_small_elems(cfg->l, cfg->b),
+                      0.0, h.stream);
+  if (e != hipSuccess) return fail(SKETCH_E_DEVICE, "scratch clear: %s", hipGetErrorString(e));
+  if (sketch_status st = start_pass(&h)) return st;
+  const int es = src_size(src_dtype);
+  const uint8_t* A = (const uint8_t*)A_dev;
+  for (int64_t r0 = 0; r0 < m; r0 += cfg->max_block_rows) {
+    const int64_t rows = std::min<int64_t>(cfg->max_block_rows, m - r0);
+    e = enqueue_pass(&h, A + r0 * lda * es, lda, src_dtype, rows, nullptr);
+    if (e != hipSuccess) return fail(SKETCH_E_DEVICE, "pass kernels: %s", hipGetErrorString(e));
+    h.rows += rows;
+  }
+  return finalize_core(&h, S_dev, U_dev, ldu, V_dev, ldv, rank_out);
+}
+
+}  // extern "C"
+
