@@ -168,6 +168,20 @@ sketch_status sketch_restore(sketch_t h, const void* buf, size_t bytes);
  * compute mode; E_CAPACITY if the rows would exceed m_capacity; E_STATE after finalize. */
 sketch_status sketch_merge(sketch_t h, const void* buf, size_t bytes);
 
+/* Power scheme with P = 1 (Sec. 2.2; the remark closing Sec. 3.3: the loop is run once more with
+ * Omega replaced by orth(H); Sec. 4.2 reports its accuracy).  Call it after the first pass over all
+ * rows of A: it replaces Omega by Omega_2 = sqrt(n) orth(H) (FP64 on the device, then rounded to
+ * the operand format like any Omega') and starts a second pass (rows = 0, G = [], H = 0).  The
+ * caller then ingests the rows of A again and calls sketch_finalize, which returns the triplets of
+ * the randomised SVD of (A A^T) A's range applied to A (singular values of A, not cubed).
+ * The scale sqrt(n) is a reading: results depend only on the span of Omega.  route: 0 = Cholesky
+ * QR2 of H when its tests accept it, else shifted Cholesky QR3, else block Gram-Schmidt with
+ * Householder TSQR; 2 = shifted QR3 first; 1 = Gram-Schmidt + TSQR (all give orth(H));
+ * *route_used (nullable) = the route that produced it.  Waits for the stream.  A later
+ * sketch_reset draws a Gaussian Omega again when the handle draws its own (it keeps Omega_2
+ * otherwise), and checkpoints store Omega_2 itself.  E_STATE before any rows or after finalize. */
+sketch_status sketch_power_restart(sketch_t h, int32_t route, int32_t* route_used);
+
 /* Copies Omega' (n x l, FP64, row-major, leading dimension ld >= l) into device memory. */
 sketch_status sketch_get_omega(sketch_t h, double* omega_dev, int64_t ld);
 

@@ -25,7 +25,7 @@ EXPORTED = [
     "sketch_ingest_block", "sketch_poll", "sketch_finalize", "sketch_finalize_paths",
     "sketch_debug_force_paths",
     "sketch_get_omega", "sketch_checkpoint_size", "sketch_checkpoint", "sketch_restore",
-    "sketch_merge", "sketch_pca_static",
+    "sketch_merge", "sketch_pca_static", "sketch_power_restart",
     "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
     "sketch_destroy", "sketch_last_error",
     "sketch_server_workspace_size", "sketch_server_stream_bytes", "sketch_server_create",
@@ -99,6 +99,7 @@ def load_library(path=None):
         "sketch_checkpoint": (I32, [P, P, ctypes.c_size_t]),
         "sketch_restore": (I32, [P, P, ctypes.c_size_t]),
         "sketch_merge": (I32, [P, P, ctypes.c_size_t]),
+        "sketch_power_restart": (I32, [P, I32, ctypes.POINTER(I32)]),
         "sketch_pca_static": (I32, [cfgp, P, I32, I64, I64, P, P, I64, P, I64,
                                     ctypes.POINTER(I32), P]),
         "sketch_debug_state": (I32, [P, P, P, ctypes.POINTER(I64)]),
@@ -234,6 +235,12 @@ def sketch_pca_static(cfg, A, S, U, V, stream=None):
     return rank.value
 
 
+def sketch_power_restart(h, route=0):
+    used = ctypes.c_int32(-1)
+    _check(load_library().sketch_power_restart(h, int(route), ctypes.byref(used)))
+    return used.value
+
+
 def sketch_get_omega(h, out):
     _check(load_library().sketch_get_omega(h, _ptr(out), out.stride(0)))
 
@@ -361,6 +368,11 @@ class Sketch:
 
     def merge(self, buf):
         sketch_merge(self.h, buf)
+
+    def power_restart(self, route=0):
+        """Power scheme P = 1: Omega <- sqrt(n) orth(H) and a new pass; re-ingest A, then
+        finalize.  Returns the orthonormalisation route used."""
+        return sketch_power_restart(self.h, route)
 
     def profile(self, on=True):
         sketch_profile_enable(self.h, on)

@@ -2198,4 +2198,96 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   return hipStreamSynchronize(stream);
 }
 
+// ---------------------------------------------------------------- power scheme, P = 1
+// Omega_2 = sqrt(n) orth(H) for the second pass (Sec. 2.2 and the remark closing Sec. 3.3: the
+// loop runs again with Omega replaced by H after orth; Sec. 4.2 measures it).  orth is the Q
+// factor of H by Cholesky QR2 when its tests accept it (as for R_B: no pivot below 1e-8 of its
+// diagonal entry, second factor within 1e-6 of I), else shifted Cholesky QR3, else block
+// Gram-Schmidt with Householder TSQR.  H's columns all lean towards v_1 (they are A^T A omega_j),
+// so H is as ill-conditioned as (sigma_1 / sigma_l)^2 and the later routes are taken more often
+// than for R_B.  The sqrt(n) scale keeps the entries near the unit variance of the Gaussian
+// Omega (which the FP8 operand format needs); Alg. 4 depends on Omega only through its span.
+__global__ void k_scale_cols(double* __restrict__ X, int64_t ldx, int64_t rows, int cols,
+                             double a) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < rows * cols;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = q / rows, r = q - c * rows;
+    X[c * ldx + r] *= a;
+  }
+}
+
+hipError_t run_power_omega(PowerArgs& p, hipStream_t stream) {
+  Ctx cx{stream};
+  const int L = p.l, b = p.b;
+  const int64_t n = p.n;
+  Small sm = carve_small(p.small, p.l, p.b);
+  int* fail = sm.info + 1;
+  int* ill = sm.info + 2;
+  const double u = 1.1102230246251565e-16;     // 2^-53
+  int route = p.route;
+  for (;;) {
+    if (route == 0) {
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, fail, 0);
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, ill, 0);
+      cx.chk();
+      gram_upper(cx, p.H, p.ldh, n, L, p.red_ws, sm.Jm);
+      chol(cx, sm.Jm, L, 0.0, sm.Wk, sm.Jk, fail, 1e-8, 0.0, ill);
+      right_trmul(cx, p.W1, p.ldw, p.H, p.ldh, n, L, sm.Jk);
+      gram_upper(cx, p.W1, p.ldw, n, L, p.red_ws, sm.Jm);
+      chol(cx, sm.Jm, L, 0.0, sm.Wm, sm.Jk, fail, 0.0, 1e-6, ill);
+      right_trmul(cx, p.om64, p.ldo, p.W1, p.ldw, n, L, sm.Jk);
+    } else if (route == 2) {
+      const double shift_rel = 11.0 * ((double)n * L + (double)L * (L + 1)) * u;
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, fail, 0);
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, ill, 0);
+      cx.chk();
+      gram_upper(cx, p.H, p.ldh, n, L, p.red_ws, sm.Jm);
+      chol(cx, sm.Jm, L, shift_rel, sm.Wk, sm.Jk, fail);
+      right_trmul(cx, p.W1, p.ldw, p.H, p.ldh, n, L, sm.Jk);
+      gram_upper(cx, p.W1, p.ldw, n, L, p.red_ws, sm.Jm);
+      chol(cx, sm.Jm, L, 0.0, sm.Wk, sm.Jk, fail);
+      right_trmul(cx, p.W2, p.ldw, p.W1, p.ldw, n, L, sm.Jk);
+      gram_upper(cx, p.W2, p.ldw, n, L, p.red_ws, sm.Jm);
+      chol(cx, sm.Jm, L, 0.0, sm.Wk, sm.Jk, fail);
+      right_trmul(cx, p.om64, p.ldo, p.W2, p.ldw, n, L, sm.Jk);
+    } else {
+      // block Gram-Schmidt with two Householder TSQR passes per block, on a copy of H
+      if (cx.ok())
+        cx.err = hipMemcpy2DAsync(p.W1, p.ldw * 8, p.H, p.ldh * 8, n * 8, L,
+                                  hipMemcpyDeviceToDevice, stream);
+      for (int c0 = 0; c0 < L && cx.ok(); c0 += b) {
+        const int w = (L - c0 < b) ? (L - c0) : b;
+        double* Qp = p.W2 + (int64_t)c0 * p.ldw;
+        const double* Bp = p.W1 + (int64_t)c0 * p.ldw;
+        tn(cx, p.W2, p.ldw, Bp, p.ldw, c0, w, n, p.red_ws, sm.C1, w, nullptr, 0);
+        nn<double>(cx, Qp, p.ldw, Bp, p.ldw, p.W2, p.ldw, c0, sm.C1, w, w, n, -1.0, nullptr, 0);
+        tsqr(cx, Qp, p.ldw, n, w, p.tsqr_ws, sm.R1, nullptr, 0);
+        tn(cx, p.W2, p.ldw, Qp, p.ldw, c0, w, n, p.red_ws, sm.C2, w, nullptr, 0);
+        nn<double>(cx, Qp, p.ldw, Qp, p.ldw, p.W2, p.ldw, c0, sm.C2, w, w, n, -1.0, nullptr, 0);
+        tsqr(cx, Qp, p.ldw, n, w, p.tsqr_ws, sm.R2, nullptr, 0);
+      }
+      if (cx.ok())
+        cx.err = hipMemcpy2DAsync(p.om64, p.ldo * 8, p.W2, p.ldw * 8, n * 8, L,
+                                  hipMemcpyDeviceToDevice, stream);
+      if (!cx.ok()) return cx.err;
+      p.route_used = 1;
+      break;
+    }
+    if (!cx.ok()) return cx.err;
+    int hflags[2] = {1, 1};
+    cx.err = hipMemcpyAsync(hflags, sm.info + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+    if (!cx.ok()) return cx.err;
+    if (hflags[0] == 0 && (route == 2 || hflags[1] == 0)) {
+      p.route_used = route;
+      break;
+    }
+    route = (route == 0) ? 2 : 1;
+  }
+  hipLaunchKernelGGL(k_scale_cols, dim3(grid_for(n * L)), dim3(TPB), 0, stream, p.om64, p.ldo, n,
+                     L, sqrt((double)n));
+  cx.chk();
+  return cx.err;
+}
+
 }  // namespace sk

@@ -126,6 +126,19 @@ struct FinalizeArgs {
   int32_t path_rb = -1;              // out: 0 Cholesky QR2 of B^T, 2 shifted Cholesky QR3,
                                      //      1 Gram-Schmidt + TSQR
 };
+// Power scheme with P = 1: Omega_2 = sqrt(n) orth(H) (FP64, column-major) for the second pass.
+struct PowerArgs {
+  int64_t n;
+  int l, b;
+  const double* H; int64_t ldh;      // n x l, column-major
+  double* om64; int64_t ldo;         // out: n x l (the padding is left as it is)
+  double* W1; double* W2; int64_t ldw;   // two n x l scratch matrices
+  double* red_ws; double* tsqr_ws; double* small;
+  int32_t route = 0;                 // in: 0 Cholesky QR2, then shifted QR3, then TSQR as needed;
+                                     //     2 shifted QR3 first; 1 Gram-Schmidt + TSQR
+  int32_t route_used = -1;           // out: the route that produced orth(H)
+};
+hipError_t run_power_omega(PowerArgs& p, hipStream_t s);
 constexpr int kMaxDevices = 64;
 // Once per device and thread-safe: kernel attributes the finalize needs (call on the device used).
 hipError_t finalize_prepare();

@@ -164,6 +164,7 @@ struct sketch_s {
   int* nf_dev = nullptr;            // its device address
   int32_t path_loop = -1, path_rb = -1;   // QR methods the last finalize used
   int32_t force_loop = 0, force_rb = 0;   // test hook: take the Householder paths directly
+  bool omega_derived = false;       // Omega' came from the data (power scheme), not from the seed
   uint64_t next_ticket = 1;
   hipEvent_t done_ev[kRing] = {};
   hipEvent_t copy_ev[kRing] = {};
@@ -226,6 +227,7 @@ sketch_status start_pass(sketch_t h) {
   if (e != hipSuccess) return h->dev_fail(e, "reset state");
   h->rows = 0;
   if (h->cfg.omega_from_seed) {
+    h->omega_derived = false;
     e = launch_omega_philox(h->cfg.seed, h->cfg.n, h->cfg.l, h->at<double>(L.off_om64), L.NP,
                             h->stream);
     if (e != hipSuccess) return h->dev_fail(e, "omega generation");
@@ -570,6 +572,45 @@ sketch_status sketch_finalize(sketch_t h, double* S_dev, double* U_dev, int64_t 
   return finalize_core(h, S_dev, U_dev, ldu, V_dev, ldv, rank_out);
 }
 
+sketch_status sketch_power_restart(sketch_t h, int32_t route, int32_t* route_used) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (h->phase != 1 || h->rows == 0)
+    return fail(SKETCH_E_STATE, "the power scheme needs a completed first pass (rows ingested, "
+                                "not finalized)");
+  if (route != 0 && route != 1 && route != 2) return fail(SKETCH_E_INVAL, "route must be 0, 1 or 2");
+  const Layout& L = h->lay;
+  PowerArgs p{};
+  p.n = h->cfg.n;
+  p.l = h->cfg.l;
+  p.b = h->cfg.b;
+  p.H = h->at<double>(L.off_H);
+  p.ldh = L.NP;
+  p.om64 = h->at<double>(L.off_om64);
+  p.ldo = L.NP;
+  p.W1 = h->at<double>(L.off_Bt);
+  p.W2 = h->at<double>(L.off_Qb);
+  p.ldw = L.NP;
+  p.red_ws = h->at<double>(L.off_red);
+  p.tsqr_ws = h->at<double>(L.off_tsqr);
+  p.small = h->at<double>(L.off_small);
+  p.route = route;
+  hipError_t e = run_power_omega(p, h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "power scheme: orth(H)");
+  // Omega_2 rounded to the operand format, then a fresh pass with it
+  if (sketch_status st = make_omega_ready(h)) return st;
+  const int seed_flag = h->cfg.omega_from_seed;
+  h->cfg.omega_from_seed = 0;
+  sketch_status st = start_pass(h);
+  h->cfg.omega_from_seed = seed_flag;
+  if (st != SKETCH_OK) return st;
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "power scheme");
+  h->omega_derived = true;
+  h->phase = 1;
+  if (route_used) *route_used = p.route_used;
+  return SKETCH_OK;
+}
+
 sketch_status sketch_debug_force_paths(sketch_t h, int32_t loop_householder, int32_t rb_mode) {
   if (sketch_status st = check_handle(h)) return st;
   if (rb_mode < 0 || rb_mode > 4) return fail(SKETCH_E_INVAL, "rb mode must be 0 .. 4");
@@ -641,7 +682,7 @@ CkptHeader ckpt_header(const sketch_s* h) {
   c.rows = h->rows;
   c.l = h->cfg.l;
   c.compute = h->cfg.compute;
-  c.omega_from_seed = h->cfg.omega_from_seed;
+  c.omega_from_seed = (h->cfg.omega_from_seed && !h->omega_derived) ? 1 : 0;
   c.g_bytes = (h->cfg.compute == SKETCH_F64) ? 8 : 4;
   c.hcols = h->cfg.l;
   c.seed = h->cfg.seed;
@@ -674,6 +715,7 @@ sketch_status ckpt_check(sketch_t h, const void* buf, size_t bytes, CkptHeader* 
   tmp.cfg = h->cfg;
   tmp.cfg.omega_from_seed = c.omega_from_seed;
   tmp.cfg.seed = c.seed;
+  tmp.omega_derived = false;
   tmp.rows = c.rows;
   const CkptHeader e = ckpt_header(&tmp);
   if (e.off_H != c.off_H || e.off_G != c.off_G || e.off_om != c.off_om || e.total != c.total)
@@ -770,6 +812,7 @@ sketch_status sketch_restore(sketch_t h, const void* buf, size_t bytes) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return h->dev_fail(e, "restore");
   h->cfg.seed = c.seed;
+  h->omega_derived = !c.omega_from_seed && h->cfg.omega_from_seed;
   h->rows = c.rows;
   h->phase = 1;
   return SKETCH_OK;
