@@ -87,6 +87,12 @@ typedef struct {
   int32_t omega_from_seed; /* 1: Omega drawn on the device from `seed` (Philox-4x64-10 + Box-Muller,
                               entry (r, c) from words 2(r l + c) and 2(r l + c) + 1 of the stream
                               with key (seed, 0)); 0: supplied by sketch_set_omega */
+  int32_t centre;          /* 1: PCA of the column-centred A - 1 mu^T, mu = the column means (the
+                              method assumes centred data, Sec. 2.1), still in one pass: the pass
+                              also sums the columns of A, and sketch_finalize centres the sketch
+                              (G - 1 (Omega'^T mu)^T, H - mu (G^T 1)^T) before Alg. 4 steps 9-19.
+                              Needs l <= 127.  0: A as given */
+  int32_t reserved;        /* 0 */
   uint64_t seed;
 } sketch_config;
 
@@ -181,6 +187,11 @@ sketch_status sketch_merge(sketch_t h, const void* buf, size_t bytes);
  * sketch_reset draws a Gaussian Omega again when the handle draws its own (it keeps Omega_2
  * otherwise), and checkpoints store Omega_2 itself.  E_STATE before any rows or after finalize. */
 sketch_status sketch_power_restart(sketch_t h, int32_t route, int32_t* route_used);
+
+/* Column means mu (n values, FP64, device pointer) of the rows ingested so far, for a handle
+ * created with centre = 1: the sums of the pass over the row count before sketch_finalize, the
+ * means it centred with after it.  E_STATE without centring or before any row. */
+sketch_status sketch_column_mean(sketch_t h, double* mu_dev);
 
 /* Copies Omega' (n x l, FP64, row-major, leading dimension ld >= l) into device memory. */
 sketch_status sketch_get_omega(sketch_t h, double* omega_dev, int64_t ld);

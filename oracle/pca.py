@@ -182,14 +182,23 @@ def power_omega(H):
     return np.sqrt(H.shape[0]) * Q
 
 
-def single_pass_pca_power(blocks, Omega, k, b, tau=1e-10, want_u=True, keep_state=False):
+def single_pass_pca_power(blocks, Omega, k, b, tau=1e-10, want_u=True, keep_state=False,
+                          centred=False):
     """Algorithm 4 with one power iteration (P = 1): a first pass gives H = A^T A Omega, then the
     pass and the column-block loop run again with Omega_2 = power_omega(H) (two passes over A in
-    all).  `blocks` is a list of row blocks (it is read twice).  The result carries Omega_2."""
+    all).  `blocks` is a list of row blocks (it is read twice).  The result carries Omega_2.
+    With centred=True both passes act on the column-centred matrix (centred implicitly, as in
+    single_pass_pca_centred), so Omega_2 = power_omega(A_c^T A_c Omega)."""
     blocks = list(blocks)
-    _, H1 = sketch_pass(blocks, Omega)
-    Om2 = power_omega(H1)
-    res = single_pass_pca(blocks, Om2, k, b, tau, want_u, keep_state)
+    if centred:
+        G1, H1, s_A, s_G, m = sketch_pass_centred(blocks, Omega)
+        _, H1, _ = centre_sketch(G1, H1, Omega, s_A, s_G, m)
+        Om2 = power_omega(H1)
+        res = single_pass_pca_centred(blocks, Om2, k, b, tau, want_u, keep_state)
+    else:
+        _, H1 = sketch_pass(blocks, Omega)
+        Om2 = power_omega(H1)
+        res = single_pass_pca(blocks, Om2, k, b, tau, want_u, keep_state)
     res.Omega = Om2
     return res
 

@@ -25,7 +25,7 @@ EXPORTED = [
     "sketch_ingest_block", "sketch_poll", "sketch_finalize", "sketch_finalize_paths",
     "sketch_debug_force_paths",
     "sketch_get_omega", "sketch_checkpoint_size", "sketch_checkpoint", "sketch_restore",
-    "sketch_merge", "sketch_pca_static", "sketch_power_restart",
+    "sketch_merge", "sketch_pca_static", "sketch_power_restart", "sketch_column_mean",
     "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
     "sketch_destroy", "sketch_last_error",
     "sketch_server_workspace_size", "sketch_server_stream_bytes", "sketch_server_create",
@@ -45,7 +45,8 @@ class sketch_config(ctypes.Structure):
         ("n", ctypes.c_int64), ("m_capacity", ctypes.c_int64), ("max_block_rows", ctypes.c_int64),
         ("k", ctypes.c_int32), ("l", ctypes.c_int32), ("b", ctypes.c_int32),
         ("compute", ctypes.c_int32), ("host_slots", ctypes.c_int32), ("host_src", ctypes.c_int32),
-        ("want_u", ctypes.c_int32), ("omega_from_seed", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("want_u", ctypes.c_int32), ("omega_from_seed", ctypes.c_int32),
+        ("centre", ctypes.c_int32), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -100,6 +101,7 @@ def load_library(path=None):
         "sketch_restore": (I32, [P, P, ctypes.c_size_t]),
         "sketch_merge": (I32, [P, P, ctypes.c_size_t]),
         "sketch_power_restart": (I32, [P, I32, ctypes.POINTER(I32)]),
+        "sketch_column_mean": (I32, [P, P]),
         "sketch_pca_static": (I32, [cfgp, P, I32, I64, I64, P, P, I64, P, I64,
                                     ctypes.POINTER(I32), P]),
         "sketch_debug_state": (I32, [P, P, P, ctypes.POINTER(I64)]),
@@ -241,6 +243,10 @@ def sketch_power_restart(h, route=0):
     return used.value
 
 
+def sketch_column_mean(h, out):
+    _check(load_library().sketch_column_mean(h, _ptr(out)))
+
+
 def sketch_get_omega(h, out):
     _check(load_library().sketch_get_omega(h, _ptr(out), out.stride(0)))
 
@@ -283,13 +289,14 @@ class Sketch:
     """
 
     def __init__(self, n, m_capacity, max_block_rows, k, l, b=10, compute="f32", host_slots=0,
-                 host_src="f32", want_u=False, seed=0, omega=None, stream=None):
+                 host_src="f32", want_u=False, seed=0, omega=None, stream=None, centre=False):
         import torch
         load_library()
         self.cfg = sketch_config(
             n=n, m_capacity=m_capacity, max_block_rows=max_block_rows, k=k, l=l, b=b,
             compute=DTYPES[compute], host_slots=host_slots, host_src=DTYPES[host_src],
-            want_u=int(bool(want_u)), omega_from_seed=int(omega is None), seed=seed)
+            want_u=int(bool(want_u)), omega_from_seed=int(omega is None),
+            centre=int(bool(centre)), seed=seed)
         self.n, self.k, self.l = n, k, l
         self.stream = stream
         ws = sketch_workspace_size(self.cfg)
@@ -368,6 +375,13 @@ class Sketch:
 
     def merge(self, buf):
         sketch_merge(self.h, buf)
+
+    def column_mean(self):
+        """Column means of the rows ingested (handles created with centre=True)."""
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        sketch_column_mean(self.h, out)
+        return out
 
     def power_restart(self, route=0):
         """Power scheme P = 1: Omega <- sqrt(n) orth(H) and a new pass; re-ingest A, then

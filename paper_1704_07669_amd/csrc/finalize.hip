@@ -1731,6 +1731,7 @@ void tsqr(Ctx& cx, double* X, int64_t ldx, int64_t rows, int b, double* ws, doub
 // Small-buffer layout (doubles), see finalize_small_elems.
 struct Small {
   double *W, *T, *C, *Wn, *R1, *R2, *R, *X, *RB, *C1, *C2, *Jm, *Wm, *sig, *Jk, *Wk, *sgn;
+  double *sG, *wc;   // centring: s_G = G^T 1 and w = Omega'^T mu
   int* perm; int* info;
 };
 Small carve_small(double* base, int l, int b) {
@@ -1745,6 +1746,7 @@ Small carve_small(double* base, int l, int b) {
   sm.Jk = take((int64_t)l * l); sm.Wk = take((int64_t)l * l); sm.sgn = take(l);
   sm.perm = reinterpret_cast<int*>(take(l));
   sm.info = reinterpret_cast<int*>(take(4));
+  sm.sG = take(l); sm.wc = take(l);
   return sm;
 }
 
@@ -1959,7 +1961,7 @@ size_t finalize_small_elems(int l, int b) {
   (void)b;
   const int64_t P = (int64_t)l * 32;
   int64_t e = 6 * rup<int64_t>(P, 32) + 4 * 1024 + 5 * rup<int64_t>((int64_t)l * l + l, 32) +
-              3 * rup<int64_t>(l, 32) + 32;
+              5 * rup<int64_t>(l, 32) + 32;
   return (size_t)e + 1024;
 }
 
@@ -1985,12 +1987,117 @@ size_t reduce_workspace_elems(int64_t rows, int p, int q) {
   return (size_t)(nch * p * 32 * cdiv(p, 32)) + 64;
 }
 
+// ---------------------------------------------------------------- implicit column centring
+// PCA of the column-centred A_c = A - 1 mu^T, mu = s_A / m, from the sketch of A (the method
+// assumes centred data, Sec. 2.1).  The pass accumulated s_A = A^T 1 as sketch column l of H (its
+// operand column of g is all ones); here s_G = G^T 1 and w = Omega'^T mu give
+//   G_c = G - 1 w^T,   H_c = H - mu s_G^T
+// (the A^T 1 w^T and m mu w^T terms of A_c^T G_c cancel), written over G and H.
+template <typename GT>
+__global__ __launch_bounds__(TPB) void k_col_sums(const GT* __restrict__ X, int64_t ldx,
+                                                  int64_t rows, double* __restrict__ out) {
+  __shared__ double red[TPB / 64];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += TPB) acc += (double)X[c * ldx + r];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < TPB / 64; ++w) t += red[w];
+    out[c] = t;
+  }
+}
+
+// mu = s_A / m from column l of H; w[c] = sum_r Omega'(r, c) mu_r, one workgroup per column
+__global__ __launch_bounds__(TPB) void k_centre_w(const double* __restrict__ H, int64_t ldh,
+                                                  const double* __restrict__ om, int64_t ldo,
+                                                  int64_t n, int l, double inv_m,
+                                                  double* __restrict__ mu,
+                                                  double* __restrict__ w) {
+  __shared__ double red[TPB / 64];
+  const int c = blockIdx.x;
+  const double* sA = H + (int64_t)l * ldh;
+  double acc = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += TPB) {
+    const double m_r = sA[r] * inv_m;
+    if (c == 0) mu[r] = m_r;
+    acc += om[c * ldo + r] * m_r;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int v = 0; v < TPB / 64; ++v) t += red[v];
+    w[c] = t;
+  }
+}
+
+template <typename GT>
+__global__ void k_centre_G(GT* __restrict__ G, int64_t ldg, int64_t rows, int l,
+                           const double* __restrict__ w) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < rows * l;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = q / rows, r = q - c * rows;
+    G[c * ldg + r] = (GT)((double)G[c * ldg + r] - w[c]);
+  }
+}
+
+__global__ void k_centre_H(double* __restrict__ H, int64_t ldh, int64_t n, int l,
+                           const double* __restrict__ mu, const double* __restrict__ sG) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n * l;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = q / n, r = q - c * n;
+    H[c * ldh + r] -= mu[r] * sG[c];
+  }
+}
+
+hipError_t centre_sketch(int mode, void* G, int64_t ldg, int64_t m, double* H, int64_t ldh,
+                         int64_t n, int l, const double* om64, int64_t ldo, double* mu,
+                         double* small, int b, hipStream_t stream) {
+  Ctx cx{stream};
+  Small sm = carve_small(small, l, b);
+  if (mode == M_F64)
+    hipLaunchKernelGGL(k_col_sums<double>, dim3(l), dim3(TPB), 0, stream, (const double*)G, ldg, m,
+                       sm.sG);
+  else
+    hipLaunchKernelGGL(k_col_sums<float>, dim3(l), dim3(TPB), 0, stream, (const float*)G, ldg, m,
+                       sm.sG);
+  cx.chk();
+  if (cx.ok())
+    hipLaunchKernelGGL(k_centre_w, dim3(l), dim3(TPB), 0, stream, H, ldh, om64, ldo, n, l,
+                       1.0 / (double)m, mu, sm.wc);
+  cx.chk();
+  if (cx.ok()) {
+    if (mode == M_F64)
+      hipLaunchKernelGGL(k_centre_G<double>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
+                         (double*)G, ldg, m, l, sm.wc);
+    else
+      hipLaunchKernelGGL(k_centre_G<float>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
+                         (float*)G, ldg, m, l, sm.wc);
+  }
+  cx.chk();
+  if (cx.ok())
+    hipLaunchKernelGGL(k_centre_H, dim3(grid_for(n * l)), dim3(TPB), 0, stream, H, ldh, n, l, mu,
+                       sm.sG);
+  cx.chk();
+  return cx.err;
+}
+
 hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   Ctx cx{stream};
   const int b = f.b, l = f.l, t = l / b;
   const int64_t m = f.m, n = f.n;
   Small sm = carve_small(f.small, l, b);
   Ctrl* ctrl = f.ctrl;
+  if (f.centre) {
+    hipError_t e = centre_sketch(f.mode, const_cast<void*>(f.G), f.ldg, m,
+                                 const_cast<double*>(f.H), f.ldh, n, l, f.om64, f.ldo, f.mu,
+                                 f.small, b, stream);
+    if (e != hipSuccess) return e;
+  }
 
   // ---------------- column-block loop (Alg. 4 steps 9-15).  Cholesky QR of the blocks first; if a
   // block was flagged as too ill-conditioned for it, the loop is repeated with Householder TSQR.

@@ -50,7 +50,11 @@ struct PassItem {
   int32_t strips, rsplit, rchunk, red_wgs;
   int32_t wg1, wg2, wgr, wgh;   // first workgroup of the item in the g, a^T g, reduce and
                                 //   row-split sum grids
-  int32_t hsum_wgs, pad0, pad1, pad2;
+  int32_t hsum_wgs;
+  int32_t sum_col;     // G-operand column set to ones, so a^T g also accumulates the column sums
+                       //   of a in that column of H (implicit centring); 0: none (column 0 is
+                       //   always a sketch column)
+  int32_t pad1, pad2;
 };
 struct PassGroup {
   int mode;            // Mode
@@ -94,6 +98,7 @@ hipError_t launch_fill_rows(double* p, int64_t rows, int cols, int64_t ld, doubl
 hipError_t launch_copy_state(int mode, const void* G, int64_t ldg, int64_t rows, const double* H,
                              int64_t ldh, int64_t n, int l, double* Gout, double* Hout,
                              hipStream_t s);
+hipError_t launch_scale_f64(double* p, int64_t count, double a, hipStream_t s);
 // a(:, 0:cols) += b(:, 0:cols) over `rows` rows (column-major FP64)
 hipError_t launch_add_cols(double* a, int64_t lda, const double* b, int64_t ldb, int64_t rows,
                            int cols, hipStream_t s);
@@ -118,6 +123,8 @@ struct FinalizeArgs {
   double* small;                     // small matrices, see finalize.hip
   Ctrl* ctrl;
   double* S; double* U; int64_t ldu; double* V; int64_t ldv;
+  int32_t centre = 0;                // 1: column l of H holds s_A = A^T 1; centre G and H first
+  double* mu = nullptr;              // out (centre): the column means, n values
   int32_t force_loop = 0;            // in: 1 takes the Householder TSQR path of the loop directly
   int32_t force_rb = 0;              // in: 1 Gram-Schmidt + TSQR for R_B, 2 shifted Cholesky QR3,
                                      //     3 QR2 formed, then treated as not accepted,
@@ -139,6 +146,11 @@ struct PowerArgs {
   int32_t route_used = -1;           // out: the route that produced orth(H)
 };
 hipError_t run_power_omega(PowerArgs& p, hipStream_t s);
+// Implicit centring of the sketch in place: G <- G - 1 (Omega'^T mu)^T, H <- H - mu (G^T 1)^T with
+// mu = H(:, l) / m (column l of H holds A^T 1); writes mu (n values).
+hipError_t centre_sketch(int mode, void* G, int64_t ldg, int64_t m, double* H, int64_t ldh,
+                         int64_t n, int l, const double* om64, int64_t ldo, double* mu,
+                         double* small, int b, hipStream_t s);
 constexpr int kMaxDevices = 64;
 // Once per device and thread-safe: kernel attributes the finalize needs (call on the device used).
 hipError_t finalize_prepare();

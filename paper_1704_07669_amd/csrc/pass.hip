@@ -387,14 +387,16 @@ __global__ void k_reduce1(const PassItem one, const PassItem* __restrict__ grp, 
     s *= scale;
     bad |= !isfinite(s);
     G[(int64_t)c * ldg + g_row0 + r] = s;
+    // the operand of a^T g; the column-sum column (centring) is all ones
+    const acc_t so = (it.sum_col != 0 && c == it.sum_col) ? (acc_t)1 : s;
     if constexpr (HILO) {
       SK_GLOBAL __bf16* hi = reinterpret_cast<SK_GLOBAL __bf16*>(gop);
       SK_GLOBAL __bf16* lo = hi + (int64_t)LP * ldp;
-      const __bf16 h = to_bf16((float)s);
+      const __bf16 h = to_bf16((float)so);
       hi[(int64_t)c * ldp + r] = h;
-      lo[(int64_t)c * ldp + r] = to_bf16((float)s - from_bf16(h));
+      lo[(int64_t)c * ldp + r] = to_bf16((float)so - from_bf16(h));
     } else {
-      reinterpret_cast<SK_GLOBAL acc_t*>(gop)[(int64_t)c * ldp + r] = s;
+      reinterpret_cast<SK_GLOBAL acc_t*>(gop)[(int64_t)c * ldp + r] = so;
     }
   }
   if (bad) {

@@ -172,6 +172,7 @@ const char* validate_stream(const sketch_server_config* s, const sketch_config* 
   if (c->l > c->n) return "l must be <= n";
   if (c->omega_from_seed != 1) return "served streams draw Omega from their seed";
   if (c->host_slots != 0) return "served streams take device rows (host_slots = 0)";
+  if (c->centre != 0) return "served streams are not centred (centre = 0)";
   if (c->want_u != 0 && c->want_u != 1) return "want_u must be 0 or 1";
   return nullptr;
 }

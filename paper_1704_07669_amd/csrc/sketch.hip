@@ -79,7 +79,7 @@ struct Layout {
   int LP, NT, t, splits_max;
   int64_t NP, MCAP, RBP, LDST, NQ;
   int64_t off_ctrl, off_fp8, off_om64, off_omc, off_G, off_H, off_P1, off_Gop, off_P2, off_cnt, off_stage, off_fp8q,
-      off_Q, off_Bt, off_Qb, off_tsqr, off_red, off_small, total;
+      off_Q, off_Bt, off_Qb, off_tsqr, off_red, off_small, off_mu, total;
   int64_t stage_slot_bytes;
   int64_t tsqr_elems, red_elems;
 };
@@ -101,12 +101,15 @@ const char* validate(const sketch_config* c) {
     return "host_src not supported by the compute mode";
   if (c->want_u != 0 && c->want_u != 1) return "want_u must be 0 or 1";
   if (c->omega_from_seed != 0 && c->omega_from_seed != 1) return "omega_from_seed must be 0 or 1";
+  if (c->centre != 0 && c->centre != 1) return "centre must be 0 or 1";
+  if (c->centre && c->l > 127) return "l must be <= 127 with centre = 1";
+  if (c->reserved != 0) return "reserved must be 0";
   return nullptr;
 }
 
 Layout plan(const sketch_config* c) {
   Layout L{};
-  L.LP = (int)rup<int64_t>(c->l, 16);
+  L.LP = (int)rup<int64_t>(c->l + (c->centre ? 1 : 0), 16);   // the column sums take column l
   L.NT = L.LP / 16;
   L.t = c->l / c->b;
   L.NP = rup<int64_t>(c->n, kNpAlign);
@@ -143,6 +146,7 @@ Layout plan(const sketch_config* c) {
   L.off_tsqr = take(L.tsqr_elems * 8);
   L.off_red = take(L.red_elems * 8);
   L.off_small = take((int64_t)finalize_small_elems(c->l, c->b) * 8);
+  L.off_mu = take(c->centre ? L.NP * 8 : 0);
   L.total = off;
   return L;
 }
@@ -165,6 +169,7 @@ struct sketch_s {
   int32_t path_loop = -1, path_rb = -1;   // QR methods the last finalize used
   int32_t force_loop = 0, force_rb = 0;   // test hook: take the Householder paths directly
   bool omega_derived = false;       // Omega' came from the data (power scheme), not from the seed
+  int64_t mean_rows = 0;            // rows behind the means finalize centred with (centre = 1)
   uint64_t next_ticket = 1;
   hipEvent_t done_ev[kRing] = {};
   hipEvent_t copy_ev[kRing] = {};
@@ -267,6 +272,7 @@ hipError_t enqueue_pass(sketch_t h, const void* A, int64_t lda, int src_dtype, i
   it.fp8_exp = nullptr;
   it.ctrl = h->ctrl();
   it.nf_host = h->nf_dev;
+  it.sum_col = c.centre ? c.l : 0;
   int src = src_dtype;
   if (c.compute == SKETCH_FP8_E4M3) {
     uint32_t* amax = h->at<uint32_t>(L.off_fp8);
@@ -353,6 +359,8 @@ sketch_status finalize_core(sketch_t h, double* S_dev, double* U_dev, int64_t ld
   f.ldv = ldv;
   f.force_loop = h->force_loop;
   f.force_rb = h->force_rb;
+  f.centre = c.centre;
+  f.mu = c.centre ? h->at<double>(L.off_mu) : nullptr;
   if (e == hipSuccess) e = run_finalize(f, h->stream);
   if (e == hipSuccess && h->prof) e = hipEventRecord(fb, h->stream);
   Ctrl hc;
@@ -361,6 +369,7 @@ sketch_status finalize_core(sketch_t h, double* S_dev, double* U_dev, int64_t ld
   if (e != hipSuccess) return h->dev_fail(e, "finalize");
   if (h->prof) h->recs.push_back({fa, fb, nullptr, 2});
   h->phase = 2;
+  h->mean_rows = h->rows;
   h->path_loop = f.path_loop;
   h->path_rb = f.path_rb;
   if (hc.nonfinite) {
@@ -594,7 +603,12 @@ sketch_status sketch_power_restart(sketch_t h, int32_t route, int32_t* route_use
   p.tsqr_ws = h->at<double>(L.off_tsqr);
   p.small = h->at<double>(L.off_small);
   p.route = route;
-  hipError_t e = run_power_omega(p, h->stream);
+  hipError_t e = hipSuccess;
+  if (h->cfg.centre)   // Omega_2 from the centred sketch: orth(A_c^T A_c Omega)
+    e = centre_sketch(h->cfg.compute, h->ws + L.off_G, L.MCAP, h->rows, h->at<double>(L.off_H),
+                      L.NP, h->cfg.n, h->cfg.l, h->at<double>(L.off_om64), L.NP,
+                      h->at<double>(L.off_mu), h->at<double>(L.off_small), h->cfg.b, h->stream);
+  if (e == hipSuccess) e = run_power_omega(p, h->stream);
   if (e != hipSuccess) return h->dev_fail(e, "power scheme: orth(H)");
   // Omega_2 rounded to the operand format, then a fresh pass with it
   if (sketch_status st = make_omega_ready(h)) return st;
@@ -608,6 +622,27 @@ sketch_status sketch_power_restart(sketch_t h, int32_t route, int32_t* route_use
   h->omega_derived = true;
   h->phase = 1;
   if (route_used) *route_used = p.route_used;
+  return SKETCH_OK;
+}
+
+sketch_status sketch_column_mean(sketch_t h, double* mu_dev) {
+  if (sketch_status st = check_handle(h)) return st;
+  if (!h->cfg.centre) return fail(SKETCH_E_STATE, "the handle does not centre (centre = 0)");
+  if (!mu_dev) return fail(SKETCH_E_INVAL, "mu is NULL");
+  const Layout& L = h->lay;
+  hipError_t e;
+  if (h->phase == 2) {
+    if (h->mean_rows == 0) return fail(SKETCH_E_STATE, "no rows were ingested");
+    e = hipMemcpyAsync(mu_dev, h->at<double>(L.off_mu), h->cfg.n * 8, hipMemcpyDeviceToDevice,
+                       h->stream);
+  } else {
+    if (h->rows == 0) return fail(SKETCH_E_STATE, "no rows were ingested");
+    e = hipMemcpyAsync(mu_dev, h->at<double>(L.off_H) + (int64_t)h->cfg.l * L.NP, h->cfg.n * 8,
+                       hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = launch_scale_f64(mu_dev, h->cfg.n, 1.0 / (double)h->rows, h->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->dev_fail(e, "column mean");
   return SKETCH_OK;
 }
 
@@ -666,7 +701,7 @@ struct CkptHeader {
   uint32_t version, header_bytes;
   int64_t n, rows;
   int32_t l, compute, omega_from_seed, g_bytes;
-  int32_t hcols, pad0;
+  int32_t hcols, centre;
   uint64_t seed;
   int64_t off_H, off_G, off_om, total;
   int64_t pad1[4];
@@ -684,7 +719,8 @@ CkptHeader ckpt_header(const sketch_s* h) {
   c.compute = h->cfg.compute;
   c.omega_from_seed = (h->cfg.omega_from_seed && !h->omega_derived) ? 1 : 0;
   c.g_bytes = (h->cfg.compute == SKETCH_F64) ? 8 : 4;
-  c.hcols = h->cfg.l;
+  c.hcols = h->cfg.l + (h->cfg.centre ? 1 : 0);   // with centring, column l holds A^T 1
+  c.centre = h->cfg.centre;
   c.seed = h->cfg.seed;
   int64_t off = rup<int64_t>(sizeof(CkptHeader), 64);
   c.off_H = off;
@@ -705,10 +741,13 @@ sketch_status ckpt_check(sketch_t h, const void* buf, size_t bytes, CkptHeader* 
   memcpy(&c, buf, sizeof(c));
   if (c.magic != kCkptMagic || c.version != kCkptVersion || c.header_bytes != sizeof(CkptHeader))
     return fail(SKETCH_E_INVAL, "not a checkpoint of this library version");
-  if (c.n != h->cfg.n || c.l != h->cfg.l || c.compute != h->cfg.compute)
-    return fail(SKETCH_E_INVAL, "checkpoint of n=%lld l=%d compute=%d does not fit this handle",
-                (long long)c.n, c.l, c.compute);
-  if (c.rows < 0 || c.hcols != c.l || c.g_bytes != ((c.compute == SKETCH_F64) ? 8 : 4))
+  if (c.n != h->cfg.n || c.l != h->cfg.l || c.compute != h->cfg.compute ||
+      c.centre != h->cfg.centre)
+    return fail(SKETCH_E_INVAL,
+                "checkpoint of n=%lld l=%d compute=%d centre=%d does not fit this handle",
+                (long long)c.n, c.l, c.compute, c.centre);
+  if (c.rows < 0 || c.hcols != c.l + c.centre ||
+      c.g_bytes != ((c.compute == SKETCH_F64) ? 8 : 4))
     return fail(SKETCH_E_INVAL, "corrupt checkpoint header");
   // recompute the section offsets from the header's own sizes
   sketch_s tmp;

@@ -50,6 +50,12 @@ __global__ void k_fill_rows(double* __restrict__ p, int64_t rows, int cols, int6
   }
 }
 
+__global__ void k_scale(double* __restrict__ p, int64_t count, double a) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] *= a;
+}
+
 // a[c * lda + r] += b[c * ldb + r] for r < rows, c < cols (column-major FP64)
 __global__ void k_add_cols(double* __restrict__ a, int64_t lda, const double* __restrict__ b,
                            int64_t ldb, int64_t rows, int cols) {
@@ -117,6 +123,12 @@ hipError_t launch_copy_omega_out(const double* om64, int64_t ldo, int64_t n, int
                                  int64_t ld, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_omega, dim3(grid_for(n * l)), dim3(256), 0, s, om64, ldo, n, l, out,
                      ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_f64(double* p, int64_t count, double a, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(count)), dim3(256), 0, s, p, count, a);
   return hipGetLastError();
 }
 

@@ -84,6 +84,30 @@ def test_init_rejects_without_touching_device():
     assert lib.sketch_destroy(None) == 1
 
 
-def test_config_struct_layout_matches_header():
-    # int64 x3, int32 x8, uint64 -> 3*8 + 8*4 + 8 = 64 bytes, no padding surprises
-    assert ctypes.sizeof(sk.sketch_config) == 64
+def test_config_struct_layout_matches_header(tmp_path):
+    """The binding's ctypes structures against the C compiler's own layout of include/sketch.h
+    (sizes and every field offset)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"sketch_config": sk.sketch_config, "sketch_server_config": sk.sketch_server_config,
+               "sketch_server_stats": sk.sketch_server_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sketch.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    assert len(out.splitlines()) == sum(len(c._fields_) + 1 for c in structs.values())
+    for line in out.splitlines():
+        name, field, val = line.split()
+        cls = structs[name]
+        want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(val) == want, (name, field)

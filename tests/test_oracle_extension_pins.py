@@ -193,6 +193,18 @@ def test_centring_removes_a_constant_row(centred_case):
     assert oracle.sin_theta_max(r0.V, r1.V) < 1e-8
 
 
+def test_centred_power_scheme_equals_algorithm1_on_centred_matrix(centred_case):
+    """P = 1 on centred data: the same as Algorithm 1 on the explicitly centred matrix with the
+    test matrix A_c^T A_c Omega (same span as Omega_2)."""
+    A, Om, k, b = centred_case["A"], centred_case["Om"], centred_case["k"], centred_case["b"]
+    Ac = A - A.mean(axis=0)
+    r = oracle.single_pass_pca_power(_blocks(A, 97), Om, k, b, centred=True, keep_state=True)
+    r1 = oracle.basic_randqb_svd(Ac, Ac.T @ (Ac @ Om), k)
+    assert np.max(oracle.rel_sigma_error(r.S, r1.S)) < 1e-9
+    assert oracle.sin_theta_max(r1.V, r.V) < 1e-7
+    assert oracle.sin_theta_max(_orth(Ac.T @ (Ac @ Om)), r.Omega / np.sqrt(A.shape[1])) < 1e-9
+
+
 def test_centring_of_centred_data_is_identity(centred_case):
     A, Om = centred_case["A"], centred_case["Om"]
     Ac = A - A.mean(axis=0)
