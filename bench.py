@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="bf16", choices=["f32", "bf16", "bf16x2", "fp8", "f64"])
-    ap.add_argument("--compare", default="f32", help="second mode reported alongside ('none' = none)")
+    ap.add_argument("--compare", default="f32,f64",
+                    help="further modes reported alongside, comma-separated ('none' = none)")
     ap.add_argument("--m", type=int, default=100000)
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--kron", default="500,200,100,200", help="m1,m2,n1,n2 with m=m1*m2, n=n1*n2")
@@ -55,6 +56,12 @@ def parse():
     ap.add_argument("--serving-rho", type=float, default=0.8,
                     help="offered load of the Poisson phase, as a fraction of saturation")
     ap.add_argument("--serving-modes", default="f32,bf16")
+    ap.add_argument("--power", default="bf16",
+                    help="modes run with the power scheme P = 1 on the resident workload ('' = none)")
+    ap.add_argument("--study", type=int, default=1,
+                    help="1: the Sec. 4.1 accuracy study (Types 1-5, 3000 x 3000, every mode)")
+    ap.add_argument("--host-configs", default="c5,c3",
+                    help="host-streamed workloads also run by the default workload ('' = none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (known bytes) to scale HBM "
                          "counters")
@@ -256,10 +263,23 @@ def h2d_peak(torch, gib=4):
         torch.cuda.synchronize()
         best = max(best, (gib << 30) / (time.perf_counter() - t0) / 1e9)
     del src, dst
+    src_pools_release(torch)
     return best
 
 
-def host_workload(args, torch, sk):
+def src_pools_release(torch):
+    """Returns freed pinned host buffers to the system (torch caches them), so the next
+    host-streamed workload can allocate its own."""
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    release = getattr(torch._C, "_host_emptyCache", None)
+    if release is not None:
+        release()
+    return release is not None
+
+
+def host_workload(args, torch, sk, which):
     """Host-streamed workloads: every row block is copied from pinned host memory by the library
     (side stream, staging ring of 3 slots) while the previous block is processed.
 
@@ -275,7 +295,7 @@ def host_workload(args, torch, sk):
     tmp = None
     peak = h2d_peak(torch, gib=1)
     print(f"[bench] pinned H2D peak {peak:.1f} GB/s", file=sys.stderr, flush=True)
-    if args.workload == "host-c3":
+    if which == "host-c3":
         m, n, blk, seed = 1_000_000, 10_000, 8192, 1003
         sig = synth.noisy_spectrum(synth.inv_square_spectrum(n), 1e-5, seed)
         K = synth.KronMatrix(1000, 1000, 100, 100, sig, seed)
@@ -387,7 +407,106 @@ def host_workload(args, torch, sk):
         "cpu_baseline": cpu,
         "modes": [{kk: v for kk, v in r.items() if kk not in ("S", "Om")} for r in res],
     }
-    print(json.dumps(line))
+    # drop every reference to the pinned rows before handing them back
+    blocks = ref_blocks = bl = blkv = host = pool32 = pool16 = None
+    src_pools_release(torch)
+    return line
+
+
+def power_bench(mode, A, K, args, torch, sk):
+    """The power scheme with P = 1 (Sec. 3.3, 4.2) on the resident workload: a first pass, Omega
+    replaced by sqrt(n) orth(H), a second pass and the finalize (two reads of A).  Reports the
+    time of the whole job, its FP32-equivalent rate per read of A, and the error against the
+    known spectrum next to the single-pass error of the same mode."""
+    m, n = A.shape
+    sigma = K.sigma
+    obj = sk.Sketch(n, m, args.block, args.k, args.l, args.b, compute=mode, seed=2002)
+
+    def one_pass():
+        for r0 in range(0, m, args.block):
+            obj.ingest(A[r0:r0 + args.block])
+
+    def job():
+        obj.reset(2002)
+        one_pass()
+        route = obj.power_restart()
+        one_pass()
+        S, _, _, _ = obj.finalize(want_u=False)
+        return S, route
+
+    job()
+    torch.cuda.synchronize()
+    steps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S, route = job()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    S = S.cpu().numpy()
+    obj.reset(2002)
+    one_pass()
+    S0, _, _, _ = obj.finalize(want_u=False)
+    S0 = S0.cpu().numpy()
+    obj.close()
+    k = args.k
+    rel1 = np.abs(S - sigma[:k]) / sigma[:k]
+    rel0 = np.abs(S0 - sigma[:k]) / sigma[:k]
+    print(f"[bench] power scheme {mode}: {ms:.2f} ms, rel sigma_k err vs known {rel1[-1]:.2e} "
+          f"(single pass {rel0[-1]:.2e})", file=sys.stderr, flush=True)
+    return {"dtype": mode, "passes": 2, "ms_per_job": ms,
+            "value": 4.0 * m * n / (ms * 1e-3) / 1e9, "unit": "GB/s (FP32 A per job)",
+            "per_read_gbps": 2 * 4.0 * m * n / (ms * 1e-3) / 1e9, "orth_route": route,
+            "rel_sigma_k_err_vs_known": float(rel1[-1]),
+            "max_rel_sigma_err_vs_known": float(rel1.max()),
+            "single_pass_rel_sigma_k_err_vs_known": float(rel0[-1]),
+            "single_pass_max_rel_sigma_err_vs_known": float(rel0.max())}
+
+
+def accuracy_study(torch, sk):
+    """Sec. 4.1's study: 3000 x 3000 matrices U diag(sigma) V^T (random orthogonal U, V) with the
+    spectra Type 1-5, k = 50, l = 60, b = 10, in every compute mode, against the known spectrum
+    (max |sigma_j - sigma_j(A)| over j <= k, the paper's max_err, and the relative error of
+    sigma_k), the FP64 GPU result, the reference's Algorithm 4 and Algorithm 2 (same Omega)."""
+    import oracle
+    import synth
+    N, k, l, b = 3000, 50, 60, 10
+    print("[bench] accuracy study (Sec. 4.1): Types 1-5 x modes", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(4100)
+    U = synth.orthonormal_factor(N, N, rng)
+    V = synth.orthonormal_factor(N, N, rng)
+    Om = synth.gaussian_omega(N, l, 4101)
+    Omt = synth.gaussian_omega(N, l, 4102)
+    out = []
+    for kind in range(1, 6):
+        s = synth.paper_type_spectrum(kind, N)
+        A = (U * s) @ V.T
+        row = {"type": kind}
+        S64 = None
+        for mode in ("f64", "f32", "bf16", "bf16x2", "fp8"):
+            At = torch.from_numpy(A).to(torch.float64 if mode == "f64" else torch.float32).cuda()
+            h = sk.Sketch(N, N, 1000, k, l, b, compute=mode, omega=Om)
+            for r0 in range(0, N, 1000):
+                h.ingest(At[r0:r0 + 1000])
+            S, _, _, _ = h.finalize(want_u=False)
+            torch.cuda.synchronize()
+            h.close()
+            S = S.cpu().numpy()
+            if mode == "f64":
+                S64 = S
+            row[mode] = {"max_err": float(np.max(np.abs(S - s[:k]))),
+                         "rel_sigma_k_err": float(abs(S[k - 1] - s[k - 1]) / s[k - 1]),
+                         "max_rel_vs_f64": float(np.max(np.abs(S - S64) / S64))}
+        r4 = oracle.single_pass_pca([A], Om, k, b, want_u=False)
+        S2, _, _ = oracle.alg2_single_pass(A, Om, Omt, k, want_u=False)
+        row["reference_alg4_max_err"] = float(np.max(np.abs(r4.S - s[:k])))
+        row["reference_alg2_max_err"] = float(np.max(np.abs(S2 - s[:k])))
+        out.append(row)
+        print(f"[bench] Type {kind}: max_err f64 {row['f64']['max_err']:.2e} "
+              f"f32 {row['f32']['max_err']:.2e} bf16 {row['bf16']['max_err']:.2e}; "
+              f"reference Alg. 4 {row['reference_alg4_max_err']:.2e}, "
+              f"Alg. 2 {row['reference_alg2_max_err']:.2e}", file=sys.stderr, flush=True)
+    return {"workload": "3000x3000 U diag(sigma) V^T, Types 1-5, k=50, l=60, b=10, "
+                        "1000-row device blocks", "rows": out}
 
 
 def roofline(res, m, n, l, mode):
@@ -516,11 +635,12 @@ def main():
     sk.load_library()
     torch.cuda.set_device(0)
     if args.workload != "fp32-resident":
-        host_workload(args, torch, sk)
+        print(json.dumps(host_workload(args, torch, sk, args.workload)))
         return
     print(f"[bench] generating A {args.m}x{args.n} FP32 on the GPU", file=sys.stderr, flush=True)
     A, K = make_matrix(args, torch)
-    modes = [args.mode] + ([args.compare] if args.compare not in ("", "none", args.mode) else [])
+    modes = [args.mode] + [c for c in args.compare.split(",")
+                           if c and c != "none" and c != args.mode]
     results = []
     for mode in modes:
         print(f"[bench] mode {mode}: {args.warmup} warmup + {args.steps} timed steps",
@@ -528,6 +648,7 @@ def main():
         results.append(bench_mode(mode, A, args, torch, sk))
         print(f"[bench] mode {mode}: {results[-1]['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
+    power = [power_bench(mode, A, K, args, torch, sk) for mode in args.power.split(",") if mode]
     p50, p99 = block_latency(A, args, torch, sk, args.mode)
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -563,6 +684,12 @@ def main():
             print("[bench] CPU baseline (reference on a bounded sample)", file=sys.stderr,
                   flush=True)
             cpu = cpu_baseline(A_host, args)
+        del A_host
+    study = accuracy_study(torch, sk) if args.study else None
+    configs = []
+    for w in [x for x in args.host_configs.split(",") if x]:
+        print(f"[bench] host-streamed workload {w}", file=sys.stderr, flush=True)
+        configs.append(host_workload(args, torch, sk, "host-" + w))
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -597,6 +724,9 @@ def main():
                              "H += a^T g": r["gemm2_ms"] * r["nblocks"],
                              "finalize": r["finalize_ms"]},
              "accuracy": acc.get(r["mode"])} for r in results[1:]],
+        "power_scheme": power,
+        "accuracy_study": study,
+        "configs": configs,
     }
     print(json.dumps(line))
 
