@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--kron", default="500,200,100,200", help="m1,m2,n1,n2 with m=m1*m2, n=n1*n2")
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--l", type=int, default=100)
-    ap.add_argument("--b", type=int, default=10)
+    ap.add_argument("--b", type=int, default=0,
+                    help="column block width of the finalize loop; 0 = l (one block, fastest)")
     ap.add_argument("--block", type=int, default=4096)
     ap.add_argument("--check", default="full", choices=["full", "none"],
                     help="FP64 reference accuracy check on the whole workload")
@@ -626,6 +627,8 @@ def cpu_baseline(A_host, args):
 
 def main():
     args = parse()
+    if args.b <= 0:
+        args.b = args.l
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))

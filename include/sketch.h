@@ -78,7 +78,10 @@ typedef struct {
   int32_t k;               /* number of singular triplets returned, 1 <= k <= l */
   int32_t l;               /* sketch width; l = t*b "slightly larger than k" (Alg. 4 step 2),
                               l <= n, l <= 128 */
-  int32_t b;               /* column block width of the finalize loop; l % b == 0, 1 <= b <= 32 */
+  int32_t b;               /* column block width of the finalize loop (Alg. 4 steps 9-15); divides l,
+                              1 <= b <= 32 or b = l.  With b = l the loop is one block: Cholesky
+                              QR twice of the whole G and B = R^-T H^T (fastest on the GPU; the
+                              workspace then holds a second m x l FP64 matrix) */
   int32_t compute;         /* sketch_dtype compute mode */
   int32_t host_slots;      /* device staging slots for pinned-host sources: 0 (device sources
                               only) or 2..4 (copies overlap compute on a side stream) */

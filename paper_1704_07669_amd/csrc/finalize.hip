@@ -19,6 +19,7 @@
 // then a one-sided (Hestenes) Jacobi SVD of R_B^T in one workgroup: R_B^T J = W with orthogonal
 // columns, so B = (W S^-1) S (Q_B J)^T, i.e. U~ = W S^-1, V = Q_B J, U = Q U~.
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -1732,6 +1733,7 @@ void tsqr(Ctx& cx, double* X, int64_t ldx, int64_t rows, int b, double* ws, doub
 struct Small {
   double *W, *T, *C, *Wn, *R1, *R2, *R, *X, *RB, *C1, *C2, *Jm, *Wm, *sig, *Jk, *Wk, *sgn;
   double *sG, *wc;   // centring: s_G = G^T 1 and w = Omega'^T mu
+  double *Rg, *Rgi;  // one column block: R of G and its inverse
   int* perm; int* info;
 };
 Small carve_small(double* base, int l, int b) {
@@ -1747,6 +1749,7 @@ Small carve_small(double* base, int l, int b) {
   sm.perm = reinterpret_cast<int*>(take(l));
   sm.info = reinterpret_cast<int*>(take(4));
   sm.sG = take(l); sm.wc = take(l);
+  sm.Rg = take((int64_t)l * l); sm.Rgi = take((int64_t)l * l);
   return sm;
 }
 
@@ -1841,13 +1844,13 @@ void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, doub
 // Y = X R^-1 for the n x L column-major X and upper triangular R^-1 (row-major, leading dimension
 // L), in column slices of at most 16 (slice c0..c0+w-1 only needs rows 0..c0+w-1 of R^-1).
 void right_trmul(Ctx& cx, double* Y, int64_t ldy, const double* X, int64_t ldx, int64_t rows,
-                 int L, const double* Rinv) {
+                 int L, const double* Rinv, int ldr = 0) {
   if (!cx.ok() || L <= 0 || rows <= 0) return;
   const int ny = cdiv(L, 16);
   const dim3 g((unsigned)cdiv<int64_t>(rows, kNnThreads), ny), blk(kNnThreads);
   hipLaunchKernelGGL((k_nn_update<double, 16>), g, blk, 0, cx.s, Y, ldy, (const double*)nullptr,
-                     0, X, ldx, L, Rinv, L, 16, rows, 1.0, (const Ctrl*)nullptr, 0,
-                     (const double*)nullptr, L);
+                     0, X, ldx, L, Rinv, ldr > 0 ? ldr : L, 16, rows, 1.0, (const Ctrl*)nullptr,
+                     0, (const double*)nullptr, L);
   cx.chk();
 }
 
@@ -1960,7 +1963,7 @@ hipError_t finalize_prepare() {
 size_t finalize_small_elems(int l, int b) {
   (void)b;
   const int64_t P = (int64_t)l * 32;
-  int64_t e = 6 * rup<int64_t>(P, 32) + 4 * 1024 + 5 * rup<int64_t>((int64_t)l * l + l, 32) +
+  int64_t e = 6 * rup<int64_t>(P, 32) + 4 * 1024 + 7 * rup<int64_t>((int64_t)l * l + l, 32) +
               5 * rup<int64_t>(l, 32) + 32;
   return (size_t)e + 1024;
 }
@@ -2086,11 +2089,85 @@ hipError_t centre_sketch(int mode, void* G, int64_t ldg, int64_t m, double* H, i
   return cx.err;
 }
 
+// ---------------------------------------------------------------- one column block (b = l)
+// Alg. 4 steps 9-15 with t = 1: Y_1 = G, [Q, R] = qr(G) with the re-orthogonalisation of Sec. 3.2
+// (here: Cholesky QR applied twice), the rank guard on R's diagonal, and B = R^{-T} H^T, which is
+// Eq. 9 with Q and B still empty.  Every step is a tall product or reduction over all rows at
+// once instead of t = l / b dependent rounds of them.  Returns false when Cholesky QR2's tests
+// reject G (a pivot below 1e-8 of its diagonal entry, or a second factor more than 1e-6 from I):
+// the caller then runs the blocked loop, whose Householder TSQR fallback handles any G.
+template <typename GT>
+__global__ void k_widen(const GT* __restrict__ G, int64_t ldg, int64_t rows, int l,
+                        double* __restrict__ X, int64_t ldx) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < rows * l;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = q / rows, r = q - c * rows;
+    X[c * ldx + r] = (double)G[c * ldg + r];
+  }
+}
+
+bool one_block(Ctx& cx, FinalizeArgs& f, const Small& sm, Ctrl& hc) {
+  const int l = f.l;
+  const int64_t m = f.m, n = f.n;
+  hipStream_t stream = cx.s;
+  double* X = f.Q2;                       // G in FP64, later the basis Q
+  int* fail = sm.info + 1;
+  int* ill = sm.info + 2;
+  if (f.mode == M_F64)
+    hipLaunchKernelGGL(k_widen<double>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
+                       (const double*)f.G, f.ldg, m, l, X, f.ldq);
+  else
+    hipLaunchKernelGGL(k_widen<float>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
+                       (const float*)f.G, f.ldg, m, l, X, f.ldq);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, fail, 0);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, ill, 0);
+  cx.chk();
+  // Q1 = G R1^-1 with R1 = chol(G^T G); Q = Q1 R2^-1 with R2 = chol(Q1^T Q1)
+  gram_upper(cx, X, f.ldq, m, l, f.red_ws, sm.Jm);
+  chol(cx, sm.Jm, l, 0.0, sm.Wk, sm.Jk, fail, 1e-8, 0.0, ill);
+  right_trmul(cx, f.Q, f.ldq, X, f.ldq, m, l, sm.Jk);
+  gram_upper(cx, f.Q, f.ldq, m, l, f.red_ws, sm.Jm);
+  chol(cx, sm.Jm, l, 0.0, sm.Wm, sm.RB, fail, 0.0, 1e-6, ill);
+  right_trmul(cx, X, f.ldq, f.Q, f.ldq, m, l, sm.RB);
+  // R = R2 R1 and R^-1 = R1^-1 R2^-1 (upper triangular, lower parts zero)
+  if (cx.ok()) cx.err = launch_fill_f64(sm.Rg, (int64_t)l * l, 0.0, stream);
+  if (cx.ok()) cx.err = launch_fill_f64(sm.Rgi, (int64_t)l * l, 0.0, stream);
+  if (cx.ok()) {
+    hipLaunchKernelGGL(k_trmm_upper, dim3(l), dim3(JMAX), 0, stream, sm.Wm, sm.Wk, sm.Rg, l);
+    hipLaunchKernelGGL(k_trmm_upper, dim3(l), dim3(JMAX), 0, stream, sm.Jk, sm.RB, sm.Rgi, l);
+  }
+  cx.chk();
+  // one wait: the acceptance flags and the diagonal of R (the rank guard sizes what follows)
+  std::vector<double> R((size_t)l * l);
+  int flags[2] = {1, 1};
+  if (cx.ok())
+    cx.err = hipMemcpyAsync(flags, fail, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (cx.ok())
+    cx.err = hipMemcpyAsync(R.data(), sm.Rg, R.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            stream);
+  if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+  if (!cx.ok() || flags[0] != 0 || flags[1] != 0) return false;
+  // rank guard: the leading columns whose R diagonal exceeds tau R_00
+  const double r0 = R[0];
+  int keep = 0;
+  while (keep < l && fabs(R[(size_t)keep * l + keep]) > kGuardTau * r0) ++keep;
+  if (!(r0 > 0.0)) keep = 0;
+  // B^T = H R^-1 over the kept columns (the leading block of R^-1 inverts R's leading block)
+  right_trmul(cx, f.Bt, f.ldb, f.H, f.ldh, n, keep, sm.Rgi, l);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, &f.ctrl->l_eff, keep);
+  cx.chk();
+  f.Q = X;
+  hc.l_eff = keep;
+  f.path_loop = 2;
+  return cx.ok();
+}
+
 hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   Ctx cx{stream};
-  const int b = f.b, l = f.l, t = l / b;
+  const int l = f.l;
+  int b = f.b;
   const int64_t m = f.m, n = f.n;
-  Small sm = carve_small(f.small, l, b);
+  Small sm = carve_small(f.small, l, b <= 32 ? b : 32);
   Ctrl* ctrl = f.ctrl;
   if (f.centre) {
     hipError_t e = centre_sketch(f.mode, const_cast<void*>(f.G), f.ldg, m,
@@ -2099,10 +2176,27 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
     if (e != hipSuccess) return e;
   }
 
+  // ---------------- one column block when b = l (see one_block)
+  Ctrl hc{};
+  bool done = false;
+  if (b == l && f.Q2 != nullptr && !f.force_loop) {
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, 1, l);
+    cx.chk();
+    done = cx.ok() && one_block(cx, f, sm, hc);
+    if (!cx.ok()) return cx.err;
+  }
+  // the blocked loop works on blocks of at most 32 columns: a wider b (b = l) that one_block did
+  // not take runs as the widest divisor of l that fits
+  if (b > 32) {
+    int d = 32;
+    while (l % d != 0) --d;
+    b = d;
+  }
+  const int t = l / b;
+
   // ---------------- column-block loop (Alg. 4 steps 9-15).  Cholesky QR of the blocks first; if a
   // block was flagged as too ill-conditioned for it, the loop is repeated with Householder TSQR.
-  Ctrl hc{};
-  for (int attempt = f.force_loop ? 1 : 0; attempt < 2 && cx.ok(); ++attempt) {
+  for (int attempt = f.force_loop ? 1 : 0; attempt < 2 && cx.ok() && !done; ++attempt) {
     const bool chol = (attempt == 0);
     hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l);
     cx.chk();
@@ -2325,7 +2419,7 @@ __global__ void k_scale_cols(double* __restrict__ X, int64_t ldx, int64_t rows, 
 
 hipError_t run_power_omega(PowerArgs& p, hipStream_t stream) {
   Ctx cx{stream};
-  const int L = p.l, b = p.b;
+  const int L = p.l, b = p.b <= 32 ? p.b : 32;   // Householder TSQR blocks of at most 32 columns
   const int64_t n = p.n;
   Small sm = carve_small(p.small, p.l, p.b);
   int* fail = sm.info + 1;

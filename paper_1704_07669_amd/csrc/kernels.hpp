@@ -117,6 +117,7 @@ struct FinalizeArgs {
   const double* H; int64_t ldh;      // n-side, column-major
   const double* om64; int64_t ldo;   // Omega' (FP64), n-side
   double* Q; int64_t ldq;            // m x l basis
+  double* Q2 = nullptr;              // second m x l FP64 matrix (ld ldq) for b = l, or null
   double* Bt; double* Qb; int64_t ldb;   // B^T and the Q factor of B^T, n-side
   double* tsqr_ws; int64_t tsqr_ws_elems;
   double* red_ws; int64_t red_ws_elems;
@@ -129,7 +130,8 @@ struct FinalizeArgs {
   int32_t force_rb = 0;              // in: 1 Gram-Schmidt + TSQR for R_B, 2 shifted Cholesky QR3,
                                      //     3 QR2 formed, then treated as not accepted,
                                      //     4 as 3 with QR2's first pivot failing
-  int32_t path_loop = -1;            // out: 0 Cholesky QR of the blocks, 1 Householder TSQR
+  int32_t path_loop = -1;            // out: 0 Cholesky QR of the blocks, 1 Householder TSQR,
+                                     //      2 one block (b = l) by Cholesky QR2
   int32_t path_rb = -1;              // out: 0 Cholesky QR2 of B^T, 2 shifted Cholesky QR3,
                                      //      1 Gram-Schmidt + TSQR
 };

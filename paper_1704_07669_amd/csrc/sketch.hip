@@ -79,7 +79,7 @@ struct Layout {
   int LP, NT, t, splits_max;
   int64_t NP, MCAP, RBP, LDST, NQ;
   int64_t off_ctrl, off_fp8, off_om64, off_omc, off_G, off_H, off_P1, off_Gop, off_P2, off_cnt, off_stage, off_fp8q,
-      off_Q, off_Bt, off_Qb, off_tsqr, off_red, off_small, off_mu, total;
+      off_Q, off_Q2, off_Bt, off_Qb, off_tsqr, off_red, off_small, off_mu, total;
   int64_t stage_slot_bytes;
   int64_t tsqr_elems, red_elems;
 };
@@ -92,7 +92,8 @@ const char* validate(const sketch_config* c) {
   if (c->max_block_rows > (int64_t)1 << 30) return "max_block_rows too large";
   if (c->l < 1 || c->l > 128) return "l must be in [1, 128]";
   if (c->k < 1 || c->k > c->l) return "k must be in [1, l]";
-  if (c->b < 1 || c->b > 32 || c->l % c->b != 0) return "b must be in [1, 32] and divide l";
+  if (c->b < 1 || (c->b > 32 && c->b != c->l) || c->l % c->b != 0)
+    return "b must divide l and be in [1, 32] or equal l";
   if (c->l > c->n) return "l must be <= n";
   if (c->compute < SKETCH_F64 || c->compute > SKETCH_FP8_E4M3) return "unknown compute mode";
   if (c->host_slots != 0 && (c->host_slots < 2 || c->host_slots > 4))
@@ -123,7 +124,7 @@ Layout plan(const sketch_config* c) {
       c->host_slots > 0 ? rup<int64_t>(c->max_block_rows * L.LDST * src_size(c->host_src), kAlign)
                         : 0;
   const int64_t rows_max = std::max<int64_t>(L.MCAP, L.NP);
-  L.tsqr_elems = (int64_t)tsqr_workspace_elems(rows_max, c->b);
+  L.tsqr_elems = (int64_t)tsqr_workspace_elems(rows_max, std::min(c->b, 32));
   L.red_elems = (int64_t)reduce_workspace_elems(rows_max, c->l, c->b);
   int64_t off = 0;
   auto take = [&](int64_t bytes) { const int64_t r = off; off += rup<int64_t>(bytes, kAlign); return r; };
@@ -141,6 +142,7 @@ Layout plan(const sketch_config* c) {
   L.off_stage = take(L.stage_slot_bytes * c->host_slots);
   L.off_fp8q = take(c->compute == SKETCH_FP8_E4M3 ? c->max_block_rows * L.NQ : 0);
   L.off_Q = take((int64_t)L.LP * L.MCAP * 8);
+  L.off_Q2 = take(c->b == c->l ? (int64_t)L.LP * L.MCAP * 8 : 0);   // one-block finalize
   L.off_Bt = take((int64_t)L.LP * L.NP * 8);
   L.off_Qb = take((int64_t)L.LP * L.NP * 8);
   L.off_tsqr = take(L.tsqr_elems * 8);
@@ -343,6 +345,7 @@ sketch_status finalize_core(sketch_t h, double* S_dev, double* U_dev, int64_t ld
   f.ldo = L.NP;
   f.Q = h->at<double>(L.off_Q);
   f.ldq = L.MCAP;
+  f.Q2 = (c.b == c.l) ? h->at<double>(L.off_Q2) : nullptr;
   f.Bt = h->at<double>(L.off_Bt);
   f.Qb = h->at<double>(L.off_Qb);
   f.ldb = L.NP;
