@@ -6,11 +6,14 @@ the input rounded once to the compute format, and the reference is then run on A
 exactly.  These functions build A' and Omega' from their definitions:
 
 * FP32: IEEE round-to-nearest-even of the FP64 value.
-* BF16: the upper 16 bits of the FP32 value after round-to-nearest-even.
+* BF16: round-to-nearest-even of the value itself to 8 significant bits (the BF16 grid), taken
+  from its FP64 representation; for FP32 inputs this is the usual RNE of the FP32 value.  Values
+  below 2^-126 in magnitude (BF16's subnormal range) go through FP32 first.
 * BF16X2: hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in FP32); the operand is hi + lo.
 * FP8 E4M3 (OCP, bias 7, largest finite 448): round-to-nearest-even with a power-of-two block
   scale 2^e chosen as the largest with amax * 2^e <= 448, so scaling itself is exact.
-* Omega' for BF16/BF16X2 is bf16(fp32(Omega)); for FP8 it is fp8(32 * fp32(Omega)) / 32.
+* Omega' for BF16/BF16X2 is bf16(Omega), rounded once from FP64; for FP8 it is
+  fp8(32 * fp32(Omega)) / 32.
 """
 import numpy as np
 
@@ -19,13 +22,24 @@ def round_fp32(x):
     return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
-def round_bf16(x):
-    """bf16 RNE of fp32(x), returned as float64."""
-    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
-    u = f.view(np.uint32).astype(np.uint64)
+def _round_bf16_from_fp32(f):
+    u = np.ascontiguousarray(f, dtype=np.float32).view(np.uint32).astype(np.uint64)
     bias = np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))
     r = ((u + bias) & np.uint64(0xFFFF0000)).astype(np.uint32)
     return r.view(np.float32).astype(np.float64)
+
+
+def round_bf16(x):
+    """bf16 RNE of x (one rounding from its FP64 value), returned as float64: the FP64 bit pattern
+    rounded to nearest even at 45 bits below its significand's top, i.e. to 8 significant bits."""
+    d = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    u = d.view(np.uint64)
+    bias = np.uint64((1 << 44) - 1) + ((u >> np.uint64(45)) & np.uint64(1))
+    r = ((u + bias) & ~np.uint64((1 << 45) - 1)).view(np.float64)
+    small = ~(np.abs(d) >= 2.0 ** -126)
+    if np.any(small):
+        r = np.where(small, _round_bf16_from_fp32(d.astype(np.float32)), r)
+    return r
 
 
 def split_bf16x2(x):

@@ -94,7 +94,16 @@ __global__ void k_omega_quantize(int64_t n, int64_t NP, int l, int LP, double* _
     } else if constexpr (MODE == M_F32) {
       const float w = (float)x; xq = w; v = w;
     } else if constexpr (MODE == M_BF16 || MODE == M_BF16X2) {
-      const __bf16 h = to_bf16((float)x); xq = (double)from_bf16(h); v = h;
+      // one rounding from FP64 to the BF16 grid (8 significant bits, nearest even) on the bit
+      // pattern, then an exact conversion; values below 2^-126 (BF16 subnormals) go through FP32
+      double r = x;
+      if (fabs(x) >= 0x1p-126 && fabs(x) < 0x1p127) {
+        uint64_t u = (uint64_t)__double_as_longlong(x);
+        u += 0xFFFFFFFFFFFull + ((u >> 45) & 1ull);
+        u &= ~0x1FFFFFFFFFFFull;
+        r = __longlong_as_double((long long)u);
+      }
+      const __bf16 h = to_bf16((float)r); xq = (double)from_bf16(h); v = h;
     } else {
       const float sx = fminf(fmaxf((float)x * 32.0f, -448.0f), 448.0f);
       const uint32_t byte = pack_fp8x2(sx, 0.0f) & 0xffu;

@@ -85,8 +85,13 @@ class KronMatrix:
         V = np.einsum("ck,dk->cdk", self.V1[:, a], self.V2[:, b]).reshape(self.n, count)
         return V
 
+    def _check_rows(self, r0: int, count: int):
+        if r0 < 0 or count < 0 or r0 + count > self.m:
+            raise ValueError(f"rows {r0} .. {r0 + count - 1} outside the matrix's {self.m} rows")
+
     def rows(self, r0: int, count: int) -> np.ndarray:
         """Rows r0 .. r0+count-1 in float64 (NumPy)."""
+        self._check_rows(r0, count)
         r = np.arange(r0, r0 + count)
         r1, r2 = r // self.m2, r % self.m2
         M = self.U1[r1][:, :, None] * self.U2[r2][:, None, :] * self.S[None]
@@ -99,6 +104,7 @@ class KronMatrix:
         Returns a float64 tensor, or writes float32 rows into ``out`` (count x n) when given.
         """
         import torch
+        self._check_rows(r0, count)      # an index past m would be read out of bounds on the device
         cache = getattr(self, "_tcache", None)
         if cache is None or cache[0] != str(device):
             t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=device)

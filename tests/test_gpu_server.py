@@ -99,17 +99,19 @@ def test_alone_and_in_the_mix(gpu_lib, data):
     assert np.array_equal(alone[0][1], mix[0][1])
 
 
-def test_matches_reference(gpu_lib, data):
-    d = data[0]
-    srv = _server(gpu_lib, "f32")
-    res, _ = _serve(gpu_lib, srv, [d])
+@pytest.mark.parametrize("mode", ["f32", "bf16", "bf16x2"])
+def test_matches_reference(gpu_lib, data, mode):
+    """Each stream of a mixed group against the reference on its own rounded rows and Omega'."""
+    srv = _server(gpu_lib, mode)
+    res, _ = _serve(gpu_lib, srv, data)
     srv.close()
-    _, _, _, Om = _single(gpu_lib, d, "f32")
-    ref = oracle.single_pass_pca(quantized_blocks(d["A"], d["blocks"], "f32"), Om, K, B)
-    S, V, rank = res[0]
-    assert rank == ref.rank
-    assert np.max(oracle.rel_sigma_error(S, ref.S)) < 2e-4
-    assert oracle.sin_theta_max(ref.V, V) < 2e-3
+    for i, d in enumerate(data):
+        _, _, _, Om = _single(gpu_lib, d, mode)
+        ref = oracle.single_pass_pca(quantized_blocks(d["A"], d["blocks"], mode), Om, K, B)
+        S, V, rank = res[i]
+        assert rank == ref.rank
+        assert np.max(oracle.rel_sigma_error(S, ref.S)) < 2e-4
+        assert oracle.sin_theta_max(ref.V, V) < 2e-3
 
 
 def test_admission_by_footprint(gpu_lib, data):

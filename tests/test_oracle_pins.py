@@ -317,6 +317,29 @@ def test_rounding_matches_torch_conversions():
     assert np.array_equal(oracle.round_fp8_e4m3(y), ty)
 
 
+def test_bf16_rounding_of_fp64_values_is_one_rne_step():
+    """FP64 inputs (Omega) are rounded once to the BF16 grid: the result has at most 8 significant
+    bits, no grid point is nearer, and ties go to the even neighbour (brute force on the grid)."""
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 4, 20000)
+    # planted exact ties and near-ties between two BF16 neighbours
+    base = np.array([0.267578125, 1.3984375, -0.75390625, 3.0])
+    step = 2.0 ** (np.floor(np.log2(np.abs(base))) - 7)
+    x = np.concatenate([x, base + step / 2, base + step / 2 * (1 - 2.0 ** -40),
+                        base + step / 2 * (1 + 2.0 ** -40)])
+    r = oracle.round_bf16(x)
+    e = np.floor(np.log2(np.abs(r)))
+    q = 2.0 ** (e - 7)                                   # grid spacing at r
+    assert np.all(np.abs(r / q - np.rint(r / q)) == 0)   # on the grid
+    for cand in (r - q, r + q, r - q / 2, r + q / 2):     # neighbours (spacing halves below 2^e)
+        ok = np.abs(cand / (2.0 ** (np.floor(np.log2(np.abs(cand))) - 7)))
+        ongrid = ok == np.rint(ok)
+        assert np.all(~ongrid | (np.abs(x - r) <= np.abs(x - cand)))
+    ties = np.abs(np.abs(x - r) - q / 2) == 0
+    assert np.any(ties)
+    assert np.all((np.rint(np.abs(r[ties]) / q[ties]) % 2) == 0)   # ties to even
+
+
 def test_bf16x2_split_is_near_exact():
     rng = np.random.default_rng(13)
     x = rng.standard_normal(10000).astype(np.float32).astype(np.float64)
