@@ -172,13 +172,17 @@ def serving_bench(args, torch, sk, mode):
             r0 += int(rows)
         return out
 
-    def run(arrivals):
-        srv = sk.Server(l, 32768, int(draws.m.max()), 4096, budget, compute=mode, src="f32",
-                        max_group=16, worker=True)
-        sids = [srv.open(int(draws.n[s_]), int(draws.m[s_]), k, b, 20000 + s_)[0]
-                for s_ in range(nstr)]
+    def run(arrivals, state_budget=None, opens=None):
+        srv = sk.Server(l, 32768, int(draws.m.max()), 4096, state_budget or budget, compute=mode,
+                        src="f32", max_group=16, worker=True)
+        sids = [None] * nstr
+        if opens is None:
+            for s_ in range(nstr):
+                sids[s_] = srv.open(int(draws.n[s_]), int(draws.m[s_]), k, b, 20000 + s_)[0]
         events = []
         for s_ in range(nstr):
+            if opens is not None:
+                events.append((opens[s_], s_, -1, None))        # the stream request itself
             for i, blk in enumerate(blocks_of(s_)):
                 events.append((0.0 if arrivals is None else arrivals[s_][i], s_, i, blk))
         events.sort(key=lambda e: (e[0], e[1], e[2]))
@@ -213,10 +217,14 @@ def serving_bench(args, torch, sk, mode):
                 drain()
                 if at - now > 2e-4:
                     time.sleep(min(at - now, 1e-3) * 0.5)
+            if i < 0:
+                sids[s_] = srv.open(int(draws.n[s_]), int(draws.m[s_]), k, b, 20000 + s_)[0]
+                continue
             tk = srv.submit(sids[s_], blk)
             owner[tk] = s_
             last_tk[s_] = tk
-        while len(lat) < len(events):
+        nblk = sum(1 for e in events if e[2] >= 0)
+        while len(lat) < nblk:
             drain()
             time.sleep(1e-4)
         t_pass = time.perf_counter() - t0
@@ -233,6 +241,8 @@ def serving_bench(args, torch, sk, mode):
                     mean_blocks_per_group=st["blocks"] / max(1, st["groups"]),
                     max_blocks_in_group=int(st["max_blocks_in_group"]),
                     finalized=int(st["finalized"]), state_peak_bytes=int(st["state_peak"]),
+                    state_budget_bytes=int(state_budget or budget),
+                    queued_peak=int(st["queued_peak"]),
                     median_rel_sigma_k_err_vs_known=float(np.median(errs)) if errs else None)
 
     sat = run(None)
@@ -246,9 +256,26 @@ def serving_bench(args, torch, sk, mode):
         gaps = rng.exponential(bytes_blk / rate)
         arrivals.append(np.cumsum(gaps))
     loaded = run(arrivals)
+    # S2: a state budget of about 16 average footprints, and the stream requests themselves
+    # arriving as a Poisson process at the rate that offers rho X in the long run; each stream's
+    # blocks then arrive as a Poisson process at rho X / 16, so about 16 streams are open at a
+    # time and admission (FIFO, by footprint) and continuous batching both engage
+    rng2 = np.random.default_rng(30003)
+    mean_bytes = total_bytes / nstr
+    lam = args.serving_rho * sat["gbps"] * 1e9 / mean_bytes
+    opens = np.cumsum(rng2.exponential(1.0 / lam, nstr))
+    per_stream = args.serving_rho * sat["gbps"] * 1e9 / 16.0
+    arr2 = []
+    for s_ in range(nstr):
+        bytes_blk = 4.0 * draws.blocks[s_] * int(draws.n[s_])
+        arr2.append(opens[s_] + np.cumsum(rng2.exponential(bytes_blk / per_stream)))
+    budget2 = int(16 * np.mean(foot))
+    admission = run(arr2, state_budget=budget2, opens=opens)
     pools.clear()
     return {"mode": mode, "streams": nstr, "data_gb": total_bytes / 1e9, "k": k, "l": l, "b": b,
-            "saturated": sat, "rho": args.serving_rho, "poisson": loaded}
+            "saturated": sat, "rho": args.serving_rho, "poisson": loaded,
+            "admission_s2": admission,
+            "latency": "block submit (host) to the GPU completion of its grouped launch"}
 
 
 def h2d_peak(torch, gib=4):

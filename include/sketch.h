@@ -303,6 +303,7 @@ typedef struct {
   int64_t blocks;          /* blocks processed */
   int64_t max_blocks_in_group;
   int64_t finalized;       /* streams finalized */
+  int64_t queued_peak;     /* most streams ever waiting for memory at once */
 } sketch_server_stats;
 
 /* Device bytes the server's workspace must hold (shared scratch + state budget); 0 if invalid. */
@@ -334,8 +335,11 @@ sketch_status sketch_server_submit(sketch_server_t s, uint64_t stream_id, const 
  * groups, admit waiting streams, launch at most one new group.  *launched = blocks launched. */
 sketch_status sketch_server_step(sketch_server_t s, int32_t* launched);
 
-/* Up to `cap` finished blocks since the last call: their tickets and latencies in seconds (from
- * submit to the host seeing the group's completion).  *count = entries written. */
+/* Up to `cap` finished blocks since the last call: their tickets and latencies in seconds, from
+ * the block's submit (host clock) to the completion of its grouped launch on the GPU (the group's
+ * completion event, converted to host time through an anchor event recorded on the idle stream
+ * at creation and refreshed every 10 s when the stream is idle; the conversion may read late by
+ * the few microseconds of one stream synchronisation).  *count = entries written. */
 sketch_status sketch_server_poll(sketch_server_t s, uint64_t* tickets, double* latency_s,
                                  int32_t cap, int32_t* count);
 

@@ -62,7 +62,7 @@ class sketch_server_config(ctypes.Structure):
 class sketch_server_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "active", "queued", "state_used", "state_peak", "groups", "blocks", "max_blocks_in_group",
-        "finalized")]
+        "finalized", "queued_peak")]
 
 
 _lib = None

@@ -275,6 +275,8 @@ struct sketch_server_s {
   bool table_used[kTableRing] = {};
   int next_table = 0;
   std::vector<std::pair<uint64_t, double>> done;   // (ticket, latency)
+  hipEvent_t anchor = nullptr;       // recorded on the idle launch stream at host time t_anchor
+  double t_anchor = 0.0;
   sketch_server_stats st{};
 
   std::mutex fin_mu;                 // the finalize scratch
@@ -341,7 +343,13 @@ sketch_status retire_locked(sketch_server_t s) {
     hipError_t e = hipEventQuery(g.ev);
     if (e == hipErrorNotReady) break;
     if (e != hipSuccess) return s->dev_fail(e, "group completion");
-    const double t = now_s();
+    // the group's completion time on the GPU, in host time through the anchor event
+    float ms = 0.f;
+    double t = now_s();
+    if (s->anchor && hipEventElapsedTime(&ms, s->anchor, g.ev) == hipSuccess)
+      t = s->t_anchor + 1e-3 * (double)ms;
+    else
+      (void)hipGetLastError();
     for (size_t i = 0; i < g.blocks.size(); ++i) {
       auto it = s->streams.find(g.blocks[i].first);
       if (it != s->streams.end()) it->second.inflight--;
@@ -350,6 +358,14 @@ sketch_status retire_locked(sketch_server_t s) {
     s->ev_pool.push_back(g.ev);
     s->inflight.pop_front();
     any = true;
+  }
+  // refresh the anchor while the stream is idle, so the float milliseconds of the event
+  // intervals stay fine-grained
+  if (any && s->inflight.empty() && s->anchor && now_s() - s->t_anchor > 10.0) {
+    hipError_t e = hipEventRecord(s->anchor, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(s->anchor);
+    if (e != hipSuccess) return s->dev_fail(e, "latency anchor");
+    s->t_anchor = now_s();
   }
   if (any) s->cv_done.notify_all();
   return SKETCH_OK;
@@ -439,7 +455,7 @@ sketch_status launch_group_locked(sketch_server_t s, int32_t* launched) {
   if (e == hipSuccess) {
     if (s->ev_pool.empty()) {
       hipEvent_t ev;
-      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      e = hipEventCreate(&ev);          // timed: its timestamp gives the blocks' latency
       if (e == hipSuccess) s->ev_pool.push_back(ev);
     }
   }
@@ -551,7 +567,10 @@ sketch_status sketch_server_create(sketch_server_t* out, const sketch_server_con
   if (e == hipSuccess)
     e = launch_fill_f64(s->at<double>(z.off_small), (int64_t)finalize_small_elems(cfg->l, 32), 0.0,
                         s->stream);
+  if (e == hipSuccess) e = hipEventCreate(&s->anchor);
+  if (e == hipSuccess) e = hipEventRecord(s->anchor, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  s->t_anchor = now_s();
   if (e != hipSuccess) {
     const char* msg = hipGetErrorString(e);
     s->sticky = SKETCH_E_DEVICE;
@@ -579,6 +598,7 @@ sketch_status sketch_server_open(sketch_server_t s, const sketch_config* cfg, ui
   const uint64_t id = st.id;
   s->streams.emplace(id, st);
   s->waitq.push_back(id);
+  s->st.queued_peak = std::max<int64_t>(s->st.queued_peak, (int64_t)s->waitq.size());
   sketch_status r = admit_waiting_locked(s);
   if (r != SKETCH_OK) return r;
   *stream_id = id;
@@ -783,6 +803,7 @@ sketch_status sketch_server_destroy(sketch_server_t s) {
   }
   for (auto& g : s->inflight) (void)hipEventDestroy(g.ev);
   for (auto ev : s->ev_pool) (void)hipEventDestroy(ev);
+  if (s->anchor) (void)hipEventDestroy(s->anchor);
   for (int i = 0; i < kTableRing; ++i)
     if (s->table_ev[i]) (void)hipEventDestroy(s->table_ev[i]);
   if (s->host_tables) (void)hipHostFree(s->host_tables);
