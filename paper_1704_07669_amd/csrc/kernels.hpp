@@ -68,7 +68,10 @@ struct PassGroup {
   int64_t wg1_total, wg2_total, wgr_total, wgh_total;
 };
 constexpr int kNpAlign = 512;        // n padding: multiple of every k-chunk of g = a Omega
-constexpr int kGemm2MaxSplits = 8;   // most row splits of one strip of a^T g
+constexpr int kGemm2MaxSplits = 32;  // most row splits of one strip of a^T g
+// Longest FP32 accumulation chains of the precision modes (FP32, BF16X2): rows of a per row-split
+// partial of a^T g, columns per k split of g = a Omega.
+constexpr int64_t kPrecRows = 512, kPrecCols = 4096;
 // Fills the launch parameters of `it` (nrows, n, A, lda and the pointers set) for a P1 capacity of
 // `splits_max` partials.
 void plan_item(PassItem& it, int mode, int src, int splits_max);
@@ -79,6 +82,8 @@ int64_t gemm2_strips(int64_t n, int mode);
 int64_t gemm2_strip_width(int mode);
 // Most (strip, row split) partial tiles of a^T g one item can have (sizes the partial scratch).
 int64_t gemm2_partial_tiles_max();
+// Bound on (strip, row split) partial tiles of one item of at most `rows` rows and n columns.
+int64_t gemm2_partial_tiles_bound(int64_t n, int64_t rows, int mode);
 hipError_t launch_gemm1(const PassGroup& g, hipStream_t s);
 hipError_t launch_reduce1(const PassGroup& g, hipStream_t s);
 // a^T g, plus (for items split over rows) the fixed-order sum of the row-split partials into H

@@ -1106,7 +1106,22 @@ int64_t g2_target() { return kG2TargetWgs; }
 
 int64_t gemm2_strip_width(int mode) { return mode == M_F64 ? 16 * g2_shape(mode).VC : 256; }
 int64_t gemm2_strips(int64_t n, int mode) { return cdiv<int64_t>(n, gemm2_strip_width(mode)); }
+// Precision modes (FP32 and BF16X2, whose operands carry 24 and 16 bits) bound the length of
+// their FP32 accumulation chains: at most kPrecRows rows of a per row-split partial of a^T g
+// and at most kPrecCols columns per k split of g = a Omega.  The partials are summed in FP64
+// (H) or in a fixed order (G).  Alg. 4 amplifies a relative sketch error by (sigma_1 /
+// sigma_j)^2 (Eq. 9), so the chain length shows in the result: on sigma_j = j^-2, 250000 x 10000,
+// l = 100, 8192-row blocks, the FP32 mode's relative sigma_k error against FP64 is 1.6e-3 with
+// the throughput shape's 1366-row partials and 9e-6 with 512-row ones.
+bool prec_mode(int mode) { return mode == M_F32 || mode == M_BF16X2; }
 int64_t gemm2_partial_tiles_max() { return std::max<int64_t>(g2_target(), 1024 / WAVES); }
+int64_t gemm2_partial_tiles_bound(int64_t n, int64_t rows, int mode) {
+  int64_t t = gemm2_partial_tiles_max();
+  if (prec_mode(mode))
+    t = std::max<int64_t>(t, gemm2_strips(n, mode) *
+                                 std::min<int64_t>(kGemm2MaxSplits, cdiv<int64_t>(rows, kPrecRows)));
+  return t;
+}
 
 // Launch shape of one item.
 //   g = a Omega: row tiles of 128 rows times k splits, as many splits as keep the launch within
@@ -1120,6 +1135,8 @@ void plan_item(PassItem& it, int mode, int src, int splits_max) {
   it.vec_ok = ((((uintptr_t)it.A) % 16) == 0) && ((it.lda * es) % 16 == 0);
   it.row_tiles = (int)cdiv<int64_t>(it.nrows, ROW_TILE);
   int splits = (int)std::max<int64_t>(1, std::min<int64_t>(splits_max, kG1Wgs / it.row_tiles));
+  if (prec_mode(mode))
+    splits = (int)std::max<int64_t>(splits, std::min<int64_t>(splits_max, cdiv<int64_t>(it.n, kPrecCols)));
   it.kchunk = rup<int64_t>(cdiv<int64_t>(it.n, splits), kG1KAlign);
   it.splits = (int)cdiv<int64_t>(it.n, it.kchunk);
   const G2Shape sh = g2_shape(mode);
@@ -1142,8 +1159,11 @@ void plan_item(PassItem& it, int mode, int src, int splits_max) {
     // least 8 steps of rows
     const int64_t strips = cdiv<int64_t>(it.n, 256);
     const int64_t want = g2_target() / strips;
-    const int rsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kGemm2MaxSplits, want,
-                                                                    steps / 8}));
+    int rsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kGemm2MaxSplits, want,
+                                                              steps / 8}));
+    if (prec_mode(mode))
+      rsplit = (int)std::max<int64_t>(rsplit, std::min<int64_t>(kGemm2MaxSplits,
+                                                               cdiv<int64_t>(it.nrows, kPrecRows)));
     it.rchunk = (int)rup<int64_t>(cdiv<int64_t>(it.nrows, rsplit), (int64_t)KR);
     it.rsplit = (int)cdiv<int64_t>(it.nrows, it.rchunk);
     it.strips = (int)strips;

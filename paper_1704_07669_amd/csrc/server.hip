@@ -103,12 +103,15 @@ int64_t up(int64_t v) { return rup<int64_t>(v, kAlign); }
 int64_t item_bound(int64_t rows, int64_t n, int LP, int mode) {
   const int64_t rows16 = rup<int64_t>(rows, 16);
   const int64_t row_tiles = cdiv<int64_t>(rows, 128);
-  const int64_t split_rows = std::min<int64_t>(kSplitsCap * rows16, 512 * 128 + 128 * row_tiles + 16);
+  // (the precision modes take at least n / kPrecCols splits)
+  const int64_t split_rows = std::min<int64_t>(
+      kSplitsCap * rows16, std::max<int64_t>(512 * 128 + 128 * row_tiles + 16,
+                                             cdiv<int64_t>(n, kPrecCols) * rows16));
   const int g = acc_bytes(mode);
   const int64_t p1 = split_rows * LP * g;
   const int64_t gop = (int64_t)LP * rows16 * g;
-  const int64_t p2 = gemm2_partial_tiles_max() * (int64_t)LP * gemm2_strip_width(mode) * g;
-  (void)n;
+  const int64_t p2 = gemm2_partial_tiles_bound(n, rows, mode) * (int64_t)LP *
+                     gemm2_strip_width(mode) * g;
   return up(p1) + up(gop) + up(p2);
 }
 
