@@ -291,7 +291,9 @@ typedef struct {
   int64_t max_block_rows;  /* largest block */
   int64_t state_bytes;     /* device memory for resident stream states (the admission budget) */
   int32_t worker;          /* 1: a library thread schedules; 0: the caller calls sketch_server_step */
-  int32_t pad;
+  int32_t host_slots;      /* device staging slots for pinned-host blocks (0: device rows only); each
+                              holds max_block_rows x max_n rows of the src format, copied on a
+                              library-owned stream while earlier groups compute */
 } sketch_server_config;
 
 typedef struct {
@@ -327,16 +329,32 @@ sketch_status sketch_server_open(sketch_server_t s, const sketch_config* cfg, ui
 
 /* Queues the next nrows rows of a stream (device pointer, src format, ld >= n).  *ticket
  * identifies the block in sketch_server_poll.  E_STATE after the stream's finalize began;
- * E_CAPACITY past its m_capacity or max_block_rows. */
+ * E_CAPACITY past its m_capacity or max_block_rows.  Same as sketch_server_submit_ex with
+ * src_is_device = 1 and no arrival time. */
 sketch_status sketch_server_submit(sketch_server_t s, uint64_t stream_id, const void* rows,
                                    int64_t nrows, int64_t ld, uint64_t* ticket);
+
+/* As sketch_server_submit, with the rows either in device memory (src_is_device = 1) or in pinned
+ * host memory (0; needs host_slots > 0, else E_INVAL; pageable memory is rejected with E_INVAL):
+ * a host block is copied into a free staging slot when its group forms, on the library's copy
+ * stream, and the group's kernels wait for the copy.  arrival_s: the block's arrival time on
+ * sketch_server_clock(), from which its latency is measured (< 0: the submit time).  The caller
+ * keeps the rows unchanged until sketch_server_poll reports the ticket or the stream's finalize
+ * returns. */
+sketch_status sketch_server_submit_ex(sketch_server_t s, uint64_t stream_id, const void* rows,
+                                      int32_t src_is_device, int64_t nrows, int64_t ld,
+                                      double arrival_s, uint64_t* ticket);
+
+/* Seconds on the monotonic clock the server stamps submits and completions with. */
+double sketch_server_clock(void);
 
 /* One scheduler round (worker = 0 only; with a worker it returns E_STATE): retire finished
  * groups, admit waiting streams, launch at most one new group.  *launched = blocks launched. */
 sketch_status sketch_server_step(sketch_server_t s, int32_t* launched);
 
 /* Up to `cap` finished blocks since the last call: their tickets and latencies in seconds, from
- * the block's submit (host clock) to the completion of its grouped launch on the GPU (the group's
+ * the block's arrival (its submit, or the arrival_s given) to the completion of its grouped
+ * launch on the GPU (the group's
  * completion event, converted to host time through an anchor event recorded on the idle stream
  * at creation and refreshed every 10 s when the stream is idle; the conversion may read late by
  * the few microseconds of one stream synchronisation).  *count = entries written. */

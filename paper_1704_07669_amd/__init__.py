@@ -29,7 +29,8 @@ EXPORTED = [
     "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
     "sketch_destroy", "sketch_last_error",
     "sketch_server_workspace_size", "sketch_server_stream_bytes", "sketch_server_create",
-    "sketch_server_open", "sketch_server_submit", "sketch_server_step", "sketch_server_poll",
+    "sketch_server_open", "sketch_server_submit", "sketch_server_submit_ex", "sketch_server_clock",
+    "sketch_server_step", "sketch_server_poll",
     "sketch_server_finalize", "sketch_server_get_stats", "sketch_server_destroy",
 ]
 
@@ -55,7 +56,7 @@ class sketch_server_config(ctypes.Structure):
         ("compute", ctypes.c_int32), ("src", ctypes.c_int32), ("l", ctypes.c_int32),
         ("max_group", ctypes.c_int32), ("max_n", ctypes.c_int64), ("max_m", ctypes.c_int64),
         ("max_block_rows", ctypes.c_int64), ("state_bytes", ctypes.c_int64),
-        ("worker", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("worker", ctypes.c_int32), ("host_slots", ctypes.c_int32),
     ]
 
 
@@ -115,6 +116,8 @@ def load_library(path=None):
         "sketch_server_create": (I32, [ctypes.POINTER(P), scfgp, P, ctypes.c_size_t, P]),
         "sketch_server_open": (I32, [P, cfgp, ctypes.POINTER(U64), ctypes.POINTER(I32)]),
         "sketch_server_submit": (I32, [P, U64, P, I64, I64, ctypes.POINTER(U64)]),
+        "sketch_server_submit_ex": (I32, [P, U64, P, I32, I64, I64, D, ctypes.POINTER(U64)]),
+        "sketch_server_clock": (D, []),
         "sketch_server_step": (I32, [P, ctypes.POINTER(I32)]),
         "sketch_server_poll": (I32, [P, ctypes.POINTER(U64), ctypes.POINTER(D), I32,
                                      ctypes.POINTER(I32)]),
@@ -446,6 +449,19 @@ def sketch_server_submit(srv, sid, rows):
     return tk.value
 
 
+def sketch_server_submit_ex(srv, sid, rows, arrival_s=-1.0):
+    """rows: a CUDA tensor or a pinned CPU tensor (row-major)."""
+    tk = ctypes.c_uint64()
+    _check(load_library().sketch_server_submit_ex(srv, sid, _ptr(rows), int(rows.is_cuda),
+                                                  rows.shape[0], rows.stride(0), float(arrival_s),
+                                                  ctypes.byref(tk)))
+    return tk.value
+
+
+def sketch_server_clock():
+    return load_library().sketch_server_clock()
+
+
 def sketch_server_step(srv):
     n = ctypes.c_int32()
     _check(load_library().sketch_server_step(srv, ctypes.byref(n)))
@@ -485,18 +501,19 @@ class Server:
     the workspace (group scratch, finalize scratch and that budget) is one torch allocation."""
 
     def __init__(self, l, max_n, max_m, max_block_rows, state_bytes, compute="f32", src="f32",
-                 max_group=16, worker=True, stream=None):
+                 max_group=16, worker=True, stream=None, host_slots=0):
         import torch
         load_library()
         self.cfg = sketch_server_config(
             compute=DTYPES[compute], src=DTYPES[src], l=l, max_group=max_group, max_n=max_n,
             max_m=max_m, max_block_rows=max_block_rows, state_bytes=state_bytes,
-            worker=int(bool(worker)), pad=0)
+            worker=int(bool(worker)), host_slots=host_slots)
         self.l, self.compute, self.src = l, compute, src
         ws = sketch_server_workspace_size(self.cfg)
         self.workspace = torch.empty(ws, dtype=torch.uint8, device="cuda")
         self.h = sketch_server_create(self.cfg, self.workspace, stream)
         self.meta = {}
+        self._held = {}   # ticket -> (stream id, rows) until retired
         self.closed = False
 
     def stream_config(self, n, m, k, b, seed, max_block_rows=None, want_u=False):
@@ -514,16 +531,39 @@ class Server:
         self.meta[sid] = cfg
         return sid, admitted
 
-    def submit(self, sid, rows):
-        if rows.dim() != 2 or rows.stride(1) != 1 or not rows.is_cuda:
-            raise ValueError("rows must be a row-major 2-D CUDA tensor")
-        return sketch_server_submit(self.h, sid, rows)
+    def submit(self, sid, rows, arrival_s=-1.0):
+        """rows: a row-major 2-D CUDA tensor, or a pinned CPU tensor when host_slots > 0, of the
+        server's source type.  The server keeps a reference to it until its ticket is polled or
+        its stream finalized (the library reads the rows asynchronously).  arrival_s, on the
+        clock of ``clock()``, is when the block arrived; by default the submit time."""
+        import torch
+        if rows.dim() != 2 or rows.stride(1) != 1:
+            raise ValueError("rows must be a row-major 2-D tensor")
+        want = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[self.src]
+        if rows.dtype != want:
+            raise ValueError(f"rows must be {want}, got {rows.dtype}")
+        if rows.is_cuda and arrival_s < 0:
+            tk = sketch_server_submit(self.h, sid, rows)
+        else:
+            tk = sketch_server_submit_ex(self.h, sid, rows, arrival_s)
+        self._held[tk] = (sid, rows)
+        return tk
+
+    @staticmethod
+    def clock():
+        """The host clock (seconds) that arrival times and latencies are measured on."""
+        return sketch_server_clock()
 
     def step(self):
         return sketch_server_step(self.h)
 
     def poll(self, cap=4096):
-        return sketch_server_poll(self.h, cap)
+        """(ticket, latency_s) of retired blocks: arrival to the GPU completion of the grouped
+        launch that consumed the block."""
+        out = sketch_server_poll(self.h, cap)
+        for tk, _ in out:
+            self._held.pop(tk, None)
+        return out
 
     def finalize(self, sid, want_u=None):
         import torch
@@ -534,6 +574,8 @@ class Server:
         U = torch.empty(cfg.m_capacity, cfg.k, dtype=torch.float64, device="cuda") if want_u else None
         rank = sketch_server_finalize(self.h, sid, S, U, V)
         del self.meta[sid]
+        for tk in [t for t, (s, _) in self._held.items() if s == sid]:
+            del self._held[tk]
         return S, V, U, rank
 
     def stats(self):

@@ -80,8 +80,11 @@ const char* validate_server(const sketch_server_config* c) {
   if (c->max_block_rows < 1 || c->max_block_rows > (1 << 20)) return "max_block_rows out of range";
   if (c->state_bytes < 0) return "state_bytes must be >= 0";
   if (c->worker != 0 && c->worker != 1) return "worker must be 0 or 1";
+  if (c->host_slots < 0 || c->host_slots > 64) return "host_slots must be in [0, 64]";
   return nullptr;
 }
+
+int src_bytes_of(int src) { return src == SKETCH_F64 ? 8 : src == SKETCH_F32 ? 4 : 2; }
 
 struct Sizes {
   int LP, NT;
@@ -89,8 +92,9 @@ struct Sizes {
   int64_t group_bytes;    // all group slots
   int64_t cnt_per_slot;   // counters per group slot
   int64_t off_group, off_cnt, off_table, off_Q, off_Bt, off_Qb, off_tsqr, off_red,
-      off_small, off_arena, total;
+      off_small, off_arena, off_stage, total;
   int64_t NPmax, MCAPmax, tsqr_elems, red_elems;
+  int64_t LDST, stage_slot_bytes;   // staging slots for pinned-host blocks (rows padded to LDST)
 };
 
 int64_t up(int64_t v) { return rup<int64_t>(v, kAlign); }
@@ -139,6 +143,9 @@ Sizes sizes(const sketch_server_config* c) {
   z.off_red = take(z.red_elems * 8);
   z.off_small = take((int64_t)finalize_small_elems(c->l, 32) * 8);
   z.off_arena = take(c->state_bytes);
+  z.LDST = rup<int64_t>(c->max_n, 64);
+  z.stage_slot_bytes = up(c->max_block_rows * z.LDST * src_bytes_of(c->src));
+  z.off_stage = take(z.stage_slot_bytes * c->host_slots);
   z.total = off;
   return z;
 }
@@ -226,7 +233,8 @@ struct Block {
   const void* rows;
   int64_t nrows, ld;
   uint64_t ticket;
-  double t_submit;
+  double t_submit;         // arrival time the latency is measured from (host clock)
+  bool host;               // pinned host rows, copied into a staging slot at launch
 };
 
 enum { S_QUEUED = 0, S_ACTIVE = 1, S_FINALIZING = 2 };
@@ -249,6 +257,7 @@ struct Group {
   int table_slot;
   std::vector<std::pair<uint64_t, uint64_t>> blocks;   // (stream id, ticket)
   std::vector<double> t_submit;
+  std::vector<int> stage_slots;                        // staging slots its host blocks hold
 };
 
 }  // namespace
@@ -259,6 +268,9 @@ struct sketch_server_s {
   uint8_t* ws = nullptr;
   hipStream_t stream = nullptr;      // grouped launches (caller's)
   hipStream_t fin_stream = nullptr;  // finalize (library's)
+  hipStream_t copy_stream = nullptr; // host-to-device copies of pinned-host blocks (library's)
+  std::vector<char> stage_busy;      // staging slots held by an in-flight group
+  std::vector<hipEvent_t> stage_ev;  // per slot: its copy finished
   int device = 0;
   sketch_status sticky = SKETCH_OK;
 
@@ -358,6 +370,7 @@ sketch_status retire_locked(sketch_server_t s) {
       if (it != s->streams.end()) it->second.inflight--;
       s->done.push_back({g.blocks[i].second, t - g.t_submit[i]});
     }
+    for (int sl : g.stage_slots) s->stage_busy[sl] = 0;
     s->ev_pool.push_back(g.ev);
     s->inflight.pop_front();
     any = true;
@@ -397,11 +410,22 @@ sketch_status launch_group_locked(sketch_server_t s, int32_t* launched) {
     Stream& st = s->streams.at(id);
     if (st.pending.empty()) continue;
     const Block& bk = st.pending.front();
+    // a pinned-host block needs a free staging slot; without one it waits for a later group
+    int stage = -1;
+    if (bk.host) {
+      for (int i = 0; i < c.host_slots; ++i)
+        if (!s->stage_busy[i]) { stage = i; break; }
+      if (stage < 0) continue;
+    }
     uint8_t* base = s->ws + z.off_arena + st.arena_off;
     uint8_t* grp = s->ws + z.off_group + scratch;
     PassItem it{};
     it.A = bk.rows;
     it.lda = bk.ld;
+    if (bk.host) {
+      it.A = s->ws + z.off_stage + (int64_t)stage * z.stage_slot_bytes;
+      it.lda = z.LDST;
+    }
     it.nrows = (int)bk.nrows;
     it.n = st.cfg.n;
     it.omc = base + st.lay.off_omc;
@@ -422,6 +446,18 @@ sketch_status launch_group_locked(sketch_server_t s, int32_t* launched) {
     const int64_t p2 = it.rsplit > 1
         ? up((int64_t)it.strips * it.rsplit * z.LP * gemm2_strip_width(c.compute) * g8) : 0;
     if (scratch + p1 + gop + p2 > z.group_bytes) break;   // the group is full
+    if (bk.host) {
+      // copy on the library's copy stream; the grouped launch waits for it
+      const int es = src_bytes_of(c.src);
+      hipError_t e = hipMemcpy2DAsync(const_cast<void*>(it.A), z.LDST * es, bk.rows, bk.ld * es,
+                                      st.cfg.n * es, bk.nrows, hipMemcpyHostToDevice,
+                                      s->copy_stream);
+      if (e == hipSuccess) e = hipEventRecord(s->stage_ev[stage], s->copy_stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->stage_ev[stage], 0);
+      if (e != hipSuccess) return s->dev_fail(e, "host block copy");
+      s->stage_busy[stage] = 1;
+      g.stage_slots.push_back(stage);
+    }
     it.P1 = grp;
     it.Gop = grp + p1;
     it.P2 = (it.rsplit > 1) ? (void*)(grp + p1 + gop) : nullptr;
@@ -558,6 +594,12 @@ sketch_status sketch_server_create(sketch_server_t* out, const sketch_server_con
   s->arena.reset(cfg->state_bytes);
   e = hipGetDevice(&s->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->fin_stream, hipStreamNonBlocking);
+  if (e == hipSuccess && cfg->host_slots > 0)
+    e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+  s->stage_busy.assign(cfg->host_slots, 0);
+  s->stage_ev.assign(cfg->host_slots, nullptr);
+  for (int i = 0; i < cfg->host_slots && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&s->stage_ev[i], hipEventDisableTiming);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&s->host_tables,
                       sizeof(PassItem) * (size_t)kTableRing * cfg->max_group, hipHostMallocDefault);
@@ -612,8 +654,27 @@ sketch_status sketch_server_open(sketch_server_t s, const sketch_config* cfg, ui
 
 sketch_status sketch_server_submit(sketch_server_t s, uint64_t stream_id, const void* rows,
                                    int64_t nrows, int64_t ld, uint64_t* ticket) {
+  return sketch_server_submit_ex(s, stream_id, rows, 1, nrows, ld, -1.0, ticket);
+}
+
+double sketch_server_clock(void) { return now_s(); }
+
+sketch_status sketch_server_submit_ex(sketch_server_t s, uint64_t stream_id, const void* rows,
+                                      int32_t src_is_device, int64_t nrows, int64_t ld,
+                                      double arrival_s, uint64_t* ticket) {
   if (sketch_status r = check_server(s)) return r;
   if (!rows) return set_error(SKETCH_E_INVAL, "rows is NULL");
+  if (src_is_device != 0 && src_is_device != 1)
+    return set_error(SKETCH_E_INVAL, "src_is_device must be 0 or 1");
+  if (!src_is_device) {
+    if (s->cfg.host_slots == 0) return set_error(SKETCH_E_INVAL, "server has no host staging slots");
+    hipPointerAttribute_t at;
+    memset(&at, 0, sizeof(at));
+    if (hipPointerGetAttributes(&at, rows) != hipSuccess || at.type != hipMemoryTypeHost) {
+      (void)hipGetLastError();
+      return set_error(SKETCH_E_INVAL, "host rows must be pinned (hipHostMalloc)");
+    }
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->streams.find(stream_id);
   if (it == s->streams.end()) return set_error(SKETCH_E_INVAL, "unknown stream %llu", (unsigned long long)stream_id);
@@ -626,7 +687,8 @@ sketch_status sketch_server_submit(sketch_server_t s, uint64_t stream_id, const 
   if (st.rows_submitted + nrows > st.cfg.m_capacity)
     return set_error(SKETCH_E_CAPACITY, "m_capacity %lld exceeded", (long long)st.cfg.m_capacity);
   const uint64_t tk = s->next_ticket++;
-  st.pending.push_back({rows, nrows, ld, tk, now_s()});
+  st.pending.push_back({rows, nrows, ld, tk, arrival_s >= 0.0 ? arrival_s : now_s(),
+                        src_is_device == 0});
   st.rows_submitted += nrows;
   if (ticket) *ticket = tk;
   s->cv_work.notify_one();
@@ -807,6 +869,12 @@ sketch_status sketch_server_destroy(sketch_server_t s) {
   for (auto& g : s->inflight) (void)hipEventDestroy(g.ev);
   for (auto ev : s->ev_pool) (void)hipEventDestroy(ev);
   if (s->anchor) (void)hipEventDestroy(s->anchor);
+  for (auto ev : s->stage_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (s->copy_stream) {
+    (void)hipStreamSynchronize(s->copy_stream);
+    (void)hipStreamDestroy(s->copy_stream);
+  }
   for (int i = 0; i < kTableRing; ++i)
     if (s->table_ev[i]) (void)hipEventDestroy(s->table_ev[i]);
   if (s->host_tables) (void)hipHostFree(s->host_tables);

@@ -184,3 +184,102 @@ def test_server_errors(gpu_lib, data):
         big = _server(gpu_lib, "f32", state_bytes=1 << 20)
         big.open(d["n"], d["m"], K, B, 1)
     srv.close()
+
+
+def _host_server(sk, mode, worker, host_slots):
+    return sk.Server(L, max_n=4096, max_m=4096, max_block_rows=1024, state_bytes=1 << 30,
+                     compute=mode, src="f32", max_group=16, worker=worker, host_slots=host_slots)
+
+
+@pytest.mark.parametrize("mode,worker", [("f32", False), ("bf16", True), ("bf16x2", False)])
+def test_pinned_host_blocks(gpu_lib, data, mode, worker):
+    """Streams 0 and 2 submit pinned host rows, 1 and 3 device rows, through two staging slots
+    (fewer than the host blocks of one round, so host blocks wait for a slot): the staged copy
+    is the same rows, so every stream equals its single-handle result bit for bit."""
+    import torch
+    srv = _host_server(gpu_lib, mode, worker, host_slots=2)
+    host = {0: torch.from_numpy(data[0]["A"].astype(np.float32)).pin_memory(),
+            2: torch.from_numpy(data[2]["A"].astype(np.float32)).pin_memory()}
+    ids = [srv.open(d["n"], d["m"], K, B, d["seed"])[0] for d in data]
+    queues = []
+    for i, d in enumerate(data):
+        src = host[i] if i in host else d["At"]
+        queues.append(list(split_blocks(src, d["blocks"])))
+    while any(queues):
+        for i, q in enumerate(queues):
+            if q:
+                srv.submit(ids[i], q.pop(0))
+        if not worker:
+            srv.step()
+    res = {i: srv.finalize(ids[i]) for i in range(len(data))}
+    st = srv.stats()
+    srv.close()
+    assert st["finalized"] == len(data)
+    for i, d in enumerate(data):
+        S1, V1, r1, _ = _single(gpu_lib, d, mode)
+        S2, V2, _, r2 = res[i]
+        assert r1 == r2
+        assert np.array_equal(S1, S2.cpu().numpy())
+        assert np.array_equal(V1, V2.cpu().numpy())
+
+
+def test_pinned_host_padded_rows(gpu_lib, data):
+    """Host rows with a leading dimension above n (a column slice of a wider pinned matrix)."""
+    import torch
+    d = data[1]
+    wide = torch.zeros(d["m"], d["n"] + 37, dtype=torch.float32).pin_memory()
+    wide[:, 5:5 + d["n"]] = torch.from_numpy(d["A"].astype(np.float32))
+    srv = _host_server(gpu_lib, "f32", False, host_slots=1)
+    sid, _ = srv.open(d["n"], d["m"], K, B, d["seed"])
+    r0 = 0
+    for c in d["blocks"]:
+        srv.submit(sid, wide[r0:r0 + c, 5:5 + d["n"]])
+        srv.step()
+        r0 += c
+    S, V, _, _ = srv.finalize(sid)
+    srv.close()
+    S1, V1, _, _ = _single(gpu_lib, d, "f32")
+    assert np.array_equal(S1, S.cpu().numpy()) and np.array_equal(V1, V.cpu().numpy())
+
+
+def test_arrival_time_latency(gpu_lib, data):
+    """A block stamped as arrived 0.25 s before its submit reports at least 0.25 s of latency;
+    blocks stamped at submit report less than that on an idle server."""
+    import time
+    d = data[2]
+    srv = _host_server(gpu_lib, "f32", True, host_slots=1)
+    sid, _ = srv.open(d["n"], d["m"], K, B, d["seed"])
+    blocks = list(split_blocks(d["At"], d["blocks"]))
+    late = srv.submit(sid, blocks[0], arrival_s=srv.clock() - 0.25)
+    seen = {}
+    t_end = time.time() + 10
+    while late not in seen and time.time() < t_end:
+        seen.update(dict(srv.poll()))
+    fresh = [srv.submit(sid, b) for b in blocks[1:]]
+    srv.finalize(sid)
+    for _ in range(10):
+        seen.update(dict(srv.poll()))
+    srv.close()
+    assert seen[late] >= 0.25
+    assert all(0 <= seen[t] < 0.25 for t in fresh)
+
+
+def test_host_submit_errors(gpu_lib, data):
+    import torch
+    d = data[0]
+    rows = torch.from_numpy(d["A"][:100].astype(np.float32))
+    srv = _server(gpu_lib, "f32")                 # no staging slots
+    sid, _ = srv.open(d["n"], d["m"], K, B, 1)
+    with pytest.raises(gpu_lib.SketchError, match="no host staging slots"):
+        srv.submit(sid, rows.pin_memory())
+    srv.close()
+    srv = _host_server(gpu_lib, "f32", False, host_slots=1)
+    sid, _ = srv.open(d["n"], d["m"], K, B, 1)
+    with pytest.raises(gpu_lib.SketchError, match="pinned"):
+        srv.submit(sid, rows)                      # pageable
+    with pytest.raises(ValueError, match="float32"):
+        srv.submit(sid, d["At"][:10].double())
+    srv.submit(sid, rows.pin_memory())
+    _, _, _, rank = srv.finalize(sid)
+    srv.close()
+    assert rank == L

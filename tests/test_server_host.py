@@ -7,7 +7,7 @@ import paper_1704_07669_amd as sk
 
 def _srv(**kw):
     base = dict(compute=sk.F32, src=sk.F32, l=40, max_group=16, max_n=32768, max_m=200000,
-                max_block_rows=4096, state_bytes=4 << 30, worker=1, pad=0)
+                max_block_rows=4096, state_bytes=4 << 30, worker=1, host_slots=0)
     base.update(kw)
     return sk.sketch_server_config(**base)
 
@@ -45,6 +45,19 @@ def test_workspace_grows_with_budget_and_group():
     assert c > a
 
 
+def test_workspace_holds_the_staging_slots():
+    """Each pinned-host staging slot holds max_block_rows rows of max_n source elements, the
+    rows padded to 64 elements."""
+    a = sk.sketch_server_workspace_size(_srv())
+    for slots in (1, 3):
+        b = sk.sketch_server_workspace_size(_srv(host_slots=slots))
+        assert b - a == slots * _align(4096 * 32768 * 4)
+    a = sk.sketch_server_workspace_size(_srv(max_n=1000, src=sk.BF16, compute=sk.BF16))
+    b = sk.sketch_server_workspace_size(_srv(max_n=1000, src=sk.BF16, compute=sk.BF16,
+                                             host_slots=2))
+    assert b - a == 2 * _align(4096 * 1024 * 2)
+
+
 @pytest.mark.parametrize("bad,msg", [
     (dict(compute=sk.FP8_E4M3), "compute"),
     (dict(src=sk.BF16), "src"),
@@ -52,6 +65,8 @@ def test_workspace_grows_with_budget_and_group():
     (dict(max_group=0), "max_group"),
     (dict(max_n=10), "max_n"),
     (dict(worker=2), "worker"),
+    (dict(host_slots=-1), "host_slots"),
+    (dict(host_slots=65), "host_slots"),
 ])
 def test_server_config_rejected(bad, msg):
     with pytest.raises(sk.SketchError, match=msg):
