@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--serving-rho", type=float, default=0.8,
                     help="offered load of the Poisson phase, as a fraction of saturation")
     ap.add_argument("--serving-modes", default="f32,bf16")
+    ap.add_argument("--serving-host", type=int, default=1,
+                    help="1: also serve the streams from pinned host memory (first serving mode)")
     ap.add_argument("--power", default="bf16",
                     help="modes run with the power scheme P = 1 on the resident workload ('' = none)")
     ap.add_argument("--study", type=int, default=1,
@@ -136,7 +138,7 @@ def block_latency(A, args, torch, sk, mode):
     return float(np.percentile(full, 50)), float(np.percentile(full, 99))
 
 
-def serving_bench(args, torch, sk, mode):
+def serving_bench(args, torch, sk, mode, host_too=False):
     """64 concurrent streams (n uniform over the multiples of 1024 up to 32768, m uniform in
     [10000, 200000] rows, sigma_j = exp(-j/20) for j <= 256 and 0 beyond; k = 20, l = 40, b = 10;
     blocks uniform in [256, 4096] rows), each a stacked pool resident on the GPU.
@@ -164,17 +166,18 @@ def serving_bench(args, torch, sk, mode):
     budget = int(sum(foot) * 1.05) + (64 << 20)
     total_bytes = float(sum(4.0 * int(draws.m[s_]) * int(draws.n[s_]) for s_ in range(nstr)))
 
-    def blocks_of(s_):
+    def blocks_of(s_, host=None):
         r0, out = 0, []
+        pool = (host or pools)[s_]
         for rows in draws.blocks[s_]:
             a = r0 % 1024
-            out.append(pools[s_][a:a + int(rows)])
+            out.append(pool[a:a + int(rows)])
             r0 += int(rows)
         return out
 
-    def run(arrivals, state_budget=None, opens=None):
+    def run(arrivals, state_budget=None, opens=None, host=None):
         srv = sk.Server(l, 32768, int(draws.m.max()), 4096, state_budget or budget, compute=mode,
-                        src="f32", max_group=16, worker=True)
+                        src="f32", max_group=16, worker=True, host_slots=4 if host else 0)
         sids = [None] * nstr
         if opens is None:
             for s_ in range(nstr):
@@ -183,7 +186,7 @@ def serving_bench(args, torch, sk, mode):
         for s_ in range(nstr):
             if opens is not None:
                 events.append((opens[s_], s_, -1, None))        # the stream request itself
-            for i, blk in enumerate(blocks_of(s_)):
+            for i, blk in enumerate(blocks_of(s_, host)):
                 events.append((0.0 if arrivals is None else arrivals[s_][i], s_, i, blk))
         events.sort(key=lambda e: (e[0], e[1], e[2]))
         last_tk = {}
@@ -271,11 +274,29 @@ def serving_bench(args, torch, sk, mode):
         arr2.append(opens[s_] + np.cumsum(rng2.exponential(bytes_blk / per_stream)))
     budget2 = int(16 * np.mean(foot))
     admission = run(arr2, state_budget=budget2, opens=opens)
+    out = {"mode": mode, "streams": nstr, "data_gb": total_bytes / 1e9, "k": k, "l": l, "b": b,
+           "saturated": sat, "rho": args.serving_rho, "poisson": loaded,
+           "admission_s2": admission,
+           "latency": "block submit (host) to the GPU completion of its grouped launch"}
+    if host_too:
+        # the same streams with their pools in pinned host memory: every block crosses PCIe into
+        # one of 4 staging slots on the server's copy stream while earlier groups compute
+        hpools = [p.cpu().pin_memory() for p in pools]
+        pools.clear()
+        torch.cuda.empty_cache()
+        hsat = run(None, host=hpools)
+        arr3 = []
+        rng3 = np.random.default_rng(30005)
+        for s_ in range(nstr):
+            bytes_blk = 4.0 * draws.blocks[s_] * int(draws.n[s_])
+            rate = args.serving_rho * hsat["gbps"] * 1e9 * float(bytes_blk.sum()) / total_bytes
+            arr3.append(np.cumsum(rng3.exponential(bytes_blk / rate)))
+        hload = run(arr3, host=hpools)
+        hpools.clear()
+        torch._C._host_emptyCache()
+        out["host_pinned"] = {"staging_slots": 4, "saturated": hsat, "poisson": hload}
     pools.clear()
-    return {"mode": mode, "streams": nstr, "data_gb": total_bytes / 1e9, "k": k, "l": l, "b": b,
-            "saturated": sat, "rho": args.serving_rho, "poisson": loaded,
-            "admission_s2": admission,
-            "latency": "block submit (host) to the GPU completion of its grouped launch"}
+    return out
 
 
 def h2d_peak(torch, gib=4):
@@ -697,9 +718,15 @@ def main():
         for smode in [x for x in args.serving_modes.split(",") if x]:
             print(f"[bench] serving scenario, {args.serving_streams} streams, {smode}",
                   file=sys.stderr, flush=True)
-            serving.append(serving_bench(args, torch, sk, smode))
+            serving.append(serving_bench(args, torch, sk, smode,
+                                         host_too=bool(args.serving_host) and not serving))
             print(f"[bench] serving {smode}: saturated {serving[-1]['saturated']['gbps']:.1f} GB/s,"
                   f" p99 {serving[-1]['poisson']['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+            if "host_pinned" in serving[-1]:
+                hp = serving[-1]["host_pinned"]
+                print(f"[bench] serving {smode} from pinned host: saturated "
+                      f"{hp['saturated']['gbps']:.1f} GB/s, p99 {hp['poisson']['p99_ms']:.2f} ms",
+                      file=sys.stderr, flush=True)
             torch.cuda.empty_cache()
         A = A_keep
     if args.check == "full" or args.cpu_seconds > 0:

@@ -1013,10 +1013,15 @@ __global__ void k_rb_assemble(const double* __restrict__ C1, const double* __res
 // factorisation defined for cond(B) up to about 1/u and gives Q1 = B^T R1^-1 with a moderate
 // condition number; then Cholesky QR twice on Q1.  R_B = R3 R2 R1.  A pivot that is not positive
 // and finite in any pass sends the host to the Gram-Schmidt + TSQR path.
-constexpr int kCholThreads = 1024;
-constexpr int kCholSlots = JMAX / 32;        // rows / columns per thread of the 32 x 32 layout
+constexpr int kCholTG = 32;                  // threads in a kCholTG x kCholTG grid
+constexpr int kCholThreads = kCholTG * kCholTG;
+constexpr int kCholSlots = JMAX / kCholTG;   // rows / columns per thread
 
-size_t chol_lds_bytes(int L) { return ((size_t)L * (L + 1) + 2 * (size_t)L) * sizeof(double); }
+// L + 1 rows of L + 2 (row and column L: a sink for the clamped indices of partial tiles), then
+// rd[L] and dinv[L]
+size_t chol_lds_bytes(int L) {
+  return ((size_t)(L + 1) * (L + 2) + 2 * (size_t)L) * sizeof(double);
+}
 
 // Gm (upper triangle read, row-major, leading dimension ldg) + s I = R^T R with R upper triangular
 // with a positive diagonal; s = shift_rel tr(Gm) when shift_rel > 0, else 0.  Writes R and, when
@@ -1024,12 +1029,14 @@ size_t chol_lds_bytes(int L) { return ((size_t)L * (L + 1) + 2 * (size_t)L) * si
 // is not positive and finite sets *fail (left as it was otherwise) and writes identity factors.
 // Conditioning tests, each setting *ill: ill_rel > 0, a pivot below ill_rel times the diagonal
 // entry of Gm it started from; dev_rel > 0, an entry of R farther than dev_rel from the identity.
-// One workgroup, threads in a 32 x 32 grid, each owning rows ty + 32 m and columns tx + 32 n of the
-// trailing block.  Right-looking factorisation in LDS, one row of R per step (rank-1 update of the
-// trailing upper triangle); then R^-1 by right-looking back substitution on the identity, one row
-// per step from the bottom, with R^-1[k][c] (k < c) kept in the strictly lower triangle at [c][k].
-// Every step loads its operands into registers before it stores, so the loads overlap, and ends
-// with its only barrier (scalings are deferred or applied where the values are read).
+// One workgroup, threads in a T x T grid (T = kCholTG), each owning rows ty + T m and columns
+// tx + T n of the trailing block, in T x T tiles.  Right-looking factorisation in LDS, two
+// pivots per step; then R^-1 by right-looking back substitution on the identity, two rows per
+// step from the bottom, with R^-1[k][c] (k < c) kept in the strictly lower triangle at [c][k].
+// Every loop bound is uniform: a step visits the tiles that meet its trailing block (in the
+// factorisation only those on or above the diagonal), and the rows and columns of a tile past
+// L - 1 are clamped to row / column L of the LDS matrix, a sink that nothing reads as data.  Every
+// step loads its operands into registers before it stores and ends with its only barrier.
 // The outputs of a failed factorisation: identity factors, so that the kernels that consume them
 // before the host reads the failure flag work on defined, finite values.
 __device__ __forceinline__ void chol_write_identity(double* __restrict__ R,
@@ -1049,16 +1056,15 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
                                                        int* __restrict__ fail, double ill_rel,
                                                        double dev_rel, int* __restrict__ ill,
                                                        int force_fail) {
-  extern __shared__ double a[];     // L x (L + 1), then rd[L] (diag of R), dinv[L] (its inverse)
-  const int LS = L + 1, tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
-  double* rd = a + (int64_t)L * LS;
+  extern __shared__ double a[];
+  const int LS = L + 2, tid = threadIdx.x, ty = tid / kCholTG, tx = tid % kCholTG;
+  double* rd = a + (int64_t)(L + 1) * LS;
   double* dinv = rd + L;
-  stage8(L * L, tid, kCholThreads,
-         [&](int idx) { return Gm[(int64_t)(idx / L) * ldg + idx % L]; },
-         [&](int idx, double v) {
-           const int i = idx / L, c = idx % L;
-           a[i * LS + c] = (c >= i) ? v : 0.0;
-         });
+  // the upper triangle of Gm; the strictly lower triangle and the sink row and column are zero
+  for (int idx = tid; idx < (L + 1) * LS; idx += kCholThreads) {
+    const int i = idx / LS, c = idx - i * LS;
+    a[idx] = (i < L && c < L && c >= i) ? Gm[(int64_t)i * ldg + c] : 0.0;
+  }
   __syncthreads();
   if (shift_rel > 0.0) {
     if (tid < 64) {
@@ -1079,7 +1085,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
   // Two pivots per step.  With t = a[j][j+1] / d0, row j+1 after pivot j is a[j+1][c] - t a[j][c]
   // and d1 is its diagonal entry; every thread forms what it needs of that row, and the trailing
   // rows take both rank-1 updates at once.  Row j+1 itself is stored one step later (by the
-  // threads of ty = 0), when no thread reads it any more, so a step still needs one barrier.
+  // threads of ty = 0), when no thread reads it any more.
   double w1[kCholSlots];                      // row j+1 of the previous step (ty == 0 threads)
   int wrow = -1;
   int j = 0;
@@ -1087,7 +1093,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     if (ty == 0 && wrow >= 0) {
 #pragma unroll
       for (int n = 0; n < kCholSlots; ++n) {
-        const int c = wrow + tx + 32 * n;
+        const int c = wrow + tx + kCholTG * n;
         if (c < L) a[wrow * LS + c] = w1[n];
       }
     }
@@ -1104,41 +1110,49 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     }
     if (tid == 0) { rd[j] = sqrt(d0); rd[j + 1] = sqrt(d1); }
     const double i0 = 1.0 / d0, i1 = 1.0 / d1;
+    const int j2 = j + 2;
+    const int mc = (L - j2 + kCholTG - 1) / kCholTG;         // tiles along the trailing block (uniform)
+    // the two pivot rows at this thread's columns c = j2 + tx + T n of the trailing block
     double c0[kCholSlots], c1[kCholSlots];
 #pragma unroll
     for (int n = 0; n < kCholSlots; ++n) {
-      const int c = j + 2 + tx + 32 * n;
-      const double x0 = c < L ? a[j * LS + c] : 0.0;
-      const double x1 = c < L ? a[(j + 1) * LS + c] : 0.0;
-      c0[n] = x0;
-      c1[n] = x1 - tj * x0;
+      if (n < mc) {
+        const int c = min(j2 + tx + kCholTG * n, L);
+        const double x0 = a[j * LS + c];
+        c0[n] = x0;
+        c1[n] = a[(j + 1) * LS + c] - tj * x0;
+      }
     }
     if (ty == 0) {
 #pragma unroll
       for (int n = 0; n < kCholSlots; ++n) {
-        const int c = j + 1 + tx + 32 * n;
+        const int c = j + 1 + tx + kCholTG * n;
         w1[n] = c < L ? a[(j + 1) * LS + c] - tj * a[j * LS + c] : 0.0;
       }
     }
     wrow = j + 1;
-    // a[i][c] -= a[j][i] a[j][c] / d0 + a1[i] a1[c] / d1 for j + 1 < i <= c < L
+    // a[i][c] -= a[j][i] a[j][c] / d0 + a1[i] a1[c] / d1 for j + 1 < i <= c < L; tiles (m, n)
+    // with n < m lie below the diagonal and are skipped, the diagonal tiles keep their lower part
 #pragma unroll
     for (int m = 0; m < kCholSlots; ++m) {
-      const int i = j + 2 + ty + 32 * m;
-      if (i < L) {
+      if (m < mc) {
+        const int i = min(j2 + ty + kCholTG * m, L);
         const double x0 = a[j * LS + i];
         const double r0 = x0 * i0;
         const double r1 = (a[(j + 1) * LS + i] - tj * x0) * i1;
         double v[kCholSlots];
 #pragma unroll
-        for (int n = 0; n < kCholSlots; ++n) {
-          const int c = j + 2 + tx + 32 * n;
-          v[n] = (c >= i && c < L) ? a[i * LS + c] : 0.0;
+        for (int n = m; n < kCholSlots; ++n) {
+          const int c = min(j2 + tx + kCholTG * n, L);
+          if (n < mc) v[n] = a[i * LS + c];
         }
 #pragma unroll
-        for (int n = 0; n < kCholSlots; ++n) {
-          const int c = j + 2 + tx + 32 * n;
-          if (c >= i && c < L) a[i * LS + c] = fma(-r1, c1[n], fma(-r0, c0[n], v[n]));
+        for (int n = m; n < kCholSlots; ++n) {
+          const int c = min(j2 + tx + kCholTG * n, L);
+          if (n < mc) {
+            const double u = fma(-r1, c1[n], fma(-r0, c0[n], v[n]));
+            a[i * LS + c] = (n > m || c >= i) ? u : v[n];
+          }
         }
       }
     }
@@ -1147,7 +1161,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
   if (ty == 0 && wrow >= 0) {
 #pragma unroll
     for (int n = 0; n < kCholSlots; ++n) {
-      const int c = wrow + tx + 32 * n;
+      const int c = wrow + tx + kCholTG * n;
       if (c < L) a[wrow * LS + c] = w1[n];
     }
   }
@@ -1174,9 +1188,10 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     // it; X[i][c] = rhs[i][c] / R_ii, then rhs[k][c] -= R[k][i] X[i][c] for k < i, c >= i.  The
     // right-hand sides stay unscaled in the strictly lower triangle (rhs[i][c] at [c][i]); X[i][c]
     // is formed where it is used, so a step needs one barrier.
-    // Two rows per step, i and i - 1: X[i-1][c] = (rhs[i-1][c] - R[i-1][i] X[i][c]) / R_{i-1,i-1}
-    // is formed where it is used, and the updated rhs[i-1][c] is stored one step later (by the
-    // threads of ty = 0), when no thread reads it any more.
+    // Two rows per step, i and h = i - 1: X[h][c] = (rhs[h][c] - R[h][i] X[i][c]) / R_hh is formed
+    // where it is used, and the updated rhs[h][c] is stored one step later (by the threads of
+    // ty = 0), when no thread reads it any more.  Thread (ty, tx) updates rows k = ty + T m < h
+    // at columns c = h + tx + T n.
     double w1[kCholSlots];
     int wcol = -1;                               // k of the stored-late entries rhs[k][c], c > k
     int i = L - 1;
@@ -1184,39 +1199,45 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
       if (ty == 0 && wcol >= 0) {
 #pragma unroll
         for (int n = 0; n < kCholSlots; ++n) {
-          const int c = wcol + tx + 32 * n;
+          const int c = wcol + tx + kCholTG * n;
           if (c > wcol && c < L) a[c * LS + wcol] = w1[n];
         }
       }
       const int h = i - 1;
       const double di = dinv[i], dh = dinv[h];
       const double rhi = a[h * LS + i];          // R[i-1][i]
+      const int nc = (L - h + kCholTG - 1) / kCholTG;          // column tiles from h (uniform)
+      const int mk = (h + kCholTG - 1) / kCholTG;              // row tiles below h (uniform)
       double xi[kCholSlots], xh[kCholSlots];
 #pragma unroll
       for (int n = 0; n < kCholSlots; ++n) {
-        const int c = h + tx + 32 * n;
-        const double yi = (c > i && c < L) ? a[c * LS + i] * di : (c == i ? di : 0.0);
-        const double rh = (c > h && c < L) ? a[c * LS + h] - rhi * yi : 0.0;
-        xi[n] = yi;
-        xh[n] = (c == h) ? dh : rh * dh;
-        if (ty == 0) w1[n] = rh;
+        if (n < nc) {
+          const int c = h + tx + kCholTG * n;
+          const int cc = min(c, L);
+          const double yi = (c > i && c < L) ? a[cc * LS + i] * di : (c == i ? di : 0.0);
+          const double rh = (c > h && c < L) ? a[cc * LS + h] - rhi * yi : 0.0;
+          xi[n] = yi;
+          xh[n] = (c == h) ? dh : rh * dh;
+          if (ty == 0) w1[n] = rh;
+        }
       }
       wcol = h;
 #pragma unroll
       for (int m = 0; m < kCholSlots; ++m) {
-        const int k = ty + 32 * m;
-        if (k < h) {
-          const double rki = a[k * LS + i], rkh = a[k * LS + h];
+        if (m < mk) {
+          const int k = min(ty + kCholTG * m, L);     // rows k >= h go to the sink row
+          const int kk = k < h ? k : L;
+          const double rki = a[kk * LS + i], rkh = a[kk * LS + h];
           double v[kCholSlots];
 #pragma unroll
           for (int n = 0; n < kCholSlots; ++n) {
-            const int c = h + tx + 32 * n;
-            v[n] = c < L ? a[c * LS + k] : 0.0;
+            const int c = min(h + tx + kCholTG * n, L);
+            if (n < nc) v[n] = a[c * LS + kk];
           }
 #pragma unroll
           for (int n = 0; n < kCholSlots; ++n) {
-            const int c = h + tx + 32 * n;
-            if (c < L) a[c * LS + k] = fma(-rkh, xh[n], fma(-rki, xi[n], v[n]));
+            const int c = min(h + tx + kCholTG * n, L);
+            if (n < nc) a[c * LS + kk] = fma(-rkh, xh[n], fma(-rki, xi[n], v[n]));
           }
         }
       }
@@ -1225,7 +1246,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
     if (ty == 0 && wcol >= 0) {
 #pragma unroll
       for (int n = 0; n < kCholSlots; ++n) {
-        const int c = wcol + tx + 32 * n;
+        const int c = wcol + tx + kCholTG * n;
         if (c > wcol && c < L) a[c * LS + wcol] = w1[n];
       }
     }
@@ -1269,6 +1290,11 @@ __global__ __launch_bounds__(JMAX) void k_trmm_upper(const double* __restrict__ 
 
 __global__ void k_set_int(int* p, int v) {
   if (threadIdx.x == 0) *p = v;
+}
+
+// out[i] = R[i][i] for the L x L row-major R.
+__global__ void k_diag(const double* __restrict__ R, int L, double* __restrict__ out) {
+  for (int i = threadIdx.x; i < L; i += blockDim.x) out[i] = R[(int64_t)i * L + i];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1318,13 +1344,18 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
                                                            int* __restrict__ perm,
                                                            double* __restrict__ nrm) {
   extern __shared__ double M[];           // N columns x CS, then the pair table
-  __shared__ int rotated;
+  __shared__ int rotated, large;
   __shared__ double nrm2[JMAX];           // squared column norms
   constexpr int LPP = kJacobiLpp, LPAD = LPP * EPL, CS = jacobi_cs(LPAD);
   const int N = (L + 1) & ~1;
   uint8_t* pairs = reinterpret_cast<uint8_t*>(M + (int64_t)N * CS);   // (N-1) x N/2 x {p, q}
   const double tol = (double)L * 2.220446049250313e-16;
   const double tol2 = tol * tol;
+  // Convergence is quadratic at the end: once every pair of a sweep starts with a relative
+  // inner product |g| / sqrt(a b) <= sqrt(tol) / 8, the rotations of a further sweep would move
+  // the columns by about N (sqrt(tol) / 8)^2 <= tol relative, the stopping threshold itself, so
+  // that sweep (which would only confirm convergence) is skipped.
+  const double stop2 = tol / 64.0;
   const int grp = threadIdx.x / LPP, gl = threadIdx.x % LPP;
   stage8(N * LPAD, threadIdx.x, kJacobiThreads,                        // M(:, col) = R_B(col, :)^T
          [&](int idx) {
@@ -1358,7 +1389,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
       v += dpp::mov<dpp::kHalfMirror>(v);
       if (gl == 0) nrm2[col] = v;
     }
-    if (threadIdx.x == 0) rotated = 0;
+    if (threadIdx.x == 0) { rotated = 0; large = 0; }
     __syncthreads();
     int p = 0, q = 0;
     if (active) { p = pairs[2 * grp]; q = pairs[2 * grp + 1]; }
@@ -1405,13 +1436,14 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
             nrm2[p] = fmax(fma(-t, g, a), 0.0);
             nrm2[q] = fma(t, g, bb);
             rotated = 1;
+            if (g * g > stop2 * (a * bb)) large = 1;
           }
         }
         p = pn; q = qn;
       }
       __syncthreads();
     }
-    if (!rotated) { ++sweep; break; }
+    if (!rotated || !large) { ++sweep; break; }
     __syncthreads();
   }
   if (threadIdx.x == 0) info[0] = sweep;
@@ -1928,8 +1960,7 @@ const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, 
   hipLaunchKernelGGL(k_trmm_upper, dim3(L), dim3(JMAX), 0, cx.s, Rs, sm.RB, Racc, L);
   cx.chk();
   int hfail = 1;
-  if (cx.ok()) cx.err = hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, cx.s);
-  if (cx.ok()) cx.err = hipStreamSynchronize(cx.s);
+  if (cx.ok()) cx.err = read_back(&hfail, fail, sizeof(int), cx.s, f.host_pin, f.host_ev);
   if (!cx.ok() || hfail != 0) return nullptr;
   return Racc;
 }
@@ -2137,20 +2168,24 @@ bool one_block(Ctx& cx, FinalizeArgs& f, const Small& sm, Ctrl& hc) {
     hipLaunchKernelGGL(k_trmm_upper, dim3(l), dim3(JMAX), 0, stream, sm.Jk, sm.RB, sm.Rgi, l);
   }
   cx.chk();
-  // one wait: the acceptance flags and the diagonal of R (the rank guard sizes what follows)
-  std::vector<double> R((size_t)l * l);
-  int flags[2] = {1, 1};
+  // one wait: the acceptance flags and the diagonal of R (the rank guard sizes what follows),
+  // read back together: the diagonal goes to sm.sG, which follows the flags in the small matrices
+  if (cx.ok()) {
+    hipLaunchKernelGGL(k_diag, dim3(1), dim3(JMAX), 0, stream, sm.Rg, l, sm.sG);
+    cx.chk();
+  }
+  const int64_t dofs = sm.sG - reinterpret_cast<const double*>(sm.info);
+  std::vector<double> rb((size_t)(dofs + l));
   if (cx.ok())
-    cx.err = hipMemcpyAsync(flags, fail, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
-  if (cx.ok())
-    cx.err = hipMemcpyAsync(R.data(), sm.Rg, R.size() * sizeof(double), hipMemcpyDeviceToHost,
-                            stream);
-  if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+    cx.err = read_back(rb.data(), sm.info, rb.size() * sizeof(double), stream, f.host_pin,
+                       f.host_ev);
+  const int* flags = reinterpret_cast<const int*>(rb.data()) + 1;   // info[1], info[2]
   if (!cx.ok() || flags[0] != 0 || flags[1] != 0) return false;
   // rank guard: the leading columns whose R diagonal exceeds tau R_00
-  const double r0 = R[0];
+  const double* diag = rb.data() + dofs;
+  const double r0 = diag[0];
   int keep = 0;
-  while (keep < l && fabs(R[(size_t)keep * l + keep]) > kGuardTau * r0) ++keep;
+  while (keep < l && fabs(diag[keep]) > kGuardTau * r0) ++keep;
   if (!(r0 > 0.0)) keep = 0;
   // B^T = H R^-1 over the kept columns (the leading block of R^-1 inverts R's leading block)
   right_trmul(cx, f.Bt, f.ldb, f.H, f.ldh, n, keep, sm.Rgi, l);
@@ -2278,8 +2313,7 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
     if (!cx.ok()) break;
     // one wait per loop: the rank decided on the device (it sizes the rest) and the Cholesky QR
     // flag (pad[0]), which sends the loop round again with Householder TSQR
-    cx.err = hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
-    if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+    cx.err = read_back(&hc, ctrl, sizeof(Ctrl), stream, f.host_pin, f.host_ev);
     if (!chol || !cx.ok() || hc.pad[0] == 0) break;
   }
   if (!cx.ok()) return cx.err;
@@ -2373,8 +2407,7 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
     if (!cx.ok()) return cx.err;
     if (rb_mode != 0) break;
     int hflags[2] = {1, 1};
-    cx.err = hipMemcpyAsync(hflags, sm.info + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
-    if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+    cx.err = read_back(hflags, sm.info + 1, 2 * sizeof(int), stream, f.host_pin, f.host_ev);
     if (!cx.ok()) return cx.err;
     if (hflags[0] == 0 && hflags[1] == 0 && f.force_rb != 3) break;
     rb_mode = 2;
@@ -2395,8 +2428,8 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
       }
     }
   }
-  if (!cx.ok()) return cx.err;
-  return hipStreamSynchronize(stream);
+  // the caller's read-back of the control block waits for the outputs
+  return cx.err;
 }
 
 // ---------------------------------------------------------------- power scheme, P = 1
@@ -2476,8 +2509,7 @@ hipError_t run_power_omega(PowerArgs& p, hipStream_t stream) {
     }
     if (!cx.ok()) return cx.err;
     int hflags[2] = {1, 1};
-    cx.err = hipMemcpyAsync(hflags, sm.info + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
-    if (cx.ok()) cx.err = hipStreamSynchronize(stream);
+    cx.err = read_back(hflags, sm.info + 1, 2 * sizeof(int), stream, p.host_pin, p.host_ev);
     if (!cx.ok()) return cx.err;
     if (hflags[0] == 0 && (route == 2 || hflags[1] == 0)) {
       p.route_used = route;

@@ -114,6 +114,14 @@ hipError_t launch_copy_omega_out(const double* om64, int64_t ldo, int64_t n, int
                                  int64_t ld, hipStream_t s);
 
 // ---------------------------------------------------------------- finalize (Alg. 4 steps 9-19)
+// The finalize's small read-backs to the host (acceptance flags, the rank): with a pinned host
+// buffer of kHostPinBytes and an event, a read-back copies into the buffer and waits by polling
+// the event, which returns within microseconds of the copy; with either missing it copies into
+// the destination and synchronises the stream.  bytes = 0 only waits for the stream's work.
+constexpr size_t kHostPinBytes = 4096;
+hipError_t read_back(void* dst, const void* src, size_t bytes, hipStream_t s, void* pin,
+                     hipEvent_t ev);
+
 struct FinalizeArgs {
   int mode;
   int64_t m, n;
@@ -139,6 +147,8 @@ struct FinalizeArgs {
                                      //      2 one block (b = l) by Cholesky QR2
   int32_t path_rb = -1;              // out: 0 Cholesky QR2 of B^T, 2 shifted Cholesky QR3,
                                      //      1 Gram-Schmidt + TSQR
+  void* host_pin = nullptr;          // pinned host staging of the read-backs (kHostPinBytes), or null
+  hipEvent_t host_ev = nullptr;      // event the read-backs poll, or null
 };
 // Power scheme with P = 1: Omega_2 = sqrt(n) orth(H) (FP64, column-major) for the second pass.
 struct PowerArgs {
@@ -151,6 +161,8 @@ struct PowerArgs {
   int32_t route = 0;                 // in: 0 Cholesky QR2, then shifted QR3, then TSQR as needed;
                                      //     2 shifted QR3 first; 1 Gram-Schmidt + TSQR
   int32_t route_used = -1;           // out: the route that produced orth(H)
+  void* host_pin = nullptr;          // as in FinalizeArgs
+  hipEvent_t host_ev = nullptr;
 };
 hipError_t run_power_omega(PowerArgs& p, hipStream_t s);
 // Implicit centring of the sketch in place: G <- G - 1 (Omega'^T mu)^T, H <- H - mu (G^T 1)^T with

@@ -268,6 +268,8 @@ struct sketch_server_s {
   uint8_t* ws = nullptr;
   hipStream_t stream = nullptr;      // grouped launches (caller's)
   hipStream_t fin_stream = nullptr;  // finalize (library's)
+  void* fin_pin = nullptr;           // pinned staging of the finalize's read-backs
+  hipEvent_t fin_ev = nullptr;       // the event those read-backs poll
   hipStream_t copy_stream = nullptr; // host-to-device copies of pinned-host blocks (library's)
   std::vector<char> stage_busy;      // staging slots held by an in-flight group
   std::vector<hipEvent_t> stage_ev;  // per slot: its copy finished
@@ -612,6 +614,8 @@ sketch_status sketch_server_create(sketch_server_t* out, const sketch_server_con
   if (e == hipSuccess)
     e = launch_fill_f64(s->at<double>(z.off_small), (int64_t)finalize_small_elems(cfg->l, 32), 0.0,
                         s->stream);
+  if (e == hipSuccess) e = hipHostMalloc(&s->fin_pin, kHostPinBytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fin_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreate(&s->anchor);
   if (e == hipSuccess) e = hipEventRecord(s->anchor, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -810,10 +814,11 @@ sketch_status sketch_server_finalize(sketch_server_t s, uint64_t stream_id, doub
       f.ldu = ldu;
       f.V = V_dev;
       f.ldv = ldv;
+      f.host_pin = s->fin_pin;
+      f.host_ev = s->fin_ev;
       e = run_finalize(f, s->fin_stream);
       Ctrl hc{};
-      if (e == hipSuccess) e = hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->fin_stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(s->fin_stream);
+      if (e == hipSuccess) e = read_back(&hc, ctrl, sizeof(Ctrl), s->fin_stream, s->fin_pin, s->fin_ev);
       if (e == hipSuccess) {
         rank = hc.l_eff;
         if (hc.nonfinite) result = set_error(SKETCH_E_NONFINITE, "a block of the stream held NaN or Inf");
@@ -869,6 +874,8 @@ sketch_status sketch_server_destroy(sketch_server_t s) {
   for (auto& g : s->inflight) (void)hipEventDestroy(g.ev);
   for (auto ev : s->ev_pool) (void)hipEventDestroy(ev);
   if (s->anchor) (void)hipEventDestroy(s->anchor);
+  if (s->fin_pin) (void)hipHostFree(s->fin_pin);
+  if (s->fin_ev) (void)hipEventDestroy(s->fin_ev);
   for (auto ev : s->stage_ev)
     if (ev) (void)hipEventDestroy(ev);
   if (s->copy_stream) {

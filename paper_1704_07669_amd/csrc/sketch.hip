@@ -168,6 +168,8 @@ struct sketch_s {
   sketch_status sticky = SKETCH_OK;
   int* nf_host = nullptr;           // host-mapped non-finite flag (host address), or null
   int* nf_dev = nullptr;            // its device address
+  void* fin_pin = nullptr;          // pinned staging of the finalize's read-backs, or null
+  hipEvent_t fin_ev = nullptr;      // the event those read-backs poll, or null
   int32_t path_loop = -1, path_rb = -1;   // QR methods the last finalize used
   int32_t force_loop = 0, force_rb = 0;   // test hook: take the Householder paths directly
   bool omega_derived = false;       // Omega' came from the data (power scheme), not from the seed
@@ -364,11 +366,12 @@ sketch_status finalize_core(sketch_t h, double* S_dev, double* U_dev, int64_t ld
   f.force_rb = h->force_rb;
   f.centre = c.centre;
   f.mu = c.centre ? h->at<double>(L.off_mu) : nullptr;
+  f.host_pin = h->fin_pin;
+  f.host_ev = h->fin_ev;
   if (e == hipSuccess) e = run_finalize(f, h->stream);
   if (e == hipSuccess && h->prof) e = hipEventRecord(fb, h->stream);
   Ctrl hc;
-  if (e == hipSuccess) e = hipMemcpyAsync(&hc, h->ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = read_back(&hc, h->ctrl(), sizeof(Ctrl), h->stream, h->fin_pin, h->fin_ev);
   if (e != hipSuccess) return h->dev_fail(e, "finalize");
   if (h->prof) h->recs.push_back({fa, fb, nullptr, 2});
   h->phase = 2;
@@ -443,6 +446,8 @@ sketch_status sketch_init(sketch_t* out, const sketch_config* cfg, void* dev_ws,
     *reinterpret_cast<volatile int*>(h->nf_host) = 0;
     e = hipHostGetDevicePointer((void**)&h->nf_dev, h->nf_host, 0);
   }
+  if (e == hipSuccess) e = hipHostMalloc(&h->fin_pin, kHostPinBytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fin_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     sketch_destroy(h);
     return fail(SKETCH_E_DEVICE, "stream/event creation: %s", hipGetErrorString(e));
@@ -606,6 +611,8 @@ sketch_status sketch_power_restart(sketch_t h, int32_t route, int32_t* route_use
   p.tsqr_ws = h->at<double>(L.off_tsqr);
   p.small = h->at<double>(L.off_small);
   p.route = route;
+  p.host_pin = h->fin_pin;
+  p.host_ev = h->fin_ev;
   hipError_t e = hipSuccess;
   if (h->cfg.centre)   // Omega_2 from the centred sketch: orth(A_c^T A_c Omega)
     e = centre_sketch(h->cfg.compute, h->ws + L.off_G, L.MCAP, h->rows, h->at<double>(L.off_H),
@@ -620,7 +627,7 @@ sketch_status sketch_power_restart(sketch_t h, int32_t route, int32_t* route_use
   sketch_status st = start_pass(h);
   h->cfg.omega_from_seed = seed_flag;
   if (st != SKETCH_OK) return st;
-  e = hipStreamSynchronize(h->stream);
+  e = read_back(nullptr, nullptr, 0, h->stream, h->fin_pin, h->fin_ev);
   if (e != hipSuccess) return h->dev_fail(e, "power scheme");
   h->omega_derived = true;
   h->phase = 1;
@@ -956,6 +963,8 @@ sketch_status sketch_destroy(sketch_t h) {
   }
   for (auto ev : h->ev_free) (void)hipEventDestroy(ev);
   if (h->nf_host) (void)hipHostFree(h->nf_host);
+  if (h->fin_pin) (void)hipHostFree(h->fin_pin);
+  if (h->fin_ev) (void)hipEventDestroy(h->fin_ev);
   delete h;
   return SKETCH_OK;
 }

@@ -1,5 +1,7 @@
 // Small device helpers: fills (kernel-based, so the library issues no memset nodes) and copies of
 // internal column-major state to the caller's row-major FP64 buffers.
+#include <cstring>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -84,6 +86,26 @@ inline int grid_for(int64_t work) {
   return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
 }
 }  // namespace
+
+hipError_t read_back(void* dst, const void* src, size_t bytes, hipStream_t s, void* pin,
+                     hipEvent_t ev) {
+  if (pin == nullptr || ev == nullptr || bytes > kHostPinBytes) {
+    hipError_t e = bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+  }
+  hipError_t e = bytes ? hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
+  if (e == hipSuccess) e = hipEventRecord(ev, s);
+  if (e == hipSuccess) {
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    // the polls leave "not ready" as the runtime's last error; the launch checks that follow
+    // read it, so it is cleared once the event has completed
+    if (e == hipSuccess) (void)hipGetLastError();
+  }
+  if (e == hipSuccess && bytes) memcpy(dst, pin, bytes);
+  return e;
+}
 
 hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s) {
   if (count <= 0) return hipSuccess;
