@@ -244,6 +244,111 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
   }
 }
 
+// The Gram matrix X^T X of the first L <= 16 MT columns of X over row chunks, each workgroup
+// reading its rows of X once: the 16 x 16 tiles (mt, nt) with mt <= nt accumulate on the FP64
+// matrix cores (the operand of tile nt's columns is that of tile nt's rows), and the partials go
+// out in k_tn_mfma's slice layout (column slices of 32, rows a < 32 (y + 1) of slice y), so
+// k_tn_final_gram sums them unchanged; the slice rows below the diagonal tiles, which nothing
+// reads, are written as zeros.  The waves' sums are combined through LDS in rounds of kGramRound
+// tiles.  The next rows are loaded after the matrix-core work that frees the operand registers:
+// at one wave per SIMD the product is bound by the matrix cores (about 124 16x16x4 FP64 MFMAs per
+// 16 rows and 112 columns), which the loads of the following rows overlap.
+__host__ __device__ constexpr int gram_tile_count(int MT) { return MT * (MT + 1) / 2; }
+constexpr int kGramRound = 16;
+
+template <int MT>
+__device__ __forceinline__ void gram_fetch(const double* __restrict__ X, int64_t ldx, int L,
+                                           int64_t rr, int64_t r_end, int r16, bool full,
+                                           double (&xa)[MT][4]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int a = mt * 16 + r16;
+    const double* px = X + (int64_t)(a < L ? a : 0) * ldx + rr;
+    if (full) {
+      const f64x4 v = *reinterpret_cast<const f64x4*>(px);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xa[mt][j] = (a < L) ? v[j] : 0.0;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xa[mt][j] = (a < L && rr + j < r_end) ? px[j] : 0.0;
+    }
+  }
+}
+
+template <int MT>
+__global__ __launch_bounds__(TPB) void k_gram_mfma(const double* __restrict__ X, int64_t ldx,
+                                                   int L, int64_t rows, int RCH,
+                                                   double* __restrict__ part) {
+  constexpr int NTILE = gram_tile_count(MT);
+  __shared__ double red[(TPB / 64 - 1) * kGramRound * 4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
+  const int64_t r_begin = (int64_t)blockIdx.x * RCH;
+  const int64_t r_end = min<int64_t>(rows, r_begin + RCH);
+  const bool aligned = (ldx % 4) == 0;
+  f64x4 acc[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) acc[t] = f64x4{0, 0, 0, 0};
+  double xa[MT][4];
+  constexpr int STEP = (TPB / 64) * 16;
+  for (int64_t r0 = r_begin + wave * 16; r0 < r_end; r0 += STEP) {
+    gram_fetch<MT>(X, ldx, L, r0 + 4 * g, r_end, r16, aligned && r0 + 16 <= r_end, xa);
+    int t = 0;
+#pragma unroll
+    for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+      for (int mt = 0; mt <= nt; ++mt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[t] = mma_f64(xa[mt][j], xa[nt][j], acc[t]);
+        ++t;
+      }
+    mfma_drain();
+  }
+  const int64_t per_slice = (int64_t)gridDim.x * L * 32;
+  double* mine = part + (int64_t)blockIdx.x * L * 32;
+#pragma unroll
+  for (int t0 = 0; t0 < NTILE; t0 += kGramRound) {
+    __syncthreads();
+    if (wave > 0) {
+#pragma unroll
+      for (int u = 0; u < kGramRound; ++u)
+        if (t0 + u < NTILE)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            red[(((wave - 1) * kGramRound + u) * 4 + i) * 64 + lane] = acc[t0 + u][i];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      int t = 0;
+#pragma unroll
+      for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+        for (int mt = 0; mt <= nt; ++mt) {
+          if (t >= t0 && t < t0 + kGramRound) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              double sm = acc[t][i];
+              for (int w = 1; w < TPB / 64; ++w)
+                sm += red[(((w - 1) * kGramRound + (t - t0)) * 4 + i) * 64 + lane];
+              const int a = mt * 16 + acc_row<double>(g, i), c = nt * 16 + r16;
+              if (a < L && c < L) mine[(c >> 5) * per_slice + (int64_t)a * 32 + (c & 31)] = sm;
+            }
+          }
+          ++t;
+        }
+    }
+  }
+  // the tiles (nt + 1, nt) of even nt: rows of slice nt / 2 below its diagonal tile
+  if (wave == 1) {
+#pragma unroll
+    for (int nt = 0; nt + 1 < MT; nt += 2)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int a = (nt + 1) * 16 + acc_row<double>(g, i), c = nt * 16 + r16;
+        if (a < L && c < L) mine[(c >> 5) * per_slice + (int64_t)a * 32 + (c & 31)] = 0.0;
+      }
+  }
+}
+
 // Sum of the chunk partials (chunk stride pq entries) for the entries e0 .. e0 + ecount - 1, entry
 // e = a q + c going to out[a * ldo + c] (row-major, leading dimension ldo).  A workgroup owns 64
 // entries (one per lane, consecutive in part, so the loads coalesce); its 16 waves take the
@@ -1329,8 +1434,10 @@ __device__ __forceinline__ double rsq_nr1(double x) {
 // accumulated: with M J = W (orthogonal columns, norms sigma), B^T = Q_B R_B and M = R_B^T,
 // B^T W = Q_B J S^2, so V = B^T W S^-2 (see run_finalize).
 constexpr int kJacobiLds = 160 * 1024 - 4096;   // dynamic LDS limit of k_jacobi (static: norms)
-constexpr int kJacobiLpp = 8;                   // lanes per pair
+constexpr int kJacobiLpp = 8;                   // lanes per pair (the 8-lane reduction below)
 constexpr int kJacobiThreads = 64 * kJacobiLpp; // one lane group per pair for N <= 128
+// rows per lane (EPL) the kernel is built for: LPAD = kJacobiLpp EPL covers every L <= JMAX
+#define SK_JACOBI_EPLS(X) X(2) X(4) X(8) X(12) X(13) X(14) X(16)
 
 __host__ __device__ constexpr int jacobi_cs(int lpad) {
   return ((lpad / kJacobiLpp) % 2 == 0) ? lpad + kJacobiLpp : lpad;
@@ -1471,11 +1578,13 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
   }
 }
 
-// EPL (rows per lane) for L: LPAD = 8 EPL >= L.
+// EPL (rows per lane) for L: the smallest built one with kJacobiLpp EPL >= L.
 inline int jacobi_epl(int L) {
   const int need = cdiv(L, kJacobiLpp);
-  return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 13 ? 13
-         : need <= 14 ? 14 : 16;
+#define SK_EPL_PICK(E) if (need <= (E)) return (E);
+  SK_JACOBI_EPLS(SK_EPL_PICK)
+#undef SK_EPL_PICK
+  return 16;
 }
 size_t jacobi_lds_bytes(int L) {
   const int N = (L + 1) & ~1, CS = jacobi_cs(kJacobiLpp * jacobi_epl(L));
@@ -1856,6 +1965,29 @@ void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, doub
       tn_rows_per_chunk(rows), rup<int64_t>(cdiv<int64_t>(rows, want), 16));
   const int nch = (int)cdiv<int64_t>(rows, rch);
   const dim3 grid(nch, ny);
+  // one read of X for the whole upper triangle (l <= 112); the slice launch otherwise
+  const int nch1 = (int)cdiv<int64_t>(rows, std::max<int64_t>(tn_rows_per_chunk(rows),
+                                                              rup<int64_t>(cdiv<int64_t>(rows, kGramWgs), 16)));
+  const int rch1 = (int)std::max<int64_t>(tn_rows_per_chunk(rows),
+                                          rup<int64_t>(cdiv<int64_t>(rows, kGramWgs), 16));
+  if (mt <= 7) {
+    const dim3 g1(nch1);
+    switch (mt) {
+      case 1: hipLaunchKernelGGL(k_gram_mfma<1>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 2: hipLaunchKernelGGL(k_gram_mfma<2>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 3: hipLaunchKernelGGL(k_gram_mfma<3>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 4: hipLaunchKernelGGL(k_gram_mfma<4>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 5: hipLaunchKernelGGL(k_gram_mfma<5>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 6: hipLaunchKernelGGL(k_gram_mfma<6>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      default: hipLaunchKernelGGL(k_gram_mfma<7>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+    }
+    cx.chk();
+    if (!cx.ok()) return;
+    hipLaunchKernelGGL(k_tn_final_gram, dim3((unsigned)cdiv<int64_t>((int64_t)ny * L * 32, 64)),
+                       dim3(kTnFinalThreads), 0, cx.s, red_ws, nch1, L, ny, Gm, L);
+    cx.chk();
+    return;
+  }
   switch (mt) {
     case 1: tn_launch<1>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
     case 2: tn_launch<2>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
@@ -1978,10 +2110,9 @@ hipError_t finalize_prepare() {
   if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
   std::lock_guard<std::mutex> lock(mu);
   if (done[dev]) return hipSuccess;
-  for (const void* kj : {(const void*)k_jacobi<2>, (const void*)k_jacobi<4>,
-                         (const void*)k_jacobi<8>, (const void*)k_jacobi<12>,
-                         (const void*)k_jacobi<13>, (const void*)k_jacobi<14>,
-                         (const void*)k_jacobi<16>})
+#define SK_EPL_FN(E) (const void*)k_jacobi<E>,
+  for (const void* kj : {SK_JACOBI_EPLS(SK_EPL_FN)})
+#undef SK_EPL_FN
     if (e == hipSuccess)
       e = hipFuncSetAttribute(kj, hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiLds);
   if (e == hipSuccess)
@@ -2159,7 +2290,7 @@ bool one_block(Ctx& cx, FinalizeArgs& f, const Small& sm, Ctrl& hc) {
   right_trmul(cx, f.Q, f.ldq, X, f.ldq, m, l, sm.Jk);
   gram_upper(cx, f.Q, f.ldq, m, l, f.red_ws, sm.Jm);
   chol(cx, sm.Jm, l, 0.0, sm.Wm, sm.RB, fail, 0.0, 1e-6, ill);
-  right_trmul(cx, X, f.ldq, f.Q, f.ldq, m, l, sm.RB);
+  if (f.U != nullptr) right_trmul(cx, X, f.ldq, f.Q, f.ldq, m, l, sm.RB);   // Q only feeds U
   // R = R2 R1 and R^-1 = R1^-1 R2^-1 (upper triangular, lower parts zero)
   if (cx.ok()) cx.err = launch_fill_f64(sm.Rg, (int64_t)l * l, 0.0, stream);
   if (cx.ok()) cx.err = launch_fill_f64(sm.Rgi, (int64_t)l * l, 0.0, stream);
@@ -2357,22 +2488,17 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
     // ---------------- Jacobi SVD of R_B^T
     {
       const size_t jshm = jacobi_lds_bytes(L);
+      if (jshm > (size_t)kJacobiLds) return hipErrorInvalidValue;   // l <= JMAX keeps it inside
       const dim3 g1(1), bj(kJacobiThreads);
       switch (jacobi_epl(L)) {
-        case 2: hipLaunchKernelGGL(k_jacobi<2>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info,
-                                   sm.sig, sm.perm, sm.Jm); break;
-        case 4: hipLaunchKernelGGL(k_jacobi<4>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info,
-                                   sm.sig, sm.perm, sm.Jm); break;
-        case 8: hipLaunchKernelGGL(k_jacobi<8>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info,
-                                   sm.sig, sm.perm, sm.Jm); break;
-        case 12: hipLaunchKernelGGL(k_jacobi<12>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
-                                    sm.info, sm.sig, sm.perm, sm.Jm); break;
-        case 13: hipLaunchKernelGGL(k_jacobi<13>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
-                                    sm.info, sm.sig, sm.perm, sm.Jm); break;
-        case 14: hipLaunchKernelGGL(k_jacobi<14>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
-                                    sm.info, sm.sig, sm.perm, sm.Jm); break;
-        default: hipLaunchKernelGGL(k_jacobi<16>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L,
-                                    sm.info, sm.sig, sm.perm, sm.Jm); break;
+#define SK_EPL_CASE(E)                                                                        \
+        case E:                                                                               \
+          hipLaunchKernelGGL(k_jacobi<E>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info, \
+                             sm.sig, sm.perm, sm.Jm);                                         \
+          break;
+        SK_JACOBI_EPLS(SK_EPL_CASE)
+#undef SK_EPL_CASE
+        default: break;
       }
     }
     cx.chk();
