@@ -256,27 +256,28 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
 __host__ __device__ constexpr int gram_tile_count(int MT) { return MT * (MT + 1) / 2; }
 constexpr int kGramRound = 16;
 
-template <int MT>
-__device__ __forceinline__ void gram_fetch(const double* __restrict__ X, int64_t ldx, int L,
+template <typename XT, int MT>
+__device__ __forceinline__ void gram_fetch(const XT* __restrict__ X, int64_t ldx, int L,
                                            int64_t rr, int64_t r_end, int r16, bool full,
                                            double (&xa)[MT][4]) {
+  using V4 = typename std::conditional<std::is_same<XT, double>::value, f64x4, f32x4>::type;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int a = mt * 16 + r16;
-    const double* px = X + (int64_t)(a < L ? a : 0) * ldx + rr;
+    const XT* px = X + (int64_t)(a < L ? a : 0) * ldx + rr;
     if (full) {
-      const f64x4 v = *reinterpret_cast<const f64x4*>(px);
+      const V4 v = *reinterpret_cast<const V4*>(px);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) xa[mt][j] = (a < L) ? v[j] : 0.0;
+      for (int j = 0; j < 4; ++j) xa[mt][j] = (a < L) ? (double)v[j] : 0.0;
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) xa[mt][j] = (a < L && rr + j < r_end) ? px[j] : 0.0;
+      for (int j = 0; j < 4; ++j) xa[mt][j] = (a < L && rr + j < r_end) ? (double)px[j] : 0.0;
     }
   }
 }
 
-template <int MT>
-__global__ __launch_bounds__(TPB) void k_gram_mfma(const double* __restrict__ X, int64_t ldx,
+template <typename XT, int MT>
+__global__ __launch_bounds__(TPB) void k_gram_mfma(const XT* __restrict__ X, int64_t ldx,
                                                    int L, int64_t rows, int RCH,
                                                    double* __restrict__ part) {
   constexpr int NTILE = gram_tile_count(MT);
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(TPB) void k_gram_mfma(const double* __restrict__ X,
   double xa[MT][4];
   constexpr int STEP = (TPB / 64) * 16;
   for (int64_t r0 = r_begin + wave * 16; r0 < r_end; r0 += STEP) {
-    gram_fetch<MT>(X, ldx, L, r0 + 4 * g, r_end, r16, aligned && r0 + 16 <= r_end, xa);
+    gram_fetch<XT, MT>(X, ldx, L, r0 + 4 * g, r_end, r16, aligned && r0 + 16 <= r_end, xa);
     int t = 0;
 #pragma unroll
     for (int nt = 0; nt < MT; ++nt)
@@ -346,6 +347,81 @@ __global__ __launch_bounds__(TPB) void k_gram_mfma(const double* __restrict__ X,
         const int a = (nt + 1) * 16 + acc_row<double>(g, i), c = nt * 16 + r16;
         if (a < L && c < L) mine[(c >> 5) * per_slice + (int64_t)a * 32 + (c & 31)] = 0.0;
       }
+  }
+}
+
+// Y = X W for the rows x L column-major X and the upper triangular L x L W (row-major, leading
+// dimension ldw), L <= 16 MT, on the FP64 matrix cores, reading X once: every workgroup stages W,
+// zero-padded to 16 MT, in LDS, and its waves take 16-row blocks of its row range.  The MFMA k
+// index is the column a of X (lane (r16, g) supplies X[r0 + r16][4 s + g]); output tile nt only
+// meets k < 16 (nt + 1), W being upper triangular.  The next block's operands are loaded before
+// the current block's matrix-core work.  Rows past `rows` are read clamped and not written.
+template <typename XT, int MT>
+__device__ __forceinline__ void rmul_fetch(const XT* __restrict__ X, int64_t ldx, int L,
+                                           int64_t row, int g, double (&xa)[MT][4]) {
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = 16 * t + 4 * j + g;
+      const double v = (double)X[(int64_t)(a < L ? a : L - 1) * ldx + row];
+      xa[t][j] = a < L ? v : 0.0;
+    }
+}
+
+constexpr size_t rmul_lds_bytes(int MT) { return (size_t)(16 * MT) * (16 * MT + 1) * sizeof(double); }
+
+template <typename XT, int MT>
+__global__ __launch_bounds__(TPB) void k_rmul_mfma(double* __restrict__ Y, int64_t ldy,
+                                                   const XT* __restrict__ X, int64_t ldx,
+                                                   int64_t rows, int L,
+                                                   const double* __restrict__ W, int ldw,
+                                                   int RCH) {
+  extern __shared__ double ws[];
+  constexpr int LP = 16 * MT, WS = LP + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
+  stage8(LP * LP, threadIdx.x, TPB,
+         [&](int idx) {
+           const int a = idx / LP, c = idx - a * LP;
+           return (a < L && c < L && c >= a) ? W[(int64_t)a * ldw + c] : 0.0;
+         },
+         [&](int idx, double v) {
+           const int a = idx / LP, c = idx - a * LP;
+           ws[a * WS + c] = v;
+         });
+  __syncthreads();
+  const int64_t r_begin = (int64_t)blockIdx.x * RCH;
+  const int64_t r_end = min<int64_t>(rows, r_begin + RCH);
+  double xa0[MT][4], xa1[MT][4];
+  auto block = [&](const double (&xa)[MT][4], int64_t r0) {
+    f64x4 acc[MT];
+#pragma unroll
+    for (int nt = 0; nt < MT; ++nt) acc[nt] = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+      for (int t = 0; t <= nt; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[nt] = mma_f64(xa[t][j], ws[(16 * t + 4 * j + g) * WS + nt * 16 + r16], acc[nt]);
+    mfma_drain();
+#pragma unroll
+    for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = r0 + acc_row<double>(g, i);
+        const int c = nt * 16 + r16;
+        if (r < r_end && c < L) Y[(int64_t)c * ldy + r] = acc[nt][i];
+      }
+  };
+  int64_t r0 = r_begin + wave * 16;
+  if (r0 < r_end) rmul_fetch<XT, MT>(X, ldx, L, min<int64_t>(r0 + r16, rows - 1), g, xa0);
+  for (; r0 < r_end; r0 += 128) {
+    const int64_t r1 = r0 + 64, r2 = r0 + 128;
+    if (r1 < r_end) rmul_fetch<XT, MT>(X, ldx, L, min<int64_t>(r1 + r16, rows - 1), g, xa1);
+    block(xa0, r0);
+    if (r2 < r_end) rmul_fetch<XT, MT>(X, ldx, L, min<int64_t>(r2 + r16, rows - 1), g, xa0);
+    if (r1 < r_end) block(xa1, r1);
   }
 }
 
@@ -1370,6 +1446,226 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict_
   if (dev) *ill = 1;                             // every writer stores the same value
 }
 
+// Blocked variant of k_chol (same contract), in 16 x 16 blocks of the matrix padded with the
+// identity to LP = 16 MT rows: per block column, wave 0 factors the diagonal block (one pivot at a
+// time, its lanes in step through LDS, which orders one wave's accesses), one thread per column
+// solves the block row to its right (R_kk^T Y = A_k), and the waves update the trailing upper
+// tiles on the FP64 matrix cores (A_ij -= R_ki^T R_kj, 16 x 16 x 4 products over the 16 rows of
+// the block row).  R^-1 by blocks: every diagonal block inverted by its own wave (right-looking
+// back substitution, one lane per column), Y_it = X_ii R_it in place of R_it, then the blocks at
+// distance s = j - i from the diagonal, X_ij = -sum_{t = i+1..j} Y_it X_tj, one wave per block;
+// R^-1 is kept transposed in the strictly lower triangle (X[k][c] at [c][k]) and its diagonal in
+// ri.  Three barriers per block column and one per distance.
+constexpr int kCholBlkThreads = 512;
+
+size_t cholb_lds_bytes(int L) {
+  const size_t LP = (size_t)rup(L, 16);
+  return (LP * (LP + 1) + 3 * LP) * sizeof(double);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __restrict__ Gm,
+                                                              int ldg, int L, double shift_rel,
+                                                              double* __restrict__ R,
+                                                              double* __restrict__ Rinv, int ldr,
+                                                              int* __restrict__ fail,
+                                                              double ill_rel, double dev_rel,
+                                                              int* __restrict__ ill,
+                                                              int force_fail) {
+  extern __shared__ double a[];
+  const int MT = (L + 15) >> 4, LP = 16 * MT, LS = LP + 1;
+  double* rd = a + (int64_t)LP * LS;     // diagonal of R
+  double* ri = rd + LP;                  // its inverse (the diagonal of R^-1)
+  double* g0 = ri + LP;                  // the diagonal the factorisation started from
+  __shared__ int bad;
+  __shared__ double shs;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
+  // the upper triangle of Gm, zeros below it, the identity on the padding
+  stage8(LP * LP, tid, kCholBlkThreads,
+         [&](int idx) {
+           const int i = idx / LP, c = idx - i * LP;
+           return (i < L && c < L) ? (c >= i ? Gm[(int64_t)i * ldg + c] : 0.0)
+                                   : (i == c ? 1.0 : 0.0);
+         },
+         [&](int idx, double v) {
+           const int i = idx / LP, c = idx - i * LP;
+           a[i * LS + c] = v;
+         });
+  if (tid == 0) { bad = 0; shs = 0.0; }
+  __syncthreads();
+  if (shift_rel > 0.0) {
+    if (tid < 64) {
+      double t = 0.0;
+      for (int i = tid; i < L; i += 64) t += a[i * LS + i];
+      t = wave_sum(t);
+      if (tid == 0) shs = t * shift_rel;
+    }
+    __syncthreads();
+    for (int i = tid; i < L; i += kCholBlkThreads) a[i * LS + i] += shs;
+    __syncthreads();
+  }
+  for (int i = tid; i < LP; i += kCholBlkThreads) g0[i] = a[i * LS + i];
+  __syncthreads();
+
+  for (int kb = 0; kb < MT; ++kb) {
+    const int k0 = 16 * kb;
+    // (a) the diagonal block, by wave 0: lane (bi, bc..bc+3) holds row bi, columns bc.. of it
+    if (wave == 0) {
+      const int bi = lane >> 2, bc = (lane & 3) * 4;
+      bool fl = false;
+      for (int p = 0; p < 16; ++p) {
+        const int P = k0 + p;
+        const double d = a[P * LS + P];          // the same in every lane: uniform exits
+        if (P < L) {
+          if ((force_fail && P == 0) || !(d > 0.0) || !(d < INFINITY)) fl = true;
+          if (lane == 0 && ill_rel > 0.0 && !(d >= ill_rel * g0[P])) *ill = 1;
+        }
+        if (fl) break;
+        const double r = rsq_nr(d);              // refined 1/sqrt(d); R[P][P] = d / sqrt(d)
+        if (lane > p && lane < 16) a[P * LS + k0 + lane] *= r;
+        if (lane == 0) { a[P * LS + P] = d * r; rd[P] = d * r; ri[P] = r; }
+        wave_lds_sync();
+        if (bi > p) {
+          const double xi = a[P * LS + k0 + bi];
+          double v[4], x[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            v[u] = a[(k0 + bi) * LS + k0 + bc + u];
+            x[u] = a[P * LS + k0 + bc + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (bc + u >= bi) a[(k0 + bi) * LS + k0 + bc + u] = fma(-xi, x[u], v[u]);
+        }
+        wave_lds_sync();
+      }
+      if (fl && lane == 0) bad = 1;
+    }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) *fail = 1;
+      chol_write_identity(R, Rinv, ldr, L, tid);
+      return;
+    }
+    // (b) the block row to the right: column c of R_k solves R_kk^T y = A_k(:, c)
+    if (tid < LP - k0 - 16) {
+      const int c = k0 + 16 + tid;
+      double y[16];
+#pragma unroll
+      for (int p = 0; p < 16; ++p) y[p] = a[(k0 + p) * LS + c];
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        y[p] *= ri[k0 + p];
+#pragma unroll
+        for (int q = p + 1; q < 16; ++q) y[q] = fma(-a[(k0 + p) * LS + k0 + q], y[p], y[q]);
+      }
+#pragma unroll
+      for (int p = 0; p < 16; ++p) a[(k0 + p) * LS + c] = y[p];
+    }
+    __syncthreads();
+    // (c) trailing tiles (mi, nc), kb < mi <= nc < MT, one wave per tile
+    const int nb = MT - kb - 1;
+    for (int tt = wave; tt < nb * (nb + 1) / 2; tt += kCholBlkThreads / 64) {
+      int nc = 0;
+      while ((nc + 1) * (nc + 2) / 2 <= tt) ++nc;
+      const int mi = tt - nc * (nc + 1) / 2;
+      const int i0 = k0 + 16 + 16 * mi, c0 = k0 + 16 + 16 * nc;
+      f64x4 acc = f64x4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kr = k0 + 4 * s + g;
+        acc = mma_f64(a[kr * LS + i0 + r16], a[kr * LS + c0 + r16], acc);
+      }
+      mfma_drain();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[(i0 + acc_row<double>(g, i)) * LS + c0 + r16] -= acc[i];
+    }
+    __syncthreads();
+  }
+  bool dev = false;
+  for (int idx = tid; idx < L * L; idx += kCholBlkThreads) {
+    const int i = idx / L, c = idx - i * L;
+    const double v = c > i ? a[i * LS + c] : (c == i ? rd[i] : 0.0);
+    R[(int64_t)i * ldr + c] = v;
+    dev |= dev_rel > 0.0 && !(fabs(v - (c == i ? 1.0 : 0.0)) <= dev_rel);
+  }
+  if (dev) *ill = 1;                             // every writer stores the same value
+  if (Rinv == nullptr) return;
+  __syncthreads();
+  // (d1) X_ii = R_ii^-1, wave i, lane c owning column c (q from the bottom: x_q = rhs_q / R_qq,
+  // then rhs_t -= R_tq x_q for t < q)
+  if (wave < MT && lane < 16) {
+    const int k0 = 16 * wave, c = lane;
+    double x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = (q == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 15; q >= 0; --q) {
+      if (q <= c) {
+        x[q] *= ri[k0 + q];
+#pragma unroll
+        for (int t = 0; t < q; ++t) x[t] = fma(-a[(k0 + t) * LS + k0 + q], x[q], x[t]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q < c) a[(k0 + c) * LS + k0 + q] = x[q];
+  }
+  __syncthreads();
+  // (d2) Y_it = X_ii R_it in place of R_it (i < t), one thread per column of a block
+  for (int w = tid; w < 16 * MT * (MT - 1) / 2; w += kCholBlkThreads) {
+    const int col = w & 15, bp = w >> 4;
+    int t = 1;
+    while (t * (t + 1) / 2 <= bp) ++t;
+    const int i = bp - t * (t - 1) / 2;        // block pair (i, t), i < t
+    const int k0 = 16 * i, c = 16 * t + col;
+    double y[16], o[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) y[r] = a[(k0 + r) * LS + c];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      double sacc = ri[k0 + q] * y[q];
+#pragma unroll
+      for (int r = q + 1; r < 16; ++r) sacc = fma(a[(k0 + r) * LS + k0 + q], y[r], sacc);
+      o[q] = sacc;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[(k0 + q) * LS + c] = o[q];
+  }
+  __syncthreads();
+  // (d3) X_ij = -sum_{t=i+1..j} Y_it X_tj at distance s = j - i, one wave per block
+  for (int s = 1; s < MT; ++s) {
+    for (int i = wave; i < MT - s; i += kCholBlkThreads / 64) {
+      const int j = i + s, qi = 16 * i, cj = 16 * j;
+      f64x4 acc = f64x4{0, 0, 0, 0};
+      for (int t = i + 1; t <= j; ++t) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int r = 4 * kk + g;                // row r of block t
+          const double av = a[(qi + r16) * LS + 16 * t + r];
+          double bv;
+          if (t < j) bv = a[(cj + r16) * LS + 16 * t + r];
+          else bv = (r < r16) ? a[(cj + r16) * LS + cj + r] : (r == r16 ? ri[cj + r16] : 0.0);
+          acc = mma_f64(av, bv, acc);
+        }
+      }
+      mfma_drain();
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[(cj + r16) * LS + qi + acc_row<double>(g, k)] = -acc[k];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < L * L; idx += kCholBlkThreads) {
+    const int i = idx / L, c = idx - i * L;
+    Rinv[(int64_t)i * ldr + c] = c > i ? a[c * LS + i] : (c == i ? ri[i] : 0.0);
+  }
+}
+
 // out = X Y for upper triangular L x L X and Y (row-major, leading dimension L); out must not
 // alias X or Y.  One workgroup per row i (row i of X staged in LDS), one thread per column; the
 // loads of Y are issued eight at a time.
@@ -1953,7 +2249,8 @@ void cholqr_lane(Ctx& cx, double* Y, int64_t ldy, int64_t rows, const double* G,
 
 // Gram matrix X^T X (L x L, upper triangle, row-major, leading dimension L) of the n x L
 // column-major X, in column slices of at most 32.
-void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, double* red_ws,
+template <typename XT>
+void gram_upper(Ctx& cx, const XT* X, int64_t ldx, int64_t rows, int L, double* red_ws,
                 double* Gm) {
   if (!cx.ok() || L <= 0) return;
   // about one workgroup per CU over all slices: a workgroup's share of the matrix-core work then
@@ -1973,13 +2270,13 @@ void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, doub
   if (mt <= 7) {
     const dim3 g1(nch1);
     switch (mt) {
-      case 1: hipLaunchKernelGGL(k_gram_mfma<1>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 2: hipLaunchKernelGGL(k_gram_mfma<2>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 3: hipLaunchKernelGGL(k_gram_mfma<3>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 4: hipLaunchKernelGGL(k_gram_mfma<4>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 5: hipLaunchKernelGGL(k_gram_mfma<5>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 6: hipLaunchKernelGGL(k_gram_mfma<6>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      default: hipLaunchKernelGGL(k_gram_mfma<7>, g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 1: hipLaunchKernelGGL((k_gram_mfma<XT, 1>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 2: hipLaunchKernelGGL((k_gram_mfma<XT, 2>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 3: hipLaunchKernelGGL((k_gram_mfma<XT, 3>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 4: hipLaunchKernelGGL((k_gram_mfma<XT, 4>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 5: hipLaunchKernelGGL((k_gram_mfma<XT, 5>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 6: hipLaunchKernelGGL((k_gram_mfma<XT, 6>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      default: hipLaunchKernelGGL((k_gram_mfma<XT, 7>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
     }
     cx.chk();
     if (!cx.ok()) return;
@@ -1988,6 +2285,10 @@ void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, doub
     cx.chk();
     return;
   }
+  if constexpr (!std::is_same<XT, double>::value) {
+    cx.err = hipErrorInvalidValue;             // FP32 columns are read directly only for l <= 112
+    return;
+  } else {
   switch (mt) {
     case 1: tn_launch<1>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
     case 2: tn_launch<2>(cx, 2, grid, X, ldx, X, ldx, L, 32, rows, rch, red_ws, nullptr, 0, L); break;
@@ -2003,26 +2304,57 @@ void gram_upper(Ctx& cx, const double* X, int64_t ldx, int64_t rows, int L, doub
   hipLaunchKernelGGL(k_tn_final_gram, dim3((unsigned)cdiv<int64_t>((int64_t)ny * L * 32, 64)),
                      dim3(kTnFinalThreads), 0, cx.s, red_ws, nch, L, ny, Gm, L);
   cx.chk();
+  }
 }
 
 // Y = X R^-1 for the n x L column-major X and upper triangular R^-1 (row-major, leading dimension
 // L), in column slices of at most 16 (slice c0..c0+w-1 only needs rows 0..c0+w-1 of R^-1).
-void right_trmul(Ctx& cx, double* Y, int64_t ldy, const double* X, int64_t ldx, int64_t rows,
+template <typename XT>
+void right_trmul(Ctx& cx, double* Y, int64_t ldy, const XT* X, int64_t ldx, int64_t rows,
                  int L, const double* Rinv, int ldr = 0) {
   if (!cx.ok() || L <= 0 || rows <= 0) return;
+  const int mt = cdiv(L, 16);
+  if (mt <= 7 && (const void*)Y != (const void*)X) {
+    // one read of X on the matrix cores, one workgroup per CU (W takes most of the LDS)
+    const int rch = (int)std::max<int64_t>(64, rup<int64_t>(cdiv<int64_t>(rows, 256), 16));
+    const dim3 g1((unsigned)cdiv<int64_t>(rows, rch));
+    const int lw = ldr > 0 ? ldr : L;
+    switch (mt) {
+#define SK_RMUL(M)                                                                                \
+      case M:                                                                                     \
+        hipLaunchKernelGGL((k_rmul_mfma<XT, M>), g1, dim3(TPB), rmul_lds_bytes(M), cx.s, Y, ldy, X, ldx, \
+                           rows, L, Rinv, lw, rch);                                               \
+        break;
+      SK_RMUL(1) SK_RMUL(2) SK_RMUL(3) SK_RMUL(4) SK_RMUL(5) SK_RMUL(6) SK_RMUL(7)
+#undef SK_RMUL
+      default: break;
+    }
+    cx.chk();
+    return;
+  }
+  if constexpr (!std::is_same<XT, double>::value) {
+    cx.err = hipErrorInvalidValue;             // FP32 columns are read directly only for l <= 112
+    return;
+  } else {
   const int ny = cdiv(L, 16);
   const dim3 g((unsigned)cdiv<int64_t>(rows, kNnThreads), ny), blk(kNnThreads);
   hipLaunchKernelGGL((k_nn_update<double, 16>), g, blk, 0, cx.s, Y, ldy, (const double*)nullptr,
                      0, X, ldx, L, Rinv, ldr > 0 ? ldr : L, 16, rows, 1.0, (const Ctrl*)nullptr,
                      0, (const double*)nullptr, L);
   cx.chk();
+  }
 }
 
+constexpr bool kCholBlocked = true;
 void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double* Rinv, int* fail,
           double ill_rel = 0.0, double dev_rel = 0.0, int* ill = nullptr, int force_fail = 0) {
   if (!cx.ok()) return;
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), chol_lds_bytes(L), cx.s, Gm, L, L,
-                     shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill, force_fail);
+  if (kCholBlocked)
+    hipLaunchKernelGGL(k_chol_blk, dim3(1), dim3(kCholBlkThreads), cholb_lds_bytes(L), cx.s, Gm, L,
+                       L, shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill, force_fail);
+  else
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), chol_lds_bytes(L), cx.s, Gm, L, L,
+                       shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill, force_fail);
   cx.chk();
 }
 
@@ -2118,6 +2450,19 @@ hipError_t finalize_prepare() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)chol_lds_bytes(JMAX));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_chol_blk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)cholb_lds_bytes(JMAX));
+#define SK_RMUL_ATTR(M)                                                                        \
+  if (e == hipSuccess)                                                                         \
+    e = hipFuncSetAttribute((const void*)k_rmul_mfma<double, M>,                               \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)rmul_lds_bytes(M)); \
+  if (e == hipSuccess)                                                                         \
+    e = hipFuncSetAttribute((const void*)k_rmul_mfma<float, M>,                                \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)rmul_lds_bytes(M));
+  SK_RMUL_ATTR(1) SK_RMUL_ATTR(2) SK_RMUL_ATTR(3) SK_RMUL_ATTR(4) SK_RMUL_ATTR(5) SK_RMUL_ATTR(6)
+  SK_RMUL_ATTR(7)
+#undef SK_RMUL_ATTR
   if (e == hipSuccess) done[dev] = true;
   return e;
 }
@@ -2272,22 +2617,38 @@ bool one_block(Ctx& cx, FinalizeArgs& f, const Small& sm, Ctrl& hc) {
   const int l = f.l;
   const int64_t m = f.m, n = f.n;
   hipStream_t stream = cx.s;
-  double* X = f.Q2;                       // G in FP64, later the basis Q
+  double* X = f.Q2;                       // G in FP64 where it is widened; the basis Q
   int* fail = sm.info + 1;
   int* ill = sm.info + 2;
-  if (f.mode == M_F64)
-    hipLaunchKernelGGL(k_widen<double>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
-                       (const double*)f.G, f.ldg, m, l, X, f.ldq);
-  else
-    hipLaunchKernelGGL(k_widen<float>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
-                       (const float*)f.G, f.ldg, m, l, X, f.ldq);
+  // up to l = 112 the Gram and product kernels read G (FP32 or FP64) themselves
+  const bool direct = l <= 112;
+  if (!direct) {
+    if (f.mode == M_F64)
+      hipLaunchKernelGGL(k_widen<double>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
+                         (const double*)f.G, f.ldg, m, l, X, f.ldq);
+    else
+      hipLaunchKernelGGL(k_widen<float>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
+                         (const float*)f.G, f.ldg, m, l, X, f.ldq);
+  }
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, fail, 0);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, ill, 0);
   cx.chk();
   // Q1 = G R1^-1 with R1 = chol(G^T G); Q = Q1 R2^-1 with R2 = chol(Q1^T Q1)
-  gram_upper(cx, X, f.ldq, m, l, f.red_ws, sm.Jm);
+  if (!direct) {
+    gram_upper(cx, (const double*)X, f.ldq, m, l, f.red_ws, sm.Jm);
+  } else if (f.mode == M_F64) {
+    gram_upper(cx, (const double*)f.G, f.ldg, m, l, f.red_ws, sm.Jm);
+  } else {
+    gram_upper(cx, (const float*)f.G, f.ldg, m, l, f.red_ws, sm.Jm);
+  }
   chol(cx, sm.Jm, l, 0.0, sm.Wk, sm.Jk, fail, 1e-8, 0.0, ill);
-  right_trmul(cx, f.Q, f.ldq, X, f.ldq, m, l, sm.Jk);
+  if (!direct) {
+    right_trmul(cx, f.Q, f.ldq, (const double*)X, f.ldq, m, l, sm.Jk);
+  } else if (f.mode == M_F64) {
+    right_trmul(cx, f.Q, f.ldq, (const double*)f.G, f.ldg, m, l, sm.Jk);
+  } else {
+    right_trmul(cx, f.Q, f.ldq, (const float*)f.G, f.ldg, m, l, sm.Jk);
+  }
   gram_upper(cx, f.Q, f.ldq, m, l, f.red_ws, sm.Jm);
   chol(cx, sm.Jm, l, 0.0, sm.Wm, sm.RB, fail, 0.0, 1e-6, ill);
   if (f.U != nullptr) right_trmul(cx, X, f.ldq, f.Q, f.ldq, m, l, sm.RB);   // Q only feeds U
