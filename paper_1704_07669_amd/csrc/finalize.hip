@@ -1514,36 +1514,37 @@ __global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __re
 
   for (int kb = 0; kb < MT; ++kb) {
     const int k0 = 16 * kb;
-    // (a) the diagonal block, by wave 0: lane (bi, bc..bc+3) holds row bi, columns bc.. of it
+    // (a) the diagonal block, by wave 0 in registers: lane c < 16 holds column c (rows 0..15),
+    // takes the entries of other columns by lane broadcasts, and ends with R's rows in its
+    // column; lanes past 16 carry identity columns that no broadcast reads
     if (wave == 0) {
-      const int bi = lane >> 2, bc = (lane & 3) * 4;
+      const int c = lane;
+      double col[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) col[i] = c < 16 ? a[(k0 + i) * LS + k0 + c] : 0.0;
       bool fl = false;
+#pragma unroll
       for (int p = 0; p < 16; ++p) {
         const int P = k0 + p;
-        const double d = a[P * LS + P];          // the same in every lane: uniform exits
+        const double d = dpp::lane(col[p], p);   // A[P][P], the same in every lane
         if (P < L) {
           if ((force_fail && P == 0) || !(d > 0.0) || !(d < INFINITY)) fl = true;
           if (lane == 0 && ill_rel > 0.0 && !(d >= ill_rel * g0[P])) *ill = 1;
         }
         if (fl) break;
-        const double r = rsq_nr(d);              // refined 1/sqrt(d); R[P][P] = d / sqrt(d)
-        if (lane > p && lane < 16) a[P * LS + k0 + lane] *= r;
-        if (lane == 0) { a[P * LS + P] = d * r; rd[P] = d * r; ri[P] = r; }
-        wave_lds_sync();
-        if (bi > p) {
-          const double xi = a[P * LS + k0 + bi];
-          double v[4], x[4];
+        const double r = rsq_nr(d), rp = d * r;  // refined 1/sqrt(d); R[P][P] = d / sqrt(d)
+        if (lane == 0) { rd[P] = rp; ri[P] = r; }
+        col[p] = (c == p) ? rp : (c > p ? col[p] * r : col[p]);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            v[u] = a[(k0 + bi) * LS + k0 + bc + u];
-            x[u] = a[P * LS + k0 + bc + u];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (bc + u >= bi) a[(k0 + bi) * LS + k0 + bc + u] = fma(-xi, x[u], v[u]);
+        for (int i = p + 1; i < 16; ++i) {
+          const double rpi = dpp::lane(col[p], i);   // R[P][k0 + i]
+          col[i] = (c >= i) ? fma(-rpi, col[p], col[i]) : col[i];
         }
-        wave_lds_sync();
       }
+      if (c < 16)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (i <= c) a[(k0 + i) * LS + k0 + c] = col[i];
       if (fl && lane == 0) bad = 1;
     }
     __syncthreads();
