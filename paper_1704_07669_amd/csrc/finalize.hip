@@ -1194,259 +1194,25 @@ __global__ void k_rb_assemble(const double* __restrict__ C1, const double* __res
 // factorisation defined for cond(B) up to about 1/u and gives Q1 = B^T R1^-1 with a moderate
 // condition number; then Cholesky QR twice on Q1.  R_B = R3 R2 R1.  A pivot that is not positive
 // and finite in any pass sends the host to the Gram-Schmidt + TSQR path.
-constexpr int kCholTG = 32;                  // threads in a kCholTG x kCholTG grid
-constexpr int kCholThreads = kCholTG * kCholTG;
-constexpr int kCholSlots = JMAX / kCholTG;   // rows / columns per thread
-
-// L + 1 rows of L + 2 (row and column L: a sink for the clamped indices of partial tiles), then
-// rd[L] and dinv[L]
-size_t chol_lds_bytes(int L) {
-  return ((size_t)(L + 1) * (L + 2) + 2 * (size_t)L) * sizeof(double);
-}
-
 // Gm (upper triangle read, row-major, leading dimension ldg) + s I = R^T R with R upper triangular
 // with a positive diagonal; s = shift_rel tr(Gm) when shift_rel > 0, else 0.  Writes R and, when
 // Rinv is non-null, R^-1 (row-major, leading dimension ldr, zeros below the diagonal).  A pivot that
 // is not positive and finite sets *fail (left as it was otherwise) and writes identity factors.
 // Conditioning tests, each setting *ill: ill_rel > 0, a pivot below ill_rel times the diagonal
 // entry of Gm it started from; dev_rel > 0, an entry of R farther than dev_rel from the identity.
-// One workgroup, threads in a T x T grid (T = kCholTG), each owning rows ty + T m and columns
-// tx + T n of the trailing block, in T x T tiles.  Right-looking factorisation in LDS, two
-// pivots per step; then R^-1 by right-looking back substitution on the identity, two rows per
-// step from the bottom, with R^-1[k][c] (k < c) kept in the strictly lower triangle at [c][k].
-// Every loop bound is uniform: a step visits the tiles that meet its trailing block (in the
-// factorisation only those on or above the diagonal), and the rows and columns of a tile past
-// L - 1 are clamped to row / column L of the LDS matrix, a sink that nothing reads as data.  Every
-// step loads its operands into registers before it stores and ends with its only barrier.
 // The outputs of a failed factorisation: identity factors, so that the kernels that consume them
 // before the host reads the failure flag work on defined, finite values.
 __device__ __forceinline__ void chol_write_identity(double* __restrict__ R,
                                                     double* __restrict__ Rinv, int ldr, int L,
                                                     int tid) {
-  for (int idx = tid; idx < L * L; idx += kCholThreads) {
+  for (int idx = tid; idx < L * L; idx += blockDim.x) {
     const int i = idx / L, c = idx % L;
     R[(int64_t)i * ldr + c] = (i == c) ? 1.0 : 0.0;
     if (Rinv != nullptr) Rinv[(int64_t)i * ldr + c] = (i == c) ? 1.0 : 0.0;
   }
 }
 
-__global__ __launch_bounds__(kCholThreads) void k_chol(const double* __restrict__ Gm, int ldg,
-                                                       int L, double shift_rel,
-                                                       double* __restrict__ R,
-                                                       double* __restrict__ Rinv, int ldr,
-                                                       int* __restrict__ fail, double ill_rel,
-                                                       double dev_rel, int* __restrict__ ill,
-                                                       int force_fail) {
-  extern __shared__ double a[];
-  const int LS = L + 2, tid = threadIdx.x, ty = tid / kCholTG, tx = tid % kCholTG;
-  double* rd = a + (int64_t)(L + 1) * LS;
-  double* dinv = rd + L;
-  // the upper triangle of Gm; the strictly lower triangle and the sink row and column are zero
-  for (int idx = tid; idx < (L + 1) * LS; idx += kCholThreads) {
-    const int i = idx / LS, c = idx - i * LS;
-    a[idx] = (i < L && c < L && c >= i) ? Gm[(int64_t)i * ldg + c] : 0.0;
-  }
-  __syncthreads();
-  if (shift_rel > 0.0) {
-    if (tid < 64) {
-      double t = 0.0;
-      for (int i = tid; i < L; i += 64) t += a[i * LS + i];
-      t = wave_sum(t);
-      if (tid == 0) rd[0] = t * shift_rel;
-    }
-    __syncthreads();
-    const double sh = rd[0];
-    __syncthreads();
-    for (int i = tid; i < L; i += kCholThreads) a[i * LS + i] += sh;
-    __syncthreads();
-  }
-  // the diagonal of G, for the conditioning test (dinv is filled only after the factorisation)
-  for (int i = tid; i < L; i += kCholThreads) dinv[i] = a[i * LS + i];
-  __syncthreads();
-  // Two pivots per step.  With t = a[j][j+1] / d0, row j+1 after pivot j is a[j+1][c] - t a[j][c]
-  // and d1 is its diagonal entry; every thread forms what it needs of that row, and the trailing
-  // rows take both rank-1 updates at once.  Row j+1 itself is stored one step later (by the
-  // threads of ty = 0), when no thread reads it any more.
-  double w1[kCholSlots];                      // row j+1 of the previous step (ty == 0 threads)
-  int wrow = -1;
-  int j = 0;
-  for (; j + 1 < L; j += 2) {
-    if (ty == 0 && wrow >= 0) {
-#pragma unroll
-      for (int n = 0; n < kCholSlots; ++n) {
-        const int c = wrow + tx + kCholTG * n;
-        if (c < L) a[wrow * LS + c] = w1[n];
-      }
-    }
-    const double d0 = a[j * LS + j];           // same values in every thread: uniform exits
-    const double e01 = a[j * LS + j + 1];
-    const double tj = e01 / d0;
-    const double d1 = a[(j + 1) * LS + j + 1] - tj * e01;
-    if (tid == 0 && ill_rel > 0.0 && (!(d0 >= ill_rel * dinv[j]) || !(d1 >= ill_rel * dinv[j + 1])))
-      *ill = 1;
-    if (force_fail || !(d0 > 0.0) || !(d0 < INFINITY) || !(d1 > 0.0) || !(d1 < INFINITY)) {
-      if (tid == 0) *fail = 1;
-      chol_write_identity(R, Rinv, ldr, L, tid);
-      return;
-    }
-    if (tid == 0) { rd[j] = sqrt(d0); rd[j + 1] = sqrt(d1); }
-    const double i0 = 1.0 / d0, i1 = 1.0 / d1;
-    const int j2 = j + 2;
-    const int mc = (L - j2 + kCholTG - 1) / kCholTG;         // tiles along the trailing block (uniform)
-    // the two pivot rows at this thread's columns c = j2 + tx + T n of the trailing block
-    double c0[kCholSlots], c1[kCholSlots];
-#pragma unroll
-    for (int n = 0; n < kCholSlots; ++n) {
-      if (n < mc) {
-        const int c = min(j2 + tx + kCholTG * n, L);
-        const double x0 = a[j * LS + c];
-        c0[n] = x0;
-        c1[n] = a[(j + 1) * LS + c] - tj * x0;
-      }
-    }
-    if (ty == 0) {
-#pragma unroll
-      for (int n = 0; n < kCholSlots; ++n) {
-        const int c = j + 1 + tx + kCholTG * n;
-        w1[n] = c < L ? a[(j + 1) * LS + c] - tj * a[j * LS + c] : 0.0;
-      }
-    }
-    wrow = j + 1;
-    // a[i][c] -= a[j][i] a[j][c] / d0 + a1[i] a1[c] / d1 for j + 1 < i <= c < L; tiles (m, n)
-    // with n < m lie below the diagonal and are skipped, the diagonal tiles keep their lower part
-#pragma unroll
-    for (int m = 0; m < kCholSlots; ++m) {
-      if (m < mc) {
-        const int i = min(j2 + ty + kCholTG * m, L);
-        const double x0 = a[j * LS + i];
-        const double r0 = x0 * i0;
-        const double r1 = (a[(j + 1) * LS + i] - tj * x0) * i1;
-        double v[kCholSlots];
-#pragma unroll
-        for (int n = m; n < kCholSlots; ++n) {
-          const int c = min(j2 + tx + kCholTG * n, L);
-          if (n < mc) v[n] = a[i * LS + c];
-        }
-#pragma unroll
-        for (int n = m; n < kCholSlots; ++n) {
-          const int c = min(j2 + tx + kCholTG * n, L);
-          if (n < mc) {
-            const double u = fma(-r1, c1[n], fma(-r0, c0[n], v[n]));
-            a[i * LS + c] = (n > m || c >= i) ? u : v[n];
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (ty == 0 && wrow >= 0) {
-#pragma unroll
-    for (int n = 0; n < kCholSlots; ++n) {
-      const int c = wrow + tx + kCholTG * n;
-      if (c < L) a[wrow * LS + c] = w1[n];
-    }
-  }
-  if (j < L) {                                 // the last pivot of an odd L: nothing trails it
-    const double d = a[j * LS + j];
-    if (tid == 0 && ill_rel > 0.0 && !(d >= ill_rel * dinv[j])) *ill = 1;
-    if (force_fail || !(d > 0.0) || !(d < INFINITY)) {
-      if (tid == 0) *fail = 1;
-      chol_write_identity(R, Rinv, ldr, L, tid);
-      return;
-    }
-    if (tid == 0) rd[j] = sqrt(d);
-  }
-  __syncthreads();
-  for (int i = tid; i < L; i += kCholThreads) dinv[i] = 1.0 / rd[i];
-  __syncthreads();
-  for (int idx = tid; idx < L * L; idx += kCholThreads) {   // rows of R: row i over sqrt(d_i)
-    const int i = idx / L, c = idx % L;
-    if (c > i) a[i * LS + c] *= dinv[i];
-  }
-  __syncthreads();
-  if (Rinv != nullptr) {
-    // Solve R X = I from the bottom: row i of X is final once rows i+1.. have been subtracted from
-    // it; X[i][c] = rhs[i][c] / R_ii, then rhs[k][c] -= R[k][i] X[i][c] for k < i, c >= i.  The
-    // right-hand sides stay unscaled in the strictly lower triangle (rhs[i][c] at [c][i]); X[i][c]
-    // is formed where it is used, so a step needs one barrier.
-    // Two rows per step, i and h = i - 1: X[h][c] = (rhs[h][c] - R[h][i] X[i][c]) / R_hh is formed
-    // where it is used, and the updated rhs[h][c] is stored one step later (by the threads of
-    // ty = 0), when no thread reads it any more.  Thread (ty, tx) updates rows k = ty + T m < h
-    // at columns c = h + tx + T n.
-    double w1[kCholSlots];
-    int wcol = -1;                               // k of the stored-late entries rhs[k][c], c > k
-    int i = L - 1;
-    for (; i >= 1; i -= 2) {
-      if (ty == 0 && wcol >= 0) {
-#pragma unroll
-        for (int n = 0; n < kCholSlots; ++n) {
-          const int c = wcol + tx + kCholTG * n;
-          if (c > wcol && c < L) a[c * LS + wcol] = w1[n];
-        }
-      }
-      const int h = i - 1;
-      const double di = dinv[i], dh = dinv[h];
-      const double rhi = a[h * LS + i];          // R[i-1][i]
-      const int nc = (L - h + kCholTG - 1) / kCholTG;          // column tiles from h (uniform)
-      const int mk = (h + kCholTG - 1) / kCholTG;              // row tiles below h (uniform)
-      double xi[kCholSlots], xh[kCholSlots];
-#pragma unroll
-      for (int n = 0; n < kCholSlots; ++n) {
-        if (n < nc) {
-          const int c = h + tx + kCholTG * n;
-          const int cc = min(c, L);
-          const double yi = (c > i && c < L) ? a[cc * LS + i] * di : (c == i ? di : 0.0);
-          const double rh = (c > h && c < L) ? a[cc * LS + h] - rhi * yi : 0.0;
-          xi[n] = yi;
-          xh[n] = (c == h) ? dh : rh * dh;
-          if (ty == 0) w1[n] = rh;
-        }
-      }
-      wcol = h;
-#pragma unroll
-      for (int m = 0; m < kCholSlots; ++m) {
-        if (m < mk) {
-          const int k = min(ty + kCholTG * m, L);     // rows k >= h go to the sink row
-          const int kk = k < h ? k : L;
-          const double rki = a[kk * LS + i], rkh = a[kk * LS + h];
-          double v[kCholSlots];
-#pragma unroll
-          for (int n = 0; n < kCholSlots; ++n) {
-            const int c = min(h + tx + kCholTG * n, L);
-            if (n < nc) v[n] = a[c * LS + kk];
-          }
-#pragma unroll
-          for (int n = 0; n < kCholSlots; ++n) {
-            const int c = min(h + tx + kCholTG * n, L);
-            if (n < nc) a[c * LS + kk] = fma(-rkh, xh[n], fma(-rki, xi[n], v[n]));
-          }
-        }
-      }
-      __syncthreads();
-    }
-    if (ty == 0 && wcol >= 0) {
-#pragma unroll
-      for (int n = 0; n < kCholSlots; ++n) {
-        const int c = wcol + tx + kCholTG * n;
-        if (c > wcol && c < L) a[c * LS + wcol] = w1[n];
-      }
-    }
-    // (with i = 0 left over, row 0 of X needs no further update: X[0][c] = rhs[0][c] / R_00)
-    __syncthreads();
-  }
-  bool dev = false;
-  for (int idx = tid; idx < L * L; idx += kCholThreads) {
-    const int i = idx / L, c = idx % L;
-    const double v = c > i ? a[i * LS + c] : (c == i ? rd[i] : 0.0);
-    R[(int64_t)i * ldr + c] = v;
-    dev |= dev_rel > 0.0 && !(fabs(v - (c == i ? 1.0 : 0.0)) <= dev_rel);
-    if (Rinv != nullptr)
-      Rinv[(int64_t)i * ldr + c] = c > i ? a[c * LS + i] * dinv[i] : (c == i ? dinv[i] : 0.0);
-  }
-  if (dev) *ill = 1;                             // every writer stores the same value
-}
-
-// Blocked variant of k_chol (same contract), in 16 x 16 blocks of the matrix padded with the
+// The factorisation (k_chol_blk), in 16 x 16 blocks of the matrix padded with the
 // identity to LP = 16 MT rows: per block column, wave 0 factors the diagonal block (one pivot at a
 // time, its lanes in step through LDS, which orders one wave's accesses), one thread per column
 // solves the block row to its right (R_kk^T Y = A_k), and the waves update the trailing upper
@@ -2346,22 +2112,17 @@ void right_trmul(Ctx& cx, double* Y, int64_t ldy, const XT* X, int64_t ldx, int6
   }
 }
 
-constexpr bool kCholBlocked = true;
 void chol(Ctx& cx, const double* Gm, int L, double shift_rel, double* R, double* Rinv, int* fail,
           double ill_rel = 0.0, double dev_rel = 0.0, int* ill = nullptr, int force_fail = 0) {
   if (!cx.ok()) return;
-  if (kCholBlocked)
-    hipLaunchKernelGGL(k_chol_blk, dim3(1), dim3(kCholBlkThreads), cholb_lds_bytes(L), cx.s, Gm, L,
-                       L, shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill, force_fail);
-  else
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), chol_lds_bytes(L), cx.s, Gm, L, L,
-                       shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill, force_fail);
+  hipLaunchKernelGGL(k_chol_blk, dim3(1), dim3(kCholBlkThreads), cholb_lds_bytes(L), cx.s, Gm, L,
+                     L, shift_rel, R, Rinv, L, fail, ill_rel, dev_rel, ill, force_fail);
   cx.chk();
 }
 
 // R_B of B^T = Q_B R_B by Cholesky QR: two unshifted passes when B is well enough conditioned for
 // them (tested on the device, read back with the one wait this needs), else shifted Cholesky QR3
-// (see k_chol).  Returns the device matrix holding R_B (row-major L x L), or nullptr when a pivot
+// (see the shifted Cholesky QR3 note above k_chol_blk).  Returns the device matrix holding R_B (row-major L x L), or nullptr when a pivot
 // failed (then the caller factors B^T another way).  Q1 goes to the Q_B storage and Q2 to the H
 // storage (H is no longer needed at this point).
 const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L);
@@ -2393,7 +2154,7 @@ void chol_qr2(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L, int force_
   cx.chk();
 }
 
-// Shifted Cholesky QR3 of B^T (see k_chol); R_B as chol_qr, or nullptr when a pivot failed.
+// Shifted Cholesky QR3 of B^T (see k_chol_blk); R_B as chol_qr, or nullptr when a pivot failed.
 const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L) {
   const int64_t n = f.n;
   double* Gm = sm.Jm;
@@ -2448,9 +2209,6 @@ hipError_t finalize_prepare() {
 #undef SK_EPL_FN
     if (e == hipSuccess)
       e = hipFuncSetAttribute(kj, hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiLds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)chol_lds_bytes(JMAX));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_chol_blk, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)cholb_lds_bytes(JMAX));
