@@ -32,7 +32,9 @@ __device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
 // accumulators.  On gfx950 the FP64 16x16x4 instruction runs at half the rate of gfx942's, and the
 // compiler's hazard padding (18 wait states) is too short for it: without this drain the last
 // accumulator element can be read before it is written (observed on hardware for a single
-// dependent FP64 chain).  The scheduling barriers keep the padding between the two.
+// dependent FP64 chain).  The scheduling barriers keep the padding between the two.  Kernels with
+// FP64 chains in a loop drain inside the loop body, after each step's products, so that the
+// accumulator copies the compiler places at loop edges also come after the padding.
 __device__ __forceinline__ void mfma_drain() {
   __builtin_amdgcn_sched_barrier(0);
   asm volatile("s_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15" ::: "memory");
@@ -41,13 +43,6 @@ __device__ __forceinline__ void mfma_drain() {
 
 __device__ __forceinline__ f64x4 mma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-// FP64 product followed by the drain, so no read of its accumulator (including the copies the
-// compiler places at loop edges) can come early.
-__device__ __forceinline__ f64x4 mma_f64_drained(double a, double b, f64x4 c) {
-  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  mfma_drain();
-  return c;
 }
 __device__ __forceinline__ f32x4 mma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);

@@ -133,7 +133,7 @@ __device__ __forceinline__ typename BFrag<MODE>::type lds_frag(const uint8_t* p)
 
 __device__ __forceinline__ f64x4 mma(const Frag<M_F64>& a, const Frag<M_F64>& b, f64x4 c) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) c = mma_f64_drained(a.v[j], b.v[j], c);
+  for (int j = 0; j < 4; ++j) c = mma_f64(a.v[j], b.v[j], c);
   return c;
 }
 __device__ __forceinline__ f32x4 mma(const Frag<M_F32>& a, const Frag<M_F32>& b, f32x4 c) {
@@ -197,6 +197,9 @@ __device__ __forceinline__ void gemm1_step(const Src (&buf)[RS][PT<MODE>::V1], c
 #pragma unroll
     for (int rs = 0; rs < RS; ++rs) acc[rs][nt] = mma(a[rs], b, acc[rs][nt]);
   }
+  // FP64: the wait states once per step, inside the step, so that any copy of an accumulator the
+  // compiler places after it (loop edges) comes after them
+  if constexpr (MODE == M_F64) mfma_drain();
 }
 
 // Omega' chunks of g = a Omega: 256 bytes of each Omega' column (32 FP64 .. 256 FP8 values) per
@@ -421,7 +424,7 @@ template <> struct AFrag2<M_BF16X2> { bf16x8 hi, lo; };
 
 __device__ __forceinline__ f64x4 mma2(const GFrag<M_F64>& gq, const AFrag2<M_F64>& a, f64x4 c) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) c = mma_f64_drained(gq.v[e], a.v[e], c);
+  for (int e = 0; e < 4; ++e) c = mma_f64(gq.v[e], a.v[e], c);
   return c;
 }
 __device__ __forceinline__ f32x4 mma2(const GFrag<M_F32>& gq, const AFrag2<M_F32>& a, f32x4 c) {
@@ -549,6 +552,7 @@ __device__ __forceinline__ void gemm2_step(const Src (&a)[PT<MODE>::V2][PT<MODE>
   for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
     for (int j = 0; j < VC; ++j) acc[mt][j] = mma2(gq[mt], af[j], acc[mt][j]);
+  if constexpr (MODE == M_F64) mfma_drain();   // as in gemm1_step
 }
 
 // Grid: x = strips of 16*VC columns of a.  The WAVES waves of a workgroup take interleaved
