@@ -1250,6 +1250,7 @@ __global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __re
   double* g0 = ri + LP;                  // the diagonal the factorisation started from
   __shared__ int bad;
   __shared__ double shs;
+  __shared__ double prow[16];            // the current pivot row of a diagonal block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
   // the upper triangle of Gm, zeros below it, the identity on the padding
   stage8(LP * LP, tid, kCholBlkThreads,
@@ -1281,36 +1282,48 @@ __global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __re
   for (int kb = 0; kb < MT; ++kb) {
     const int k0 = 16 * kb;
     // (a) the diagonal block, by wave 0 in registers: lane c < 16 holds column c (rows 0..15),
-    // takes the entries of other columns by lane broadcasts, and ends with R's rows in its
-    // column; lanes past 16 carry identity columns that no broadcast reads
+    // takes the pivot row through LDS, and ends with R's rows in its column
     if (wave == 0) {
       const int c = lane;
       double col[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) col[i] = c < 16 ? a[(k0 + i) * LS + k0 + c] : 0.0;
       bool fl = false;
+      double piv[16];                            // the pivots, for the conditioning test after
+#pragma unroll
+      for (int p = 0; p < 16; ++p) piv[p] = 1.0;
 #pragma unroll
       for (int p = 0; p < 16; ++p) {
         const int P = k0 + p;
         const double d = dpp::lane(col[p], p);   // A[P][P], the same in every lane
-        if (P < L) {
-          if ((force_fail && P == 0) || !(d > 0.0) || !(d < INFINITY)) fl = true;
-          if (lane == 0 && ill_rel > 0.0 && !(d >= ill_rel * g0[P])) *ill = 1;
-        }
+        piv[p] = d;
+        if (P < L && ((force_fail && P == 0) || !(d > 0.0) || !(d < INFINITY))) fl = true;
         if (fl) break;
         const double r = rsq_nr(d), rp = d * r;  // refined 1/sqrt(d); R[P][P] = d / sqrt(d)
         if (lane == 0) { rd[P] = rp; ri[P] = r; }
         col[p] = (c == p) ? rp : (c > p ? col[p] * r : col[p]);
+        // row P of R to every lane through LDS (one store per lane, broadcast loads; one wave's
+        // LDS accesses execute in order, so the loads see the stores and the next pivot's stores
+        // follow these loads)
+        if (c < 16) prow[c] = col[p];
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int i = p + 1; i < 16; ++i) {
-          const double rpi = dpp::lane(col[p], i);   // R[P][k0 + i]
+          const double rpi = prow[i];                // R[P][k0 + i]
           col[i] = (c >= i) ? fma(-rpi, col[p], col[i]) : col[i];
         }
+        __builtin_amdgcn_wave_barrier();
       }
       if (c < 16)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
           if (i <= c) a[(k0 + i) * LS + k0 + c] = col[i];
+      if (lane == 0 && ill_rel > 0.0 && !fl) {
+        bool low = false;
+#pragma unroll
+        for (int p = 0; p < 16; ++p) low |= (k0 + p < L) && !(piv[p] >= ill_rel * g0[k0 + p]);
+        if (low) *ill = 1;
+      }
       if (fl && lane == 0) bad = 1;
     }
     __syncthreads();
