@@ -1479,18 +1479,64 @@ __global__ void k_diag(const double* __restrict__ R, int L, double* __restrict__
 }
 
 // ------------------------------------------------------------------------------------------------
-// One-sided Jacobi on M = R_B^T (L x L, L = l_eff): columns of M are the rows of R_B.  Round-robin
-// ordering: in each of the N-1 rounds (N = L rounded up to even) the N/2 disjoint pairs are rotated
-// in parallel, one 16-lane row per pair.  Outputs: sig (descending), perm, W = M J (column perm[j]
-// holds sigma_j u_j).
+// One-sided Jacobi on M = R_B^T (L x L, L = l_eff): columns of M are the rows of R_B.  Outputs:
+// sig (descending), perm, W = M J (column perm[j] holds sigma_j u_j).  Each sweep meets every
+// column pair once, in rounds of disjoint pairs rotated in parallel.
 constexpr int JSWEEPS = 40;
+constexpr int kJacobiGroups = 64;      // lane groups (one pair each per round); N / 2 <= 64
 
-__device__ __forceinline__ void rr_pair(int N, int r, int k, int& p, int& q) {
-  if (k == 0) { p = N - 1; q = r; }
-  else { p = (r + k) % (N - 1); q = (r - k + N - 1) % (N - 1); }
-  if (p > q) { const int t = p; p = q; q = t; }
+// Rounds of a sweep over n columns in the home / visitor order below: h = ceil(n / 2) rounds,
+// then the two halves of size h in parallel.
+__host__ __device__ constexpr int jacobi_rounds(int n) {
+  int r = 0;
+  while (n > 1) { const int h = (n + 1) >> 1; r += h; n = h; }
+  return r;
 }
 
+// The pair of lane group k in round r of a sweep over N (even) columns, as (home, visitor), or
+// 255 for both when the group idles.  The order: the n columns of a level (padded to 2h with an
+// empty column when n is odd) split into homes 0..h-1 and visitors h..2h-1; in round r < h group
+// j pairs home j with visitor h + (j + r) mod h, so every home meets every visitor; then the
+// homes and the visitors each repeat the scheme on their own, at the next level, the homes on
+// the first half of the level's groups (so every home stays with its group) and the visitors on
+// the second half.  A group's level-d range spans 64 >> d groups, which holds the h <= 64 >> d
+// pairs of that level.  Between two rounds a group thus changes only its visitor, except where
+// a level ends.
+__device__ __forceinline__ void jacobi_pair(int N, int r, int k, int& p, int& q) {
+  int n = N, base = 0, span = kJacobiGroups, depth = 0;
+  int off[8], pn[8];
+  p = q = 255;
+  while (depth < 8) {
+    const int h = (n + 1) >> 1;
+    if (r < h) {
+      const int j = k - base;
+      if (j < 0 || j >= h) return;
+      int v = j + r;
+      if (v >= h) v -= h;
+      int pos[2] = {j, h + v};
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        if (pos[s] >= n) return;                   // the padding column of this level
+        for (int d = depth - 1; d >= 0; --d) {
+          pos[s] += off[d];
+          if (pos[s] >= pn[d]) return;             // the padding column of an enclosing level
+        }
+      }
+      p = pos[0];
+      q = pos[1];
+      return;
+    }
+    r -= h;
+    const int half = span >> 1;
+    const bool second = (k - base) >= half;
+    off[depth] = second ? h : 0;
+    pn[depth] = n;
+    ++depth;
+    if (second) base += half;
+    n = h;
+    span = half;
+  }
+}
 
 // 1/x from the hardware estimate and one Newton step (about 2^-46 relative): enough for a
 // rotation angle, which only steers convergence.
@@ -1505,13 +1551,15 @@ __device__ __forceinline__ double rsq_nr1(double x) {
 
 // M (N columns, each padded to LPAD = 8 EPL rows, zero beyond L) lives in LDS with column stride
 // CS (LPAD, plus 8 when LPAD / 8 is even, so that the 8 pairs a wave touches spread over the LDS
-// banks); the round-robin pair table is precomputed once.  Eight lanes per pair, lane gl holding
-// rows gl + 8 e: the three inner products are reduced within the 8 lanes.  The right factor is not
-// accumulated: with M J = W (orthogonal columns, norms sigma), B^T = Q_B R_B and M = R_B^T,
-// B^T W = Q_B J S^2, so V = B^T W S^-2 (see run_finalize).
+// banks); the pair table is built once.  Eight lanes per pair, lane gl holding rows gl + 8 e: the
+// inner product is reduced within the 8 lanes.  A group keeps its home column in registers while
+// the home stays (it is written back only when it changes, and at the end of each sweep, if it was
+// rotated) and moves only the visitor through LDS.  The right factor is not accumulated: with
+// M J = W (orthogonal columns, norms sigma), B^T = Q_B R_B and M = R_B^T, B^T W = Q_B J S^2, so
+// V = B^T W S^-2 (see run_finalize).
 constexpr int kJacobiLds = 160 * 1024 - 4096;   // dynamic LDS limit of k_jacobi (static: norms)
 constexpr int kJacobiLpp = 8;                   // lanes per pair (the 8-lane reduction below)
-constexpr int kJacobiThreads = 64 * kJacobiLpp; // one lane group per pair for N <= 128
+constexpr int kJacobiThreads = kJacobiGroups * kJacobiLpp;
 // rows per lane (EPL) the kernel is built for: LPAD = kJacobiLpp EPL covers every L <= JMAX
 #define SK_JACOBI_EPLS(X) X(2) X(4) X(8) X(12) X(13) X(14) X(16)
 
@@ -1531,7 +1579,8 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
   __shared__ double nrm2[JMAX];           // squared column norms
   constexpr int LPP = kJacobiLpp, LPAD = LPP * EPL, CS = jacobi_cs(LPAD);
   const int N = (L + 1) & ~1;
-  uint8_t* pairs = reinterpret_cast<uint8_t*>(M + (int64_t)N * CS);   // (N-1) x N/2 x {p, q}
+  const int RN = jacobi_rounds(N);
+  uint8_t* pairs = reinterpret_cast<uint8_t*>(M + (int64_t)N * CS);   // RN x 64 x {home, visitor}
   const double tol = (double)L * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   // Convergence is quadratic at the end: once every pair of a sweep starts with a relative
@@ -1546,19 +1595,18 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
            return (col < L && i < L) ? RB[col * ldr + i] : 0.0;
          },
          [&](int idx, double v) { M[(idx / LPAD) * CS + idx % LPAD] = v; });
-  for (int idx = threadIdx.x; idx < (N - 1) * (N / 2); idx += kJacobiThreads) {
+  for (int idx = threadIdx.x; idx < RN * kJacobiGroups; idx += kJacobiThreads) {
     int p, q;
-    rr_pair(N, idx / (N / 2), idx % (N / 2), p, q);
+    jacobi_pair(N, idx / kJacobiGroups, idx % kJacobiGroups, p, q);
     pairs[2 * idx] = (uint8_t)p;
     pairs[2 * idx + 1] = (uint8_t)q;
   }
   __syncthreads();
-  const bool active = grp < N / 2;
   int sweep = 0;
   for (; sweep < JSWEEPS && N > 1; ++sweep) {
     // squared column norms, recomputed each sweep and carried through its rotations by
     // a' = a - t g, b' = b + t g (exact for the rotation that zeroes g)
-    for (int col = grp; col < N; col += kJacobiThreads / LPP) {
+    for (int col = grp; col < N; col += kJacobiGroups) {
       const double* mc = M + col * CS + gl;
       double s0 = 0, s1 = 0;
 #pragma unroll
@@ -1574,22 +1622,31 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
     }
     if (threadIdx.x == 0) { rotated = 0; large = 0; }
     __syncthreads();
-    int p = 0, q = 0;
-    if (active) { p = pairs[2 * grp]; q = pairs[2 * grp + 1]; }
-    for (int r = 0; r < N - 1; ++r) {
-      if (active) {
-        double* mp = M + p * CS + gl;
-        double* mq = M + q * CS + gl;
-        double xp[EPL], xq[EPL];
+    int p = pairs[2 * grp], q = pairs[2 * grp + 1];
+    int held = -1;                       // the home column held in xp (-1: none)
+    bool dirty = false;                  // xp rotated since it was loaded
+    double xp[EPL];
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) { xp[e] = mp[LPP * e]; xq[e] = mq[LPP * e]; }
-        const double a = nrm2[p], bb = nrm2[q];
-        // the next round's pair (the table never changes), fetched behind this round's loads
-        int pn = 0, qn = 0;
-        if (r + 1 < N - 1) {
-          const int pi = 2 * ((r + 1) * (N / 2) + grp);
-          pn = pairs[pi]; qn = pairs[pi + 1];
+    for (int e = 0; e < EPL; ++e) xp[e] = 0.0;
+    for (int r = 0; r < RN; ++r) {
+      // the next round's pair (the table never changes), fetched behind this round's loads
+      int pn = 255, qn = 255;
+      if (r + 1 < RN) {
+        const int pi = 2 * ((r + 1) * kJacobiGroups + grp);
+        pn = pairs[pi]; qn = pairs[pi + 1];
+      }
+      if (p != 255) {
+        if (p != held) {
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) xp[e] = M[p * CS + gl + LPP * e];
+          held = p;
+          dirty = false;
         }
+        double* mq = M + q * CS + gl;
+        double xq[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) xq[e] = mq[LPP * e];
+        const double a = nrm2[p], bb = nrm2[q];
         double g0 = 0, g1 = 0;
 #pragma unroll
         for (int e = 0; e < EPL; e += 2) {
@@ -1612,9 +1669,11 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
           const double s = c * t;
 #pragma unroll
           for (int e = 0; e < EPL; ++e) {
-            mp[LPP * e] = c * xp[e] - s * xq[e];
+            const double np = c * xp[e] - s * xq[e];
             mq[LPP * e] = s * xp[e] + c * xq[e];
+            xp[e] = np;
           }
+          dirty = true;
           if (gl == 0) {
             nrm2[p] = fmax(fma(-t, g, a), 0.0);
             nrm2[q] = fma(t, g, bb);
@@ -1622,8 +1681,18 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
             if (g * g > stop2 * (a * bb)) large = 1;
           }
         }
-        p = pn; q = qn;
       }
+      // the home goes back to LDS when the next round gives the group another one (and after
+      // the last round, so that the sweep ends with every column in LDS)
+      if (held >= 0 && pn != held) {
+        if (dirty) {
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) M[held * CS + gl + LPP * e] = xp[e];
+        }
+        held = -1;
+        dirty = false;
+      }
+      p = pn; q = qn;
       __syncthreads();
     }
     if (!rotated || !large) { ++sweep; break; }
@@ -1664,7 +1733,7 @@ inline int jacobi_epl(int L) {
 }
 size_t jacobi_lds_bytes(int L) {
   const int N = (L + 1) & ~1, CS = jacobi_cs(kJacobiLpp * jacobi_epl(L));
-  return (size_t)N * CS * sizeof(double) + (size_t)(N - 1) * (N / 2) * 2 + 16;
+  return (size_t)N * CS * sizeof(double) + (size_t)jacobi_rounds(N) * kJacobiGroups * 2 + 16;
 }
 
 // Gather the k leading factors: Wk = W(:, perm[0:kk]) / sig (U = Q Wk) and
