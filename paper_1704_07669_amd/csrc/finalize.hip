@@ -276,70 +276,110 @@ __device__ __forceinline__ void gram_fetch(const XT* __restrict__ X, int64_t ldx
   }
 }
 
-template <typename XT, int MT>
-__global__ __launch_bounds__(TPB) void k_gram_mfma(const XT* __restrict__ X, int64_t ldx,
-                                                   int L, int64_t rows, int RCH,
-                                                   double* __restrict__ part) {
-  constexpr int NTILE = gram_tile_count(MT);
-  __shared__ double red[(TPB / 64 - 1) * kGramRound * 4 * 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
-  const int64_t r_begin = (int64_t)blockIdx.x * RCH;
-  const int64_t r_end = min<int64_t>(rows, r_begin + RCH);
-  const bool aligned = (ldx % 4) == 0;
-  f64x4 acc[NTILE];
+// Eight waves: wave 2 r + h takes rows 16 r, 16 r + 64, ... of the chunk and half h of the upper
+// tiles (two waves per SIMD, so that one loads while the other multiplies, and half the
+// accumulators each); the four row groups of a half are summed through LDS in rounds.
+constexpr int kGramMfmaThreads = 512;
+constexpr int kGramGroups = kGramMfmaThreads / 128;   // row groups
+constexpr int kGramRound2 = 7;                     // tiles per LDS round
+
+template <int MT> struct GramHalves {
+  static constexpr int N = gram_tile_count(MT), H0 = (N + 1) / 2, H1 = N - H0;
+  static constexpr int first(int h) { return h ? H0 : 0; }
+  static constexpr int count(int h) { return h ? H1 : H0; }
+};
+
+template <int MT, int HALF>
+__device__ __forceinline__ void gram_half_mma(const double (&xa)[MT][4],
+                                              f64x4 (&acc)[GramHalves<MT>::H0]) {
+  constexpr int T0 = GramHalves<MT>::first(HALF), T1 = T0 + GramHalves<MT>::count(HALF);
 #pragma unroll
-  for (int t = 0; t < NTILE; ++t) acc[t] = f64x4{0, 0, 0, 0};
-  double xa[MT][4];
-  constexpr int STEP = (TPB / 64) * 16;
-  for (int64_t r0 = r_begin + wave * 16; r0 < r_end; r0 += STEP) {
-    gram_fetch<XT, MT>(X, ldx, L, r0 + 4 * g, r_end, r16, aligned && r0 + 16 <= r_end, xa);
+  for (int j = 0; j < 4; ++j) {
     int t = 0;
 #pragma unroll
     for (int nt = 0; nt < MT; ++nt)
 #pragma unroll
       for (int mt = 0; mt <= nt; ++mt) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[t] = mma_f64(xa[mt][j], xa[nt][j], acc[t]);
+        if (t >= T0 && t < T1) acc[t - T0] = mma_f64(xa[mt][j], xa[nt][j], acc[t - T0]);
         ++t;
       }
+  }
+}
+
+// Round u0 of the LDS sum: row groups 1.. store their tiles u0 .. u0 + kGramRound2 - 1 of the
+// half (STORE), or row group 0 adds them to its own and writes the chunk partials (!STORE).
+template <int MT, int HALF, bool STORE>
+__device__ __forceinline__ void gram_half_round(int u0, const f64x4 (&acc)[GramHalves<MT>::H0],
+                                                double* red, int rgp, int lane, int g, int r16,
+                                                int L, double* mine, int64_t per_slice) {
+  constexpr int T0 = GramHalves<MT>::first(HALF), T1 = T0 + GramHalves<MT>::count(HALF);
+  int t = 0;
+#pragma unroll
+  for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+    for (int mt = 0; mt <= nt; ++mt) {
+      const int u = t - T0;
+      if (t >= T0 && t < T1 && u >= u0 && u < u0 + kGramRound2) {
+        if constexpr (STORE) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            red[((((HALF * (kGramGroups - 1)) + rgp - 1) * kGramRound2 + (u - u0)) * 4 + i) * 64 +
+                lane] = acc[u][i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            double sm = acc[u][i];
+            for (int w = 1; w < kGramGroups; ++w)
+              sm += red[((((HALF * (kGramGroups - 1)) + w - 1) * kGramRound2 + (u - u0)) * 4 + i) *
+                            64 + lane];
+            const int a = mt * 16 + acc_row<double>(g, i), c = nt * 16 + r16;
+            if (a < L && c < L) mine[(c >> 5) * per_slice + (int64_t)a * 32 + (c & 31)] = sm;
+          }
+        }
+      }
+      ++t;
+    }
+}
+
+template <typename XT, int MT>
+__global__ __launch_bounds__(kGramMfmaThreads) void k_gram_mfma(const XT* __restrict__ X, int64_t ldx,
+                                                            int L, int64_t rows, int RCH,
+                                                            double* __restrict__ part) {
+  using GH = GramHalves<MT>;
+  __shared__ double red[2 * (kGramGroups - 1) * kGramRound2 * 4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
+  const int half = wave & 1, rgp = wave >> 1;
+  const int64_t r_begin = (int64_t)blockIdx.x * RCH;
+  const int64_t r_end = min<int64_t>(rows, r_begin + RCH);
+  const bool aligned = (ldx % 4) == 0;
+  f64x4 acc[GH::H0];
+#pragma unroll
+  for (int t = 0; t < GH::H0; ++t) acc[t] = f64x4{0, 0, 0, 0};
+  double xa[MT][4];
+  constexpr int STEP = kGramGroups * 16;
+  for (int64_t r0 = r_begin + rgp * 16; r0 < r_end; r0 += STEP) {
+    gram_fetch<XT, MT>(X, ldx, L, r0 + 4 * g, r_end, r16, aligned && r0 + 16 <= r_end, xa);
+    if (half == 0) gram_half_mma<MT, 0>(xa, acc);
+    else gram_half_mma<MT, 1>(xa, acc);
     mfma_drain();
   }
   const int64_t per_slice = (int64_t)gridDim.x * L * 32;
   double* mine = part + (int64_t)blockIdx.x * L * 32;
 #pragma unroll
-  for (int t0 = 0; t0 < NTILE; t0 += kGramRound) {
+  for (int u0 = 0; u0 < GH::H0; u0 += kGramRound2) {
     __syncthreads();
-    if (wave > 0) {
-#pragma unroll
-      for (int u = 0; u < kGramRound; ++u)
-        if (t0 + u < NTILE)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            red[(((wave - 1) * kGramRound + u) * 4 + i) * 64 + lane] = acc[t0 + u][i];
+    if (rgp > 0) {
+      if (half == 0) gram_half_round<MT, 0, true>(u0, acc, red, rgp, lane, g, r16, L, mine, per_slice);
+      else gram_half_round<MT, 1, true>(u0, acc, red, rgp, lane, g, r16, L, mine, per_slice);
     }
     __syncthreads();
-    if (wave == 0) {
-      int t = 0;
-#pragma unroll
-      for (int nt = 0; nt < MT; ++nt)
-#pragma unroll
-        for (int mt = 0; mt <= nt; ++mt) {
-          if (t >= t0 && t < t0 + kGramRound) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              double sm = acc[t][i];
-              for (int w = 1; w < TPB / 64; ++w)
-                sm += red[(((w - 1) * kGramRound + (t - t0)) * 4 + i) * 64 + lane];
-              const int a = mt * 16 + acc_row<double>(g, i), c = nt * 16 + r16;
-              if (a < L && c < L) mine[(c >> 5) * per_slice + (int64_t)a * 32 + (c & 31)] = sm;
-            }
-          }
-          ++t;
-        }
+    if (rgp == 0) {
+      if (half == 0) gram_half_round<MT, 0, false>(u0, acc, red, rgp, lane, g, r16, L, mine, per_slice);
+      else gram_half_round<MT, 1, false>(u0, acc, red, rgp, lane, g, r16, L, mine, per_slice);
     }
   }
   // the tiles (nt + 1, nt) of even nt: rows of slice nt / 2 below its diagonal tile
-  if (wave == 1) {
+  if (wave == 2) {
 #pragma unroll
     for (int nt = 0; nt + 1 < MT; nt += 2)
 #pragma unroll
@@ -369,10 +409,11 @@ __device__ __forceinline__ void rmul_fetch(const XT* __restrict__ X, int64_t ldx
     }
 }
 
+constexpr int kRmulThreads = 512;   // two waves per SIMD: one loads its rows while the other multiplies
 constexpr size_t rmul_lds_bytes(int MT) { return (size_t)(16 * MT) * (16 * MT + 1) * sizeof(double); }
 
 template <typename XT, int MT>
-__global__ __launch_bounds__(TPB) void k_rmul_mfma(double* __restrict__ Y, int64_t ldy,
+__global__ __launch_bounds__(kRmulThreads) void k_rmul_mfma(double* __restrict__ Y, int64_t ldy,
                                                    const XT* __restrict__ X, int64_t ldx,
                                                    int64_t rows, int L,
                                                    const double* __restrict__ W, int ldw,
@@ -380,7 +421,7 @@ __global__ __launch_bounds__(TPB) void k_rmul_mfma(double* __restrict__ Y, int64
   extern __shared__ double ws[];
   constexpr int LP = 16 * MT, WS = LP + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
-  stage8(LP * LP, threadIdx.x, TPB,
+  stage8(LP * LP, threadIdx.x, kRmulThreads,
          [&](int idx) {
            const int a = idx / LP, c = idx - a * LP;
            return (a < L && c < L && c >= a) ? W[(int64_t)a * ldw + c] : 0.0;
@@ -392,8 +433,8 @@ __global__ __launch_bounds__(TPB) void k_rmul_mfma(double* __restrict__ Y, int64
   __syncthreads();
   const int64_t r_begin = (int64_t)blockIdx.x * RCH;
   const int64_t r_end = min<int64_t>(rows, r_begin + RCH);
-  double xa0[MT][4], xa1[MT][4];
-  auto block = [&](const double (&xa)[MT][4], int64_t r0) {
+  double xa[MT][4];
+  auto block = [&](const double (&xb)[MT][4], int64_t r0) {
     f64x4 acc[MT];
 #pragma unroll
     for (int nt = 0; nt < MT; ++nt) acc[nt] = f64x4{0, 0, 0, 0};
@@ -403,7 +444,7 @@ __global__ __launch_bounds__(TPB) void k_rmul_mfma(double* __restrict__ Y, int64
       for (int t = 0; t <= nt; ++t)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[nt] = mma_f64(xa[t][j], ws[(16 * t + 4 * j + g) * WS + nt * 16 + r16], acc[nt]);
+          acc[nt] = mma_f64(xb[t][j], ws[(16 * t + 4 * j + g) * WS + nt * 16 + r16], acc[nt]);
     mfma_drain();
 #pragma unroll
     for (int nt = 0; nt < MT; ++nt)
@@ -414,14 +455,10 @@ __global__ __launch_bounds__(TPB) void k_rmul_mfma(double* __restrict__ Y, int64
         if (r < r_end && c < L) Y[(int64_t)c * ldy + r] = acc[nt][i];
       }
   };
-  int64_t r0 = r_begin + wave * 16;
-  if (r0 < r_end) rmul_fetch<XT, MT>(X, ldx, L, min<int64_t>(r0 + r16, rows - 1), g, xa0);
-  for (; r0 < r_end; r0 += 128) {
-    const int64_t r1 = r0 + 64, r2 = r0 + 128;
-    if (r1 < r_end) rmul_fetch<XT, MT>(X, ldx, L, min<int64_t>(r1 + r16, rows - 1), g, xa1);
-    block(xa0, r0);
-    if (r2 < r_end) rmul_fetch<XT, MT>(X, ldx, L, min<int64_t>(r2 + r16, rows - 1), g, xa0);
-    if (r1 < r_end) block(xa1, r1);
+  constexpr int SUB = (kRmulThreads / 64) * 16;
+  for (int64_t r0 = r_begin + wave * 16; r0 < r_end; r0 += SUB) {
+    rmul_fetch<XT, MT>(X, ldx, L, min<int64_t>(r0 + r16, rows - 1), g, xa);
+    block(xa, r0);
   }
 }
 
@@ -1469,14 +1506,44 @@ __global__ __launch_bounds__(JMAX) void k_trmm_upper(const double* __restrict__ 
   out[i * L + c] = s;
 }
 
+// Both products of k_trmm_upper in one launch (blockIdx.y picks the pair), the first also
+// writing its diagonal to diag0.
+__global__ __launch_bounds__(JMAX) void k_trmm_upper2(const double* __restrict__ X0,
+                                                      const double* __restrict__ Y0,
+                                                      double* __restrict__ out0,
+                                                      const double* __restrict__ X1,
+                                                      const double* __restrict__ Y1,
+                                                      double* __restrict__ out1, int L,
+                                                      double* __restrict__ diag0) {
+  __shared__ double xs[JMAX];
+  const bool second = blockIdx.y != 0;
+  const double* __restrict__ X = second ? X1 : X0;
+  const double* __restrict__ Y = second ? Y1 : Y0;
+  double* __restrict__ out = second ? out1 : out0;
+  const int i = blockIdx.x, c = threadIdx.x;
+  if (c < L) xs[c] = X[i * L + c];
+  __syncthreads();
+  if (c >= L) return;
+  double s = 0.0;
+  for (int k0 = i; k0 <= c; k0 += 8) {
+    double y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[u] = Y[(k0 + u <= c ? k0 + u : c) * L + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u <= c) s = fma(xs[k0 + u], y[u], s);
+  }
+  out[i * L + c] = s;
+  if (!second && c == i) diag0[i] = s;
+}
+
 __global__ void k_set_int(int* p, int v) {
   if (threadIdx.x == 0) *p = v;
 }
-
-// out[i] = R[i][i] for the L x L row-major R.
-__global__ void k_diag(const double* __restrict__ R, int L, double* __restrict__ out) {
-  for (int i = threadIdx.x; i < L; i += blockDim.x) out[i] = R[(int64_t)i * L + i];
+__global__ void k_set_int2(int* p, int* q, int v) {
+  if (threadIdx.x == 0) { *p = v; *q = v; }
 }
+
 
 // ------------------------------------------------------------------------------------------------
 // One-sided Jacobi on M = R_B^T (L x L, L = l_eff): columns of M are the rows of R_B.  Outputs:
@@ -1737,10 +1804,13 @@ size_t jacobi_lds_bytes(int L) {
 }
 
 // Gather the k leading factors: Wk = W(:, perm[0:kk]) / sig (U = Q Wk) and
-// Wv = W(:, perm[0:kk]) / sig^2 (V = B^T Wv).
+// Wv = W(:, perm[0:kk]) / sig^2 (V = B^T Wv); the first workgroup also writes S (k values, zero
+// past kk).
 __global__ void k_gather(const double* __restrict__ W, int ld, int L, const int* __restrict__ perm,
                          const double* __restrict__ sig, int kk, double* __restrict__ Wv,
-                         double* __restrict__ Wk) {
+                         double* __restrict__ Wk, int k, double* __restrict__ S) {
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < k; j += blockDim.x) S[j] = (j < kk) ? sig[j] : 0.0;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < L * kk; idx += gridDim.x * blockDim.x) {
     const int i = idx / kk, j = idx % kk;
     const int pc = perm[j];
@@ -1851,12 +1921,10 @@ __global__ void k_signed_transpose(const double* __restrict__ Vt, int64_t ldv, i
   }
 }
 
-__global__ void k_write_s(const double* __restrict__ sig, int kk, int k, double* __restrict__ S) {
-  for (int j = threadIdx.x; j < k; j += blockDim.x) S[j] = (j < kk) ? sig[j] : 0.0;
-}
-
-__global__ void k_init_ctrl(Ctrl* ctrl, int t, int l) {
+__global__ void k_init_ctrl(Ctrl* ctrl, int t, int l, int* zero0, int* zero1) {
   if (threadIdx.x == 0) {
+    if (zero0 != nullptr) *zero0 = 0;
+    if (zero1 != nullptr) *zero1 = 0;
     const int nf = ctrl->nonfinite;
     ctrl->r0 = 0.0;
     ctrl->last_iter = t - 1;
@@ -2119,13 +2187,13 @@ void gram_upper(Ctx& cx, const XT* X, int64_t ldx, int64_t rows, int L, double* 
   if (mt <= 7) {
     const dim3 g1(nch1);
     switch (mt) {
-      case 1: hipLaunchKernelGGL((k_gram_mfma<XT, 1>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 2: hipLaunchKernelGGL((k_gram_mfma<XT, 2>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 3: hipLaunchKernelGGL((k_gram_mfma<XT, 3>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 4: hipLaunchKernelGGL((k_gram_mfma<XT, 4>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 5: hipLaunchKernelGGL((k_gram_mfma<XT, 5>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      case 6: hipLaunchKernelGGL((k_gram_mfma<XT, 6>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
-      default: hipLaunchKernelGGL((k_gram_mfma<XT, 7>), g1, dim3(TPB), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 1: hipLaunchKernelGGL((k_gram_mfma<XT, 1>), g1, dim3(kGramMfmaThreads), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 2: hipLaunchKernelGGL((k_gram_mfma<XT, 2>), g1, dim3(kGramMfmaThreads), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 3: hipLaunchKernelGGL((k_gram_mfma<XT, 3>), g1, dim3(kGramMfmaThreads), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 4: hipLaunchKernelGGL((k_gram_mfma<XT, 4>), g1, dim3(kGramMfmaThreads), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 5: hipLaunchKernelGGL((k_gram_mfma<XT, 5>), g1, dim3(kGramMfmaThreads), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      case 6: hipLaunchKernelGGL((k_gram_mfma<XT, 6>), g1, dim3(kGramMfmaThreads), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
+      default: hipLaunchKernelGGL((k_gram_mfma<XT, 7>), g1, dim3(kGramMfmaThreads), 0, cx.s, X, ldx, L, rows, rch1, red_ws); break;
     }
     cx.chk();
     if (!cx.ok()) return;
@@ -2171,7 +2239,7 @@ void right_trmul(Ctx& cx, double* Y, int64_t ldy, const XT* X, int64_t ldx, int6
     switch (mt) {
 #define SK_RMUL(M)                                                                                \
       case M:                                                                                     \
-        hipLaunchKernelGGL((k_rmul_mfma<XT, M>), g1, dim3(TPB), rmul_lds_bytes(M), cx.s, Y, ldy, X, ldx, \
+        hipLaunchKernelGGL((k_rmul_mfma<XT, M>), g1, dim3(kRmulThreads), rmul_lds_bytes(M), cx.s, Y, ldy, X, ldx, \
                            rows, L, Rinv, lw, rch);                                               \
         break;
       SK_RMUL(1) SK_RMUL(2) SK_RMUL(3) SK_RMUL(4) SK_RMUL(5) SK_RMUL(6) SK_RMUL(7)
@@ -2223,8 +2291,7 @@ void chol_qr2(Ctx& cx, const FinalizeArgs& f, const Small& sm, int L, int force_
   // leave nonzero flags at sm.info[1] (a pivot failed) and sm.info[2] (a test failed), which the
   // caller reads later.  force_fail (a test hook) makes the first factorisation take its
   // failed-pivot exit at the first step.
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, fail, 0);
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, cx.s, ill, 0);
+  hipLaunchKernelGGL(k_set_int2, dim3(1), dim3(64), 0, cx.s, fail, ill, 0);
   cx.chk();
   gram_upper(cx, f.Bt, f.ldb, n, L, f.red_ws, Gm);
   chol(cx, Gm, L, 0.0, Racc, Ri, fail, 1e-8, 0.0, ill, force_fail);
@@ -2471,9 +2538,7 @@ bool one_block(Ctx& cx, FinalizeArgs& f, const Small& sm, Ctrl& hc) {
       hipLaunchKernelGGL(k_widen<float>, dim3(grid_for(m * l)), dim3(TPB), 0, stream,
                          (const float*)f.G, f.ldg, m, l, X, f.ldq);
   }
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, fail, 0);
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, ill, 0);
-  cx.chk();
+  // (the flags at fail and ill were zeroed by the control-block initialisation)
   // Q1 = G R1^-1 with R1 = chol(G^T G); Q = Q1 R2^-1 with R2 = chol(Q1^T Q1)
   if (!direct) {
     gram_upper(cx, (const double*)X, f.ldq, m, l, f.red_ws, sm.Jm);
@@ -2493,20 +2558,15 @@ bool one_block(Ctx& cx, FinalizeArgs& f, const Small& sm, Ctrl& hc) {
   gram_upper(cx, f.Q, f.ldq, m, l, f.red_ws, sm.Jm);
   chol(cx, sm.Jm, l, 0.0, sm.Wm, sm.RB, fail, 0.0, 1e-6, ill);
   if (f.U != nullptr) right_trmul(cx, X, f.ldq, f.Q, f.ldq, m, l, sm.RB);   // Q only feeds U
-  // R = R2 R1 and R^-1 = R1^-1 R2^-1 (upper triangular, lower parts zero)
-  if (cx.ok()) cx.err = launch_fill_f64(sm.Rg, (int64_t)l * l, 0.0, stream);
-  if (cx.ok()) cx.err = launch_fill_f64(sm.Rgi, (int64_t)l * l, 0.0, stream);
+  // R = R2 R1 and R^-1 = R1^-1 R2^-1 (upper triangular; the products write the zero lower parts
+  // too), and the diagonal of R to sm.sG
   if (cx.ok()) {
-    hipLaunchKernelGGL(k_trmm_upper, dim3(l), dim3(JMAX), 0, stream, sm.Wm, sm.Wk, sm.Rg, l);
-    hipLaunchKernelGGL(k_trmm_upper, dim3(l), dim3(JMAX), 0, stream, sm.Jk, sm.RB, sm.Rgi, l);
-  }
-  cx.chk();
-  // one wait: the acceptance flags and the diagonal of R (the rank guard sizes what follows),
-  // read back together: the diagonal goes to sm.sG, which follows the flags in the small matrices
-  if (cx.ok()) {
-    hipLaunchKernelGGL(k_diag, dim3(1), dim3(JMAX), 0, stream, sm.Rg, l, sm.sG);
+    hipLaunchKernelGGL(k_trmm_upper2, dim3(l, 2), dim3(JMAX), 0, stream, sm.Wm, sm.Wk, sm.Rg,
+                       sm.Jk, sm.RB, sm.Rgi, l, sm.sG);
     cx.chk();
   }
+  // one wait: the acceptance flags and the diagonal of R (the rank guard sizes what follows),
+  // read back together: the diagonal went to sm.sG, which follows the flags in the small matrices
   const int64_t dofs = sm.sG - reinterpret_cast<const double*>(sm.info);
   std::vector<double> rb((size_t)(dofs + l));
   if (cx.ok())
@@ -2548,7 +2608,8 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   Ctrl hc{};
   bool done = false;
   if (b == l && f.Q2 != nullptr && !f.force_loop) {
-    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, 1, l);
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, 1, l, sm.info + 1,
+                       sm.info + 2);
     cx.chk();
     done = cx.ok() && one_block(cx, f, sm, hc);
     if (!cx.ok()) return cx.err;
@@ -2566,7 +2627,8 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   // block was flagged as too ill-conditioned for it, the loop is repeated with Householder TSQR.
   for (int attempt = f.force_loop ? 1 : 0; attempt < 2 && cx.ok() && !done; ++attempt) {
     const bool chol = (attempt == 0);
-    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l);
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l, (int*)nullptr,
+                       (int*)nullptr);
     cx.chk();
     for (int i = 0; i < t && cx.ok(); ++i) {
       const int c0 = i * b, p = c0;
@@ -2706,7 +2768,7 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
     cx.chk();
     if (!cx.ok()) return cx.err;
     hipLaunchKernelGGL(k_gather, dim3(cdiv(L * kk, 256)), dim3(256), 0, stream, sm.Wm, L, L,
-                       sm.perm, sm.sig, kk, sm.Jk, sm.Wk);
+                       sm.perm, sm.sig, kk, sm.Jk, sm.Wk, f.k, f.S);
     cx.chk();
     // V (column-major temp in the H storage) = B^T W S^-2 in column slices of 16, its signs, then
     // the row-major outputs
@@ -2729,9 +2791,6 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
                          f.Q, f.ldq, L, sm.Wk, kk, f.k, sm.sgn, m, f.U, f.ldu, 0);
       cx.chk();
     }
-    if (!cx.ok()) return cx.err;
-    hipLaunchKernelGGL(k_write_s, dim3(1), dim3(256), 0, stream, sm.sig, kk, f.k, f.S);
-    cx.chk();
     if (!cx.ok()) return cx.err;
     if (rb_mode != 0) break;
     int hflags[2] = {1, 1};
@@ -2789,8 +2848,7 @@ hipError_t run_power_omega(PowerArgs& p, hipStream_t stream) {
   int route = p.route;
   for (;;) {
     if (route == 0) {
-      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, fail, 0);
-      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, ill, 0);
+      hipLaunchKernelGGL(k_set_int2, dim3(1), dim3(64), 0, stream, fail, ill, 0);
       cx.chk();
       gram_upper(cx, p.H, p.ldh, n, L, p.red_ws, sm.Jm);
       chol(cx, sm.Jm, L, 0.0, sm.Wk, sm.Jk, fail, 1e-8, 0.0, ill);
@@ -2800,8 +2858,7 @@ hipError_t run_power_omega(PowerArgs& p, hipStream_t stream) {
       right_trmul(cx, p.om64, p.ldo, p.W1, p.ldw, n, L, sm.Jk);
     } else if (route == 2) {
       const double shift_rel = 11.0 * ((double)n * L + (double)L * (L + 1)) * u;
-      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, fail, 0);
-      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, ill, 0);
+      hipLaunchKernelGGL(k_set_int2, dim3(1), dim3(64), 0, stream, fail, ill, 0);
       cx.chk();
       gram_upper(cx, p.H, p.ldh, n, L, p.red_ws, sm.Jm);
       chol(cx, sm.Jm, L, shift_rel, sm.Wk, sm.Jk, fail);
