@@ -1319,7 +1319,10 @@ __global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __re
   for (int kb = 0; kb < MT; ++kb) {
     const int k0 = 16 * kb;
     // (a) the diagonal block, by wave 0 in registers: lane c < 16 holds column c (rows 0..15),
-    // takes the pivot row through LDS, and ends with R's rows in its column
+    // takes the pivot row through LDS, and ends with R's rows in its column.  The scalings and
+    // updates are not masked to the upper triangle: an entry on or above the diagonal only ever
+    // meets entries on or above it (its own column's pivot-row entry and the pivot row), and the
+    // entries below it, which they also change, are neither read nor written back.
     if (wave == 0) {
       const int c = lane;
       double col[16];
@@ -1338,17 +1341,14 @@ __global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __re
         if (fl) break;
         const double r = rsq_nr(d), rp = d * r;  // refined 1/sqrt(d); R[P][P] = d / sqrt(d)
         if (lane == 0) { rd[P] = rp; ri[P] = r; }
-        col[p] = (c == p) ? rp : (c > p ? col[p] * r : col[p]);
+        col[p] = (c == p) ? rp : col[p] * r;
         // row P of R to every lane through LDS (one store per lane, broadcast loads; one wave's
         // LDS accesses execute in order, so the loads see the stores and the next pivot's stores
         // follow these loads)
         if (c < 16) prow[c] = col[p];
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int i = p + 1; i < 16; ++i) {
-          const double rpi = prow[i];                // R[P][k0 + i]
-          col[i] = (c >= i) ? fma(-rpi, col[p], col[i]) : col[i];
-        }
+        for (int i = p + 1; i < 16; ++i) col[i] = fma(-prow[i], col[p], col[i]);   // R[P][k0 + i]
         __builtin_amdgcn_wave_barrier();
       }
       if (c < 16)
