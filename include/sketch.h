@@ -226,6 +226,14 @@ sketch_status sketch_debug_state(sketch_t h, double* G_dev, double* H_dev, int64
 sketch_status sketch_philox_words(uint64_t seed, uint64_t first, int64_t count, uint64_t* out_dev,
                                   void* hip_stream);
 
+/* The pair order of one sweep of the one-sided Jacobi SVD of R_B^T (svd(B), Alg. 4 steps 16-19),
+ * computed on the host by the same code the kernel runs, for testing.  For n columns (0 <= n <= 128,
+ * rounded up to even), writes rounds x 64 x 2 bytes to host memory `pairs` (capacity bytes): for
+ * round r and lane group g, pairs[2 (64 r + g)] is the column the group keeps in registers and
+ * pairs[2 (64 r + g) + 1] the one it takes through LDS, both 255 when the group idles that round.
+ * *rounds = the number of rounds.  E_INVAL for another n or a table that does not fit. */
+sketch_status sketch_jacobi_schedule(int32_t n, uint8_t* pairs, int64_t capacity, int32_t* rounds);
+
 /* Per-kernel timing of the pass (HIP events on the launch stream, taken around every launch of
  * the two streaming products while enabled).  sketch_profile_read waits for the stream and
  * returns, for kind 0 = g = a Omega (incl. its split reduction), 1 = H += a^T g, 2 = finalize:

@@ -26,7 +26,8 @@ EXPORTED = [
     "sketch_debug_force_paths",
     "sketch_get_omega", "sketch_checkpoint_size", "sketch_checkpoint", "sketch_restore",
     "sketch_merge", "sketch_pca_static", "sketch_power_restart", "sketch_column_mean",
-    "sketch_debug_state", "sketch_philox_words", "sketch_profile_enable", "sketch_profile_read",
+    "sketch_debug_state", "sketch_philox_words", "sketch_jacobi_schedule",
+    "sketch_profile_enable", "sketch_profile_read",
     "sketch_destroy", "sketch_last_error",
     "sketch_server_workspace_size", "sketch_server_stream_bytes", "sketch_server_create",
     "sketch_server_open", "sketch_server_submit", "sketch_server_submit_ex", "sketch_server_clock",
@@ -107,6 +108,7 @@ def load_library(path=None):
                                     ctypes.POINTER(I32), P]),
         "sketch_debug_state": (I32, [P, P, P, ctypes.POINTER(I64)]),
         "sketch_philox_words": (I32, [U64, U64, I64, P, P]),
+        "sketch_jacobi_schedule": (I32, [I32, P, I64, ctypes.POINTER(I32)]),
         "sketch_profile_enable": (I32, [P, I32]),
         "sketch_profile_read": (I32, [P, I32, ctypes.POINTER(I64), ctypes.POINTER(D)]),
         "sketch_destroy": (I32, [P]),
@@ -263,6 +265,16 @@ def sketch_debug_state(h, G, H):
 def sketch_philox_words(seed, first, count, out, stream=None):
     _check(load_library().sketch_philox_words(seed, first, count, _ptr(out),
                                               _stream_handle(stream)))
+
+
+def sketch_jacobi_schedule(n):
+    """The pair table of one Jacobi sweep over n columns: a bytes object of rounds x 64 x 2
+    (home, visitor; 255 for an idle group) and the number of rounds."""
+    cap = 2 * 64 * 128
+    buf = (ctypes.c_uint8 * cap)()
+    rounds = ctypes.c_int32()
+    _check(load_library().sketch_jacobi_schedule(n, buf, cap, ctypes.byref(rounds)))
+    return bytes(buf[:rounds.value * 128]), rounds.value
 
 
 def sketch_profile_enable(h, on=True):

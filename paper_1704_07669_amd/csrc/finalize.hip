@@ -1569,7 +1569,7 @@ __host__ __device__ constexpr int jacobi_rounds(int n) {
 // the second half.  A group's level-d range spans 64 >> d groups, which holds the h <= 64 >> d
 // pairs of that level.  Between two rounds a group thus changes only its visitor, except where
 // a level ends.
-__device__ __forceinline__ void jacobi_pair(int N, int r, int k, int& p, int& q) {
+__host__ __device__ __forceinline__ void jacobi_pair(int N, int r, int k, int& p, int& q) {
   int n = N, base = 0, span = kJacobiGroups, depth = 0;
   int off[8], pn[8];
   p = q = 255;
@@ -2341,6 +2341,23 @@ const double* chol_qr3_shifted(Ctx& cx, const FinalizeArgs& f, const Small& sm, 
 }
 
 }  // namespace
+
+// The pair table of one Jacobi sweep over n columns (n rounded up to even), as k_jacobi builds
+// it: rounds x 64 lane groups x {home, visitor}, 255 for an idle group.  Returns the number of
+// rounds, or -1 when n is outside 0..JMAX or `cap` bytes cannot hold the table.
+int jacobi_schedule(int n, uint8_t* out, int64_t cap) {
+  if (n < 0 || n > JMAX) return -1;
+  const int N = (n + 1) & ~1, RN = jacobi_rounds(N);
+  if (out == nullptr || cap < (int64_t)RN * kJacobiGroups * 2) return -1;
+  for (int r = 0; r < RN; ++r)
+    for (int k = 0; k < kJacobiGroups; ++k) {
+      int p, q;
+      jacobi_pair(N, r, k, p, q);
+      out[2 * (r * kJacobiGroups + k)] = (uint8_t)p;
+      out[2 * (r * kJacobiGroups + k) + 1] = (uint8_t)q;
+    }
+  return RN;
+}
 
 // Raises the dynamic LDS limits of the kernels that need more than the default, once per device
 // (the attribute belongs to the device the call runs on), safely from any number of threads.

@@ -173,6 +173,8 @@ hipError_t centre_sketch(int mode, void* G, int64_t ldg, int64_t m, double* H, i
 constexpr int kMaxDevices = 64;
 // Once per device and thread-safe: kernel attributes the finalize needs (call on the device used).
 hipError_t finalize_prepare();
+// The pair table of one Jacobi sweep over n columns (host memory); rounds, or -1 (finalize.hip).
+int jacobi_schedule(int n, uint8_t* out, int64_t cap);
 size_t finalize_small_elems(int l, int b);
 size_t tsqr_workspace_elems(int64_t rows, int b);
 size_t reduce_workspace_elems(int64_t rows, int p, int q);

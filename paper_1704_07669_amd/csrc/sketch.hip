@@ -915,6 +915,15 @@ sketch_status sketch_philox_words(uint64_t seed, uint64_t first, int64_t count, 
   return SKETCH_OK;
 }
 
+sketch_status sketch_jacobi_schedule(int32_t n, uint8_t* pairs, int64_t capacity,
+                                     int32_t* rounds) {
+  if (!rounds) return fail(SKETCH_E_INVAL, "bad arguments");
+  const int r = jacobi_schedule(n, pairs, capacity);
+  if (r < 0) return fail(SKETCH_E_INVAL, "n outside 0..128 or the table does not fit");
+  *rounds = r;
+  return SKETCH_OK;
+}
+
 sketch_status sketch_profile_enable(sketch_t h, int32_t on) {
   if (sketch_status st = check_handle(h)) return st;
   h->prof = (on != 0);
