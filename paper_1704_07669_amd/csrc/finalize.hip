@@ -94,20 +94,20 @@ __device__ __forceinline__ void block_sum_range(const double (&v)[CMAX], double*
   __syncthreads();
 }
 
-// Copies count values into shared memory with nthr threads, eight loads in flight per thread: each
-// batch issues all of its loads (load(i), i < count) before any of its stores (store(i, v)), so a
-// batch costs one memory latency instead of eight.
-template <typename LoadF, typename StoreF>
+// Copies count values into shared memory with nthr threads, D loads in flight per thread (eight by
+// default): each batch issues all of its loads (load(i), i < count) before any of its stores
+// (store(i, v)), so a batch costs one memory latency instead of D.
+template <int D = 8, typename LoadF, typename StoreF>
 __device__ __forceinline__ void stage8(int count, int tid, int nthr, LoadF load, StoreF store) {
-  for (int base = 0; base < count; base += 8 * nthr) {
-    double v[8];
+  for (int base = 0; base < count; base += D * nthr) {
+    double v[D];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < D; ++u) {
       const int i = base + tid + u * nthr;
       v[u] = load(i < count ? i : count - 1);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < D; ++u) {
       const int i = base + tid + u * nthr;
       if (i < count) store(i, v[u]);
     }
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kRmulThreads) void k_rmul_mfma(double* __restrict__
   extern __shared__ double ws[];
   constexpr int LP = 16 * MT, WS = LP + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r16 = lane & 15;
-  stage8(LP * LP, threadIdx.x, kRmulThreads,
+  stage8<25>(LP * LP, threadIdx.x, kRmulThreads,
          [&](int idx) {
            const int a = idx / LP, c = idx - a * LP;
            return (a < L && c < L && c >= a) ? W[(int64_t)a * ldw + c] : 0.0;
@@ -1289,8 +1289,9 @@ __global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __re
   __shared__ double shs;
   __shared__ double prow[16];            // the current pivot row of a diagonal block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
-  // the upper triangle of Gm, zeros below it, the identity on the padding
-  stage8(LP * LP, tid, kCholBlkThreads,
+  // the upper triangle of Gm, zeros below it, the identity on the padding (all 112^2 entries in
+  // one batch of loads at the largest size)
+  stage8<25>(LP * LP, tid, kCholBlkThreads,
          [&](int idx) {
            const int i = idx / LP, c = idx - i * LP;
            return (i < L && c < L) ? (c >= i ? Gm[(int64_t)i * ldg + c] : 0.0)
@@ -1656,7 +1657,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double* __restr
   // that sweep (which would only confirm convergence) is skipped.
   const double stop2 = tol / 64.0;
   const int grp = threadIdx.x / LPP, gl = threadIdx.x % LPP;
-  stage8(N * LPAD, threadIdx.x, kJacobiThreads,                        // M(:, col) = R_B(col, :)^T
+  stage8<21>(N * LPAD, threadIdx.x, kJacobiThreads,                    // M(:, col) = R_B(col, :)^T
          [&](int idx) {
            const int col = idx / LPAD, i = idx % LPAD;
            return (col < L && i < L) ? RB[col * ldr + i] : 0.0;
