@@ -2091,6 +2091,10 @@ struct Small {
   double *Rg, *Rgi;  // one column block: R of G and its inverse
   int* perm; int* info;
 };
+// Flags in sm.info: [0] Jacobi sweeps, [1] and [2] the R_B Cholesky QR2 tests, [kObFail] and
+// [kObIll] the one-block Cholesky QR2 tests.
+constexpr int kObFail = 4, kObIll = 5;
+
 Small carve_small(double* base, int l, int b) {
   const int P = l * 32;   // p x b blocks with p <= l, b <= 32
   Small sm;
@@ -2526,9 +2530,13 @@ hipError_t centre_sketch(int mode, void* G, int64_t ldg, int64_t m, double* H, i
 // Alg. 4 steps 9-15 with t = 1: Y_1 = G, [Q, R] = qr(G) with the re-orthogonalisation of Sec. 3.2
 // (here: Cholesky QR applied twice), the rank guard on R's diagonal, and B = R^{-T} H^T, which is
 // Eq. 9 with Q and B still empty.  Every step is a tall product or reduction over all rows at
-// once instead of t = l / b dependent rounds of them.  Returns false when Cholesky QR2's tests
-// reject G (a pivot below 1e-8 of its diagonal entry, or a second factor more than 1e-6 from I):
-// the caller then runs the blocked loop, whose Householder TSQR fallback handles any G.
+// once instead of t = l / b dependent rounds of them.  Nothing here waits for the device: B^T is
+// formed for all l columns, and Cholesky QR2's tests (flags at sm.info[4] and [5]: a pivot below
+// 1e-8 of its diagonal entry, or a second factor more than 1e-6 from I) and R's diagonal (sm.sG,
+// for the rank guard) are read with the finalize's last wait.  If the tests reject G the caller
+// then runs the blocked loop, whose Householder TSQR fallback handles any G; if the rank guard
+// keeps fewer columns it forms the SVD again from the leading ones (B^T's leading columns do not
+// depend on the later ones, R^-1 being upper triangular).
 template <typename GT>
 __global__ void k_widen(const GT* __restrict__ G, int64_t ldg, int64_t rows, int l,
                         double* __restrict__ X, int64_t ldx) {
@@ -2544,8 +2552,8 @@ bool one_block(Ctx& cx, FinalizeArgs& f, const Small& sm, Ctrl& hc) {
   const int64_t m = f.m, n = f.n;
   hipStream_t stream = cx.s;
   double* X = f.Q2;                       // G in FP64 where it is widened; the basis Q
-  int* fail = sm.info + 1;
-  int* ill = sm.info + 2;
+  int* fail = sm.info + kObFail;
+  int* ill = sm.info + kObIll;
   // up to l = 112 the Gram and product kernels read G (FP32 or FP64) themselves
   const bool direct = l <= 112;
   if (!direct) {
@@ -2583,29 +2591,21 @@ bool one_block(Ctx& cx, FinalizeArgs& f, const Small& sm, Ctrl& hc) {
                        sm.Jk, sm.RB, sm.Rgi, l, sm.sG);
     cx.chk();
   }
-  // one wait: the acceptance flags and the diagonal of R (the rank guard sizes what follows),
-  // read back together: the diagonal went to sm.sG, which follows the flags in the small matrices
-  const int64_t dofs = sm.sG - reinterpret_cast<const double*>(sm.info);
-  std::vector<double> rb((size_t)(dofs + l));
-  if (cx.ok())
-    cx.err = read_back(rb.data(), sm.info, rb.size() * sizeof(double), stream, f.host_pin,
-                       f.host_ev);
-  const int* flags = reinterpret_cast<const int*>(rb.data()) + 1;   // info[1], info[2]
-  if (!cx.ok() || flags[0] != 0 || flags[1] != 0) return false;
-  // rank guard: the leading columns whose R diagonal exceeds tau R_00
-  const double* diag = rb.data() + dofs;
-  const double r0 = diag[0];
-  int keep = 0;
-  while (keep < l && fabs(diag[keep]) > kGuardTau * r0) ++keep;
-  if (!(r0 > 0.0)) keep = 0;
-  // B^T = H R^-1 over the kept columns (the leading block of R^-1 inverts R's leading block)
-  right_trmul(cx, f.Bt, f.ldb, f.H, f.ldh, n, keep, sm.Rgi, l);
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, &f.ctrl->l_eff, keep);
-  cx.chk();
+  // B^T = H R^-1 over all l columns (ctrl->l_eff = l from the control-block initialisation)
+  right_trmul(cx, f.Bt, f.ldb, f.H, f.ldh, n, l, sm.Rgi, l);
   f.Q = X;
-  hc.l_eff = keep;
+  hc.l_eff = l;
   f.path_loop = 2;
   return cx.ok();
+}
+
+// The rank guard of the one-block path: the leading columns whose R diagonal exceeds tau R_00.
+int one_block_keep(const double* diag, int l) {
+  const double r0 = diag[0];
+  if (!(r0 > 0.0)) return 0;
+  int keep = 0;
+  while (keep < l && fabs(diag[keep]) > kGuardTau * r0) ++keep;
+  return keep;
 }
 
 hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
@@ -2625,12 +2625,15 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   // ---------------- one column block when b = l (see one_block)
   Ctrl hc{};
   bool done = false;
+  bool verify = false;                    // one_block's tests and rank guard not yet read
+  double* const q_loop = f.Q;             // the blocked loop's basis storage
   if (b == l && f.Q2 != nullptr && !f.force_loop) {
-    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, 1, l, sm.info + 1,
-                       sm.info + 2);
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, 1, l, sm.info + kObFail,
+                       sm.info + kObIll);
     cx.chk();
     done = cx.ok() && one_block(cx, f, sm, hc);
     if (!cx.ok()) return cx.err;
+    verify = done;
   }
   // the blocked loop works on blocks of at most 32 columns: a wider b (b = l) that one_block did
   // not take runs as the widest divisor of l that fits
@@ -2643,179 +2646,235 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
 
   // ---------------- column-block loop (Alg. 4 steps 9-15).  Cholesky QR of the blocks first; if a
   // block was flagged as too ill-conditioned for it, the loop is repeated with Householder TSQR.
-  for (int attempt = f.force_loop ? 1 : 0; attempt < 2 && cx.ok() && !done; ++attempt) {
-    const bool chol = (attempt == 0);
-    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l, (int*)nullptr,
-                       (int*)nullptr);
-    cx.chk();
-    for (int i = 0; i < t && cx.ok(); ++i) {
-      const int c0 = i * b, p = c0;
-      double* Qi = f.Q + (int64_t)c0 * f.ldq;
-      // W = B Omega_i  (B^T is n x p)
-      tn(cx, f.Bt, f.ldb, f.om64 + (int64_t)c0 * f.ldo, f.ldo, p, b, n, f.red_ws, sm.W, b, ctrl, i);
-      // Y = G(:, c) - Q W, formed in the basis slot of Q_i
-      if (f.mode == M_F64)
-        nn<double>(cx, Qi, f.ldq, (const double*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
-                   sm.W, b, b, m, -1.0, ctrl, i);
-      else
-        nn<float>(cx, Qi, f.ldq, (const float*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
-                  sm.W, b, b, m, -1.0, ctrl, i);
-      if (chol) {
-        // [T; Y^T Y] = [Q, Y]^T Y in one row reduction (Q and the slot of Q_i are adjacent): T
-        // from the first p b entries, the Gram matrix of Y from the last b^2
-        int nch = tn_partials(cx, f.Q, f.ldq, Qi, f.ldq, p + b, b, m, f.red_ws, ctrl, i);
-        if (b <= kLaneCholMax) {
-          // narrow blocks: the Gram matrices in full, each factored by every lane of the apply
-          tn_final(cx, f.red_ws, nch, p + b, b, 0, (int64_t)(p + b) * b, sm.T, b, ctrl, i);
-          cholqr_lane(cx, Qi, f.ldq, m, sm.T + (int64_t)p * b, b, nullptr, sm.R1, false, sm, p,
-                      ctrl, i);
-          // C = Q^T Q_i; Z = Q_i - Q C; two Cholesky QR steps on Z
-          tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
-          if (p > 0)   // (with p = 0 the projection leaves Z = Q_i)
-            nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
-          tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C1, b, ctrl, i);
-          cholqr_lane(cx, Qi, f.ldq, m, sm.C1, b, sm.R1, sm.R2, false, sm, p, ctrl, i);
-          tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C2, b, ctrl, i);
-          cholqr_lane(cx, Qi, f.ldq, m, sm.C2, b, sm.R2, sm.R, true, sm, p, ctrl, i);
+  auto blocked_loop = [&]() {
+    for (int attempt = f.force_loop ? 1 : 0; attempt < 2 && cx.ok(); ++attempt) {
+      const bool chol = (attempt == 0);
+      hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, stream, ctrl, t, l, (int*)nullptr,
+                         (int*)nullptr);
+      cx.chk();
+      for (int i = 0; i < t && cx.ok(); ++i) {
+        const int c0 = i * b, p = c0;
+        double* Qi = f.Q + (int64_t)c0 * f.ldq;
+        // W = B Omega_i  (B^T is n x p)
+        tn(cx, f.Bt, f.ldb, f.om64 + (int64_t)c0 * f.ldo, f.ldo, p, b, n, f.red_ws, sm.W, b, ctrl, i);
+        // Y = G(:, c) - Q W, formed in the basis slot of Q_i
+        if (f.mode == M_F64)
+          nn<double>(cx, Qi, f.ldq, (const double*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
+                     sm.W, b, b, m, -1.0, ctrl, i);
+        else
+          nn<float>(cx, Qi, f.ldq, (const float*)f.G + (int64_t)c0 * f.ldg, f.ldg, f.Q, f.ldq, p,
+                    sm.W, b, b, m, -1.0, ctrl, i);
+        if (chol) {
+          // [T; Y^T Y] = [Q, Y]^T Y in one row reduction (Q and the slot of Q_i are adjacent): T
+          // from the first p b entries, the Gram matrix of Y from the last b^2
+          int nch = tn_partials(cx, f.Q, f.ldq, Qi, f.ldq, p + b, b, m, f.red_ws, ctrl, i);
+          if (b <= kLaneCholMax) {
+            // narrow blocks: the Gram matrices in full, each factored by every lane of the apply
+            tn_final(cx, f.red_ws, nch, p + b, b, 0, (int64_t)(p + b) * b, sm.T, b, ctrl, i);
+            cholqr_lane(cx, Qi, f.ldq, m, sm.T + (int64_t)p * b, b, nullptr, sm.R1, false, sm, p,
+                        ctrl, i);
+            // C = Q^T Q_i; Z = Q_i - Q C; two Cholesky QR steps on Z
+            tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
+            if (p > 0)   // (with p = 0 the projection leaves Z = Q_i)
+              nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+            tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C1, b, ctrl, i);
+            cholqr_lane(cx, Qi, f.ldq, m, sm.C1, b, sm.R1, sm.R2, false, sm, p, ctrl, i);
+            tn(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, sm.C2, b, ctrl, i);
+            cholqr_lane(cx, Qi, f.ldq, m, sm.C2, b, sm.R2, sm.R, true, sm, p, ctrl, i);
+          } else {
+            // wider blocks: the Gram matrix and its factor once, in one workgroup
+            tn_final(cx, f.red_ws, nch, p + b, b, 0, (int64_t)p * b, sm.T, b, ctrl, i);
+            cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)(p + b) * b, (int64_t)p * b, b,
+                   nullptr, sm.R1, false, sm, p, ctrl, i);
+            tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
+            if (p > 0)
+              nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+            nch = tn_partials(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, ctrl, i);
+            cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)b * b, 0, b, sm.R1, sm.R2, false, sm,
+                   p, ctrl, i);
+            nch = tn_partials(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, ctrl, i);
+            cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)b * b, 0, b, sm.R2, sm.R, true, sm, p,
+                   ctrl, i);
+          }
+          if (!cx.ok()) break;
         } else {
-          // wider blocks: the Gram matrix and its factor once, in one workgroup
-          tn_final(cx, f.red_ws, nch, p + b, b, 0, (int64_t)p * b, sm.T, b, ctrl, i);
-          cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)(p + b) * b, (int64_t)p * b, b,
-                 nullptr, sm.R1, false, sm, p, ctrl, i);
+          // T = Q^T Y
+          tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.T, b, ctrl, i);
+          // [Q_i, R_i] = qr(Y), in place
+          tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R1, ctrl, i);
+          // C = Q^T Q_i; Q_i <- Q_i - Q C; [Q_i, R~_i] = qr(Q_i)
           tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
-          if (p > 0)
-            nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
-          nch = tn_partials(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, ctrl, i);
-          cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)b * b, 0, b, sm.R1, sm.R2, false, sm,
-                 p, ctrl, i);
-          nch = tn_partials(cx, Qi, f.ldq, Qi, f.ldq, b, b, m, f.red_ws, ctrl, i);
-          cholqr(cx, Qi, f.ldq, m, f.red_ws, nch, (int64_t)b * b, 0, b, sm.R2, sm.R, true, sm, p,
-                 ctrl, i);
+          nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
+          tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R2, ctrl, i);
+          if (!cx.ok()) break;
+          // R_i = R~_i R_i and the rank guard
+          hipLaunchKernelGGL(k_guard, dim3(1), dim3(256), 0, stream, sm.R1, sm.R2, sm.R, b, i, t,
+                             ctrl);
+          cx.chk();
+          if (p > 0) {
+            hipLaunchKernelGGL(k_add_small, dim3(1), dim3(256), 0, stream, sm.T, sm.W, sm.Wn, p * b,
+                               ctrl, i);
+            cx.chk();
+          }
         }
-        if (!cx.ok()) break;
-      } else {
-        // T = Q^T Y
-        tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.T, b, ctrl, i);
-        // [Q_i, R_i] = qr(Y), in place
-        tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R1, ctrl, i);
-        // C = Q^T Q_i; Q_i <- Q_i - Q C; [Q_i, R~_i] = qr(Q_i)
-        tn(cx, f.Q, f.ldq, Qi, f.ldq, p, b, m, f.red_ws, sm.C, b, ctrl, i);
-        nn<double>(cx, Qi, f.ldq, Qi, f.ldq, f.Q, f.ldq, p, sm.C, b, b, m, -1.0, ctrl, i);
-        tsqr(cx, Qi, f.ldq, m, b, f.tsqr_ws, sm.R2, ctrl, i);
-        if (!cx.ok()) break;
-        // R_i = R~_i R_i and the rank guard
-        hipLaunchKernelGGL(k_guard, dim3(1), dim3(256), 0, stream, sm.R1, sm.R2, sm.R, b, i, t,
-                           ctrl);
-        cx.chk();
-        if (p > 0) {
-          hipLaunchKernelGGL(k_add_small, dim3(1), dim3(256), 0, stream, sm.T, sm.W, sm.Wn, p * b,
-                             ctrl, i);
+        if (!chol) {
+          hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((int64_t)b * m)), dim3(TPB), 0, stream, f.Q,
+                             f.ldq, m, c0, b, ctrl, i);
           cx.chk();
         }
+        // N = H(:, c) - B^T (T + W);  B_i^T = N R_i^{-1} (row-wise solve in the same kernel)
+        nn<double>(cx, f.Bt + (int64_t)c0 * f.ldb, f.ldb, f.H + (int64_t)c0 * f.ldh, f.ldh, f.Bt,
+                   f.ldb, p, sm.Wn, b, b, n, -1.0, ctrl, i, sm.R);
       }
-      if (!chol) {
-        hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((int64_t)b * m)), dim3(TPB), 0, stream, f.Q,
-                           f.ldq, m, c0, b, ctrl, i);
-        cx.chk();
-      }
-      // N = H(:, c) - B^T (T + W);  B_i^T = N R_i^{-1} (row-wise solve in the same kernel)
-      nn<double>(cx, f.Bt + (int64_t)c0 * f.ldb, f.ldb, f.H + (int64_t)c0 * f.ldh, f.ldh, f.Bt,
-                 f.ldb, p, sm.Wn, b, b, n, -1.0, ctrl, i, sm.R);
+      f.path_loop = chol ? 0 : 1;
+      if (!cx.ok()) break;
+      // one wait per loop: the rank decided on the device (it sizes the rest) and the Cholesky QR
+      // flag (pad[0]), which sends the loop round again with Householder TSQR
+      cx.err = read_back(&hc, ctrl, sizeof(Ctrl), stream, f.host_pin, f.host_ev);
+      if (!chol || !cx.ok() || hc.pad[0] == 0) break;
     }
-    f.path_loop = chol ? 0 : 1;
-    if (!cx.ok()) break;
-    // one wait per loop: the rank decided on the device (it sizes the rest) and the Cholesky QR
-    // flag (pad[0]), which sends the loop round again with Householder TSQR
-    cx.err = read_back(&hc, ctrl, sizeof(Ctrl), stream, f.host_pin, f.host_ev);
-    if (!chol || !cx.ok() || hc.pad[0] == 0) break;
-  }
+  };
+  if (!done) blocked_loop();
   if (!cx.ok()) return cx.err;
-  const int L = hc.l_eff;
-  const int kk = (f.k < L) ? f.k : L;
+  int L = hc.l_eff;
+  // The one-block path's only wait: its Cholesky QR2 tests, R's diagonal (the rank guard) and the
+  // R_B tests, read together (sm.sG follows sm.info in the small matrices).  Returns 1 when the
+  // tests rejected G, 2 when the guard keeps fewer than L columns (L is then cut), else 0 with
+  // the R_B tests in rbf.
+  auto check_one_block = [&](int* rbf) -> int {
+    const int64_t dofs = sm.sG - reinterpret_cast<const double*>(sm.info);
+    std::vector<double> rbuf((size_t)(dofs + l));
+    cx.err = read_back(rbuf.data(), sm.info, rbuf.size() * sizeof(double), stream, f.host_pin,
+                       f.host_ev);
+    if (!cx.ok()) return 0;
+    verify = false;
+    const int* fl = reinterpret_cast<const int*>(rbuf.data());
+    if (fl[kObFail] != 0 || fl[kObIll] != 0) return 1;
+    const int keep = one_block_keep(rbuf.data() + dofs, l);
+    if (keep < L) { L = keep; return 2; }
+    rbf[0] = fl[1];
+    rbf[1] = fl[2];
+    return 0;
+  };
+  for (;;) {
+    const int kk = (f.k < L) ? f.k : L;
+    int redo = 0;   // after the one-block check: 1 its tests rejected G, 2 the rank guard cut L
 
-  // ---------------- R_B, then the Jacobi SVD and the outputs.  Cholesky QR2 first (rb_mode 0): its
-  // acceptance tests are read with the final wait, the SVD and the outputs being formed from its
-  // R_B meanwhile; in the rare case it is not accepted, all of it is formed again from shifted
-  // Cholesky QR3 (rb_mode 2), or from Gram-Schmidt + TSQR (rb_mode 1) if a pivot of that fails.
-  for (int rb_mode = (f.force_rb >= 3) ? 0 : f.force_rb; L > 0;) {
-    const double* RBp = nullptr;
-    if (rb_mode == 0) {
-      chol_qr2(cx, f, sm, L, f.force_rb == 4 ? 1 : 0);
-      RBp = sm.RB;
-    } else if (rb_mode == 2) {
-      RBp = chol_qr3_shifted(cx, f, sm, L);
-    }
-    if (!cx.ok()) return cx.err;
-    f.path_rb = (rb_mode == 0) ? 0 : (RBp == nullptr ? 1 : 2);
-    if (RBp == nullptr) {
-      RBp = sm.RB;
-      cx.err = launch_fill_f64(sm.RB, (int64_t)L * L, 0.0, stream);
-      for (int c0 = 0; c0 < L && cx.ok(); c0 += b) {
-        const int w = (L - c0 < b) ? (L - c0) : b;
-        double* Qp = f.Qb + (int64_t)c0 * f.ldb;
-        const double* Bp = f.Bt + (int64_t)c0 * f.ldb;
-        tn(cx, f.Qb, f.ldb, Bp, f.ldb, c0, w, n, f.red_ws, sm.C1, w, nullptr, 0);
-        nn<double>(cx, Qp, f.ldb, Bp, f.ldb, f.Qb, f.ldb, c0, sm.C1, w, w, n, -1.0, nullptr, 0);
-        tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R1, nullptr, 0);
-        tn(cx, f.Qb, f.ldb, Qp, f.ldb, c0, w, n, f.red_ws, sm.C2, w, nullptr, 0);
-        nn<double>(cx, Qp, f.ldb, Qp, f.ldb, f.Qb, f.ldb, c0, sm.C2, w, w, n, -1.0, nullptr, 0);
-        tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R2, nullptr, 0);
-        if (!cx.ok()) break;
-        hipLaunchKernelGGL(k_rb_assemble, dim3(1), dim3(256), 0, stream, sm.C1, sm.C2, sm.R1,
-                           sm.R2, sm.RB, L, c0, w);
+    // ---------------- R_B, then the Jacobi SVD and the outputs.  Cholesky QR2 first (rb_mode 0): its
+    // acceptance tests are read with the final wait, the SVD and the outputs being formed from its
+    // R_B meanwhile; in the rare case it is not accepted, all of it is formed again from shifted
+    // Cholesky QR3 (rb_mode 2), or from Gram-Schmidt + TSQR (rb_mode 1) if a pivot of that fails.
+    for (int rb_mode = (f.force_rb >= 3) ? 0 : f.force_rb; L > 0;) {
+      if (verify && rb_mode == 2) {
+        // shifted Cholesky QR3 takes the H storage as scratch: settle the one-block path first
+        int rbf[2];
+        redo = check_one_block(rbf);
+        if (!cx.ok()) return cx.err;
+        if (redo != 0) break;
+      }
+      const double* RBp = nullptr;
+      if (rb_mode == 0) {
+        chol_qr2(cx, f, sm, L, f.force_rb == 4 ? 1 : 0);
+        RBp = sm.RB;
+      } else if (rb_mode == 2) {
+        RBp = chol_qr3_shifted(cx, f, sm, L);
+      }
+      if (!cx.ok()) return cx.err;
+      f.path_rb = (rb_mode == 0) ? 0 : (RBp == nullptr ? 1 : 2);
+      if (RBp == nullptr) {
+        RBp = sm.RB;
+        cx.err = launch_fill_f64(sm.RB, (int64_t)L * L, 0.0, stream);
+        for (int c0 = 0; c0 < L && cx.ok(); c0 += b) {
+          const int w = (L - c0 < b) ? (L - c0) : b;
+          double* Qp = f.Qb + (int64_t)c0 * f.ldb;
+          const double* Bp = f.Bt + (int64_t)c0 * f.ldb;
+          tn(cx, f.Qb, f.ldb, Bp, f.ldb, c0, w, n, f.red_ws, sm.C1, w, nullptr, 0);
+          nn<double>(cx, Qp, f.ldb, Bp, f.ldb, f.Qb, f.ldb, c0, sm.C1, w, w, n, -1.0, nullptr, 0);
+          tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R1, nullptr, 0);
+          tn(cx, f.Qb, f.ldb, Qp, f.ldb, c0, w, n, f.red_ws, sm.C2, w, nullptr, 0);
+          nn<double>(cx, Qp, f.ldb, Qp, f.ldb, f.Qb, f.ldb, c0, sm.C2, w, w, n, -1.0, nullptr, 0);
+          tsqr(cx, Qp, f.ldb, n, w, f.tsqr_ws, sm.R2, nullptr, 0);
+          if (!cx.ok()) break;
+          hipLaunchKernelGGL(k_rb_assemble, dim3(1), dim3(256), 0, stream, sm.C1, sm.C2, sm.R1,
+                             sm.R2, sm.RB, L, c0, w);
+          cx.chk();
+        }
+        if (!cx.ok()) return cx.err;
+      }
+      // ---------------- Jacobi SVD of R_B^T
+      {
+        const size_t jshm = jacobi_lds_bytes(L);
+        if (jshm > (size_t)kJacobiLds) return hipErrorInvalidValue;   // l <= JMAX keeps it inside
+        const dim3 g1(1), bj(kJacobiThreads);
+        switch (jacobi_epl(L)) {
+  #define SK_EPL_CASE(E)                                                                        \
+          case E:                                                                               \
+            hipLaunchKernelGGL(k_jacobi<E>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info, \
+                               sm.sig, sm.perm, sm.Jm);                                         \
+            break;
+          SK_JACOBI_EPLS(SK_EPL_CASE)
+  #undef SK_EPL_CASE
+          default: break;
+        }
+      }
+      cx.chk();
+      if (!cx.ok()) return cx.err;
+      hipLaunchKernelGGL(k_gather, dim3(cdiv(L * kk, 256)), dim3(256), 0, stream, sm.Wm, L, L,
+                         sm.perm, sm.sig, kk, sm.Jk, sm.Wk, f.k, f.S);
+      cx.chk();
+      // V (column-major temp in the Q_B storage, free once R_B is formed; H stays intact for a
+      // blocked loop that may still have to run) = B^T W S^-2 in column slices of 16, its signs,
+      // then the row-major outputs
+      double* Vt = f.Qb;
+      const dim3 gv((unsigned)cdiv<int64_t>(n, kNnThreads), cdiv(kk, 16));
+      hipLaunchKernelGGL((k_nn_update<double, 16>), gv, dim3(kNnThreads), 0, stream, Vt, f.ldb,
+                         (const double*)nullptr, 0, f.Bt, f.ldb, L, sm.Jk, kk, 16, n, 1.0,
+                         (const Ctrl*)nullptr, 0, (const double*)nullptr, kk, 0);
+      cx.chk();
+      if (!cx.ok()) return cx.err;
+      hipLaunchKernelGGL(k_signs, dim3(kk), dim3(TPB), 0, stream, Vt, f.ldb, n, sm.sgn);
+      cx.chk();
+      if (!cx.ok()) return cx.err;
+      hipLaunchKernelGGL(k_signed_transpose, dim3(grid_for(n * f.k)), dim3(TPB), 0, stream, Vt,
+                         f.ldb, kk, f.k, sm.sgn, n, f.V, f.ldv);
+      cx.chk();
+      if (f.U && cx.ok()) {
+        const dim3 gu(grid_for(m, TPB, 4096), cdiv(f.k, 16));
+        hipLaunchKernelGGL(k_write_rows, gu, dim3(TPB), (size_t)L * 16 * sizeof(double), stream,
+                           f.Q, f.ldq, L, sm.Wk, kk, f.k, sm.sgn, m, f.U, f.ldu, 0);
         cx.chk();
       }
       if (!cx.ok()) return cx.err;
-    }
-    // ---------------- Jacobi SVD of R_B^T
-    {
-      const size_t jshm = jacobi_lds_bytes(L);
-      if (jshm > (size_t)kJacobiLds) return hipErrorInvalidValue;   // l <= JMAX keeps it inside
-      const dim3 g1(1), bj(kJacobiThreads);
-      switch (jacobi_epl(L)) {
-#define SK_EPL_CASE(E)                                                                        \
-        case E:                                                                               \
-          hipLaunchKernelGGL(k_jacobi<E>, g1, bj, jshm, stream, RBp, L, L, sm.Wm, L, sm.info, \
-                             sm.sig, sm.perm, sm.Jm);                                         \
-          break;
-        SK_JACOBI_EPLS(SK_EPL_CASE)
-#undef SK_EPL_CASE
-        default: break;
+      int hflags[2] = {1, 1};
+      if (verify) {
+        redo = check_one_block(hflags);
+        if (!cx.ok()) return cx.err;
+        if (redo != 0) break;
+      } else {
+        if (rb_mode != 0) break;
+        cx.err = read_back(hflags, sm.info + 1, 2 * sizeof(int), stream, f.host_pin, f.host_ev);
+        if (!cx.ok()) return cx.err;
       }
+      if (rb_mode != 0) break;
+      if (hflags[0] == 0 && hflags[1] == 0 && f.force_rb != 3) break;
+      rb_mode = 2;
     }
-    cx.chk();
-    if (!cx.ok()) return cx.err;
-    hipLaunchKernelGGL(k_gather, dim3(cdiv(L * kk, 256)), dim3(256), 0, stream, sm.Wm, L, L,
-                       sm.perm, sm.sig, kk, sm.Jk, sm.Wk, f.k, f.S);
-    cx.chk();
-    // V (column-major temp in the H storage) = B^T W S^-2 in column slices of 16, its signs, then
-    // the row-major outputs
-    double* Vt = const_cast<double*>(f.H);
-    const dim3 gv((unsigned)cdiv<int64_t>(n, kNnThreads), cdiv(kk, 16));
-    hipLaunchKernelGGL((k_nn_update<double, 16>), gv, dim3(kNnThreads), 0, stream, Vt, f.ldh,
-                       (const double*)nullptr, 0, f.Bt, f.ldb, L, sm.Jk, kk, 16, n, 1.0,
-                       (const Ctrl*)nullptr, 0, (const double*)nullptr, kk, 0);
-    cx.chk();
-    if (!cx.ok()) return cx.err;
-    hipLaunchKernelGGL(k_signs, dim3(kk), dim3(TPB), 0, stream, Vt, f.ldh, n, sm.sgn);
-    cx.chk();
-    if (!cx.ok()) return cx.err;
-    hipLaunchKernelGGL(k_signed_transpose, dim3(grid_for(n * f.k)), dim3(TPB), 0, stream, Vt,
-                       f.ldh, kk, f.k, sm.sgn, n, f.V, f.ldv);
-    cx.chk();
-    if (f.U && cx.ok()) {
-      const dim3 gu(grid_for(m, TPB, 4096), cdiv(f.k, 16));
-      hipLaunchKernelGGL(k_write_rows, gu, dim3(TPB), (size_t)L * 16 * sizeof(double), stream,
-                         f.Q, f.ldq, L, sm.Wk, kk, f.k, sm.sgn, m, f.U, f.ldu, 0);
+    if (redo == 1) {
+      // G is too ill-conditioned for Cholesky QR2: the blocked loop, and its SVD
+      f.Q = q_loop;
+      blocked_loop();
+      if (!cx.ok()) return cx.err;
+      L = hc.l_eff;
+      continue;
+    }
+    if (redo == 2) {
+      // fewer columns pass the rank guard: the SVD of the leading ones
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, stream, &ctrl->l_eff, L);
       cx.chk();
+      if (!cx.ok()) return cx.err;
+      continue;
     }
-    if (!cx.ok()) return cx.err;
-    if (rb_mode != 0) break;
-    int hflags[2] = {1, 1};
-    cx.err = read_back(hflags, sm.info + 1, 2 * sizeof(int), stream, f.host_pin, f.host_ev);
-    if (!cx.ok()) return cx.err;
-    if (hflags[0] == 0 && hflags[1] == 0 && f.force_rb != 3) break;
-    rb_mode = 2;
+    break;
   }
   if (L <= 0) {
     // rank 0: all outputs zero
