@@ -562,9 +562,10 @@ def roofline(res, m, n, l, mode):
     """Dominant streaming kernel against its roof: HBM for the BF16/FP8 paths (algorithmic bytes
     = the block's FP32 bytes, read once per launch), the matrix-core peak for FP32/FP64
     (algorithmic flops = 2 l per element of the block, per launch)."""
+    g2 = "k_gemm2" if mode == "f64" else "k_gemm2w + k_hsum"    # FP64 keeps the strip kernel
     dom, t = ("gemm1: g = a Omega (k_gemm1 + k_reduce1)", res["gemm1_ms"]) \
         if res["gemm1_ms"] >= res["gemm2_ms"] else \
-        ("gemm2: H += a^T g (k_gemm2w + k_hsum)", res["gemm2_ms"])
+        (f"gemm2: H += a^T g ({g2})", res["gemm2_ms"])
     if not t > 0:
         return None
     elems_per_launch = m * n / res["nblocks"]
