@@ -249,12 +249,9 @@ __global__ __launch_bounds__(TPB) void k_tn_mfma(const double* __restrict__ X, i
 // matrix cores (the operand of tile nt's columns is that of tile nt's rows), and the partials go
 // out in k_tn_mfma's slice layout (column slices of 32, rows a < 32 (y + 1) of slice y), so
 // k_tn_final_gram sums them unchanged; the slice rows below the diagonal tiles, which nothing
-// reads, are written as zeros.  The waves' sums are combined through LDS in rounds of kGramRound
-// tiles.  The next rows are loaded after the matrix-core work that frees the operand registers:
-// at one wave per SIMD the product is bound by the matrix cores (about 124 16x16x4 FP64 MFMAs per
-// 16 rows and 112 columns), which the loads of the following rows overlap.
+// reads, are written as zeros.  The layout of the waves over rows and tiles is given with
+// k_gram_mfma below.
 __host__ __device__ constexpr int gram_tile_count(int MT) { return MT * (MT + 1) / 2; }
-constexpr int kGramRound = 16;
 
 template <typename XT, int MT>
 __device__ __forceinline__ void gram_fetch(const XT* __restrict__ X, int64_t ldx, int L,
@@ -394,8 +391,9 @@ __global__ __launch_bounds__(kGramMfmaThreads) void k_gram_mfma(const XT* __rest
 // dimension ldw), L <= 16 MT, on the FP64 matrix cores, reading X once: every workgroup stages W,
 // zero-padded to 16 MT, in LDS, and its waves take 16-row blocks of its row range.  The MFMA k
 // index is the column a of X (lane (r16, g) supplies X[r0 + r16][4 s + g]); output tile nt only
-// meets k < 16 (nt + 1), W being upper triangular.  The next block's operands are loaded before
-// the current block's matrix-core work.  Rows past `rows` are read clamped and not written.
+// meets k < 16 (nt + 1), W being upper triangular.  Eight waves, two per SIMD, each with one
+// row buffer: one wave's loads overlap the other's matrix-core work.  Rows past `rows` are read
+// clamped and not written.
 template <typename XT, int MT>
 __device__ __forceinline__ void rmul_fetch(const XT* __restrict__ X, int64_t ldx, int L,
                                            int64_t row, int g, double (&xa)[MT][4]) {
