@@ -2735,6 +2735,7 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   if (!done) blocked_loop();
   if (!cx.ok()) return cx.err;
   int L = hc.l_eff;
+  bool fresh = false;   // the last wait also read the control block, and no work followed it
   // The one-block path's only wait: its Cholesky QR2 tests, R's diagonal (the rank guard) and the
   // R_B tests, read together (sm.sG follows sm.info in the small matrices).  Returns 1 when the
   // tests rejected G, 2 when the guard keeps fewer than L columns (L is then cut), else 0 with
@@ -2742,9 +2743,10 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
   auto check_one_block = [&](int* rbf) -> int {
     const int64_t dofs = sm.sG - reinterpret_cast<const double*>(sm.info);
     std::vector<double> rbuf((size_t)(dofs + l));
-    cx.err = read_back(rbuf.data(), sm.info, rbuf.size() * sizeof(double), stream, f.host_pin,
-                       f.host_ev);
+    cx.err = read_back2(rbuf.data(), sm.info, rbuf.size() * sizeof(double), f.ctrl_host, ctrl,
+                        f.ctrl_host ? sizeof(Ctrl) : 0, stream, f.host_pin, f.host_ev);
     if (!cx.ok()) return 0;
+    fresh = true;
     verify = false;
     const int* fl = reinterpret_cast<const int*>(rbuf.data());
     if (fl[kObFail] != 0 || fl[kObIll] != 0) return 1;
@@ -2770,6 +2772,7 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
         if (!cx.ok()) return cx.err;
         if (redo != 0) break;
       }
+      fresh = false;
       const double* RBp = nullptr;
       if (rb_mode == 0) {
         chol_qr2(cx, f, sm, L, f.force_rb == 4 ? 1 : 0);
@@ -2850,13 +2853,16 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
         if (redo != 0) break;
       } else {
         if (rb_mode != 0) break;
-        cx.err = read_back(hflags, sm.info + 1, 2 * sizeof(int), stream, f.host_pin, f.host_ev);
+        cx.err = read_back2(hflags, sm.info + 1, 2 * sizeof(int), f.ctrl_host, ctrl,
+                            f.ctrl_host ? sizeof(Ctrl) : 0, stream, f.host_pin, f.host_ev);
         if (!cx.ok()) return cx.err;
+        fresh = true;
       }
       if (rb_mode != 0) break;
       if (hflags[0] == 0 && hflags[1] == 0 && f.force_rb != 3) break;
       rb_mode = 2;
     }
+    if (redo != 0) fresh = false;
     if (redo == 1) {
       // G is too ill-conditioned for Cholesky QR2: the blocked loop, and its SVD
       f.Q = q_loop;
@@ -2875,6 +2881,7 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
     break;
   }
   if (L <= 0) {
+    fresh = false;
     // rank 0: all outputs zero
     double zero_s = 0.0;
     (void)zero_s;
@@ -2890,7 +2897,8 @@ hipError_t run_finalize(FinalizeArgs& f, hipStream_t stream) {
       }
     }
   }
-  // the caller's read-back of the control block waits for the outputs
+  // the caller reads the control block with a wait of its own unless the last wait read it
+  f.ctrl_read = fresh && f.ctrl_host != nullptr && cx.ok();
   return cx.err;
 }
 

@@ -121,6 +121,9 @@ hipError_t launch_copy_omega_out(const double* om64, int64_t ldo, int64_t n, int
 constexpr size_t kHostPinBytes = 4096;
 hipError_t read_back(void* dst, const void* src, size_t bytes, hipStream_t s, void* pin,
                      hipEvent_t ev);
+// As read_back, for two device ranges at once (one wait): src1 to dst1 and src2 to dst2.
+hipError_t read_back2(void* dst1, const void* src1, size_t bytes1, void* dst2, const void* src2,
+                      size_t bytes2, hipStream_t s, void* pin, hipEvent_t ev);
 
 struct FinalizeArgs {
   int mode;
@@ -149,6 +152,8 @@ struct FinalizeArgs {
                                      //      1 Gram-Schmidt + TSQR
   void* host_pin = nullptr;          // pinned host staging of the read-backs (kHostPinBytes), or null
   hipEvent_t host_ev = nullptr;      // event the read-backs poll, or null
+  Ctrl* ctrl_host = nullptr;         // out, if not null: the control block, read with the last
+  bool ctrl_read = false;            //   wait when no device work followed it (ctrl_read set)
 };
 // Power scheme with P = 1: Omega_2 = sqrt(n) orth(H) (FP64, column-major) for the second pass.
 struct PowerArgs {

@@ -816,9 +816,11 @@ sketch_status sketch_server_finalize(sketch_server_t s, uint64_t stream_id, doub
       f.ldv = ldv;
       f.host_pin = s->fin_pin;
       f.host_ev = s->fin_ev;
-      e = run_finalize(f, s->fin_stream);
       Ctrl hc{};
-      if (e == hipSuccess) e = read_back(&hc, ctrl, sizeof(Ctrl), s->fin_stream, s->fin_pin, s->fin_ev);
+      f.ctrl_host = &hc;
+      e = run_finalize(f, s->fin_stream);
+      if (e == hipSuccess && !f.ctrl_read)
+        e = read_back(&hc, ctrl, sizeof(Ctrl), s->fin_stream, s->fin_pin, s->fin_ev);
       if (e == hipSuccess) {
         rank = hc.l_eff;
         if (hc.nonfinite) result = set_error(SKETCH_E_NONFINITE, "a block of the stream held NaN or Inf");

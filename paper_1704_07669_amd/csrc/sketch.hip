@@ -368,10 +368,12 @@ sketch_status finalize_core(sketch_t h, double* S_dev, double* U_dev, int64_t ld
   f.mu = c.centre ? h->at<double>(L.off_mu) : nullptr;
   f.host_pin = h->fin_pin;
   f.host_ev = h->fin_ev;
+  Ctrl hc;
+  f.ctrl_host = &hc;
   if (e == hipSuccess) e = run_finalize(f, h->stream);
   if (e == hipSuccess && h->prof) e = hipEventRecord(fb, h->stream);
-  Ctrl hc;
-  if (e == hipSuccess) e = read_back(&hc, h->ctrl(), sizeof(Ctrl), h->stream, h->fin_pin, h->fin_ev);
+  if (e == hipSuccess && !f.ctrl_read)
+    e = read_back(&hc, h->ctrl(), sizeof(Ctrl), h->stream, h->fin_pin, h->fin_ev);
   if (e != hipSuccess) return h->dev_fail(e, "finalize");
   if (h->prof) h->recs.push_back({fa, fb, nullptr, 2});
   h->phase = 2;

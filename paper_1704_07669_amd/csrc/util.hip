@@ -107,6 +107,29 @@ hipError_t read_back(void* dst, const void* src, size_t bytes, hipStream_t s, vo
   return e;
 }
 
+hipError_t read_back2(void* dst1, const void* src1, size_t bytes1, void* dst2, const void* src2,
+                      size_t bytes2, hipStream_t s, void* pin, hipEvent_t ev) {
+  const size_t off = (bytes1 + 63) & ~(size_t)63;
+  if (pin == nullptr || ev == nullptr || off + bytes2 > kHostPinBytes) {
+    hipError_t e = read_back(dst1, src1, bytes1, s, nullptr, nullptr);
+    if (e == hipSuccess) e = read_back(dst2, src2, bytes2, s, nullptr, nullptr);
+    return e;
+  }
+  uint8_t* p = static_cast<uint8_t*>(pin);
+  hipError_t e = bytes1 ? hipMemcpyAsync(p, src1, bytes1, hipMemcpyDeviceToHost, s) : hipSuccess;
+  if (e == hipSuccess && bytes2)
+    e = hipMemcpyAsync(p + off, src2, bytes2, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(ev, s);
+  if (e == hipSuccess) {
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    if (e == hipSuccess) (void)hipGetLastError();   // (as in read_back)
+  }
+  if (e == hipSuccess && bytes1) memcpy(dst1, p, bytes1);
+  if (e == hipSuccess && bytes2) memcpy(dst2, p + off, bytes2);
+  return e;
+}
+
 hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(count)), dim3(256), 0, s, p, count, v);
