@@ -1285,7 +1285,7 @@ __global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __re
   double* g0 = ri + LP;                  // the diagonal the factorisation started from
   __shared__ int bad;
   __shared__ double shs;
-  __shared__ double prow[16];            // the current pivot row of a diagonal block
+  __shared__ double prow[32];            // the current two pivot rows of a diagonal block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
   // the upper triangle of Gm, zeros below it, the identity on the padding (all 112^2 entries in
   // one batch of loads at the largest size)
@@ -1331,23 +1331,34 @@ __global__ __launch_bounds__(kCholBlkThreads) void k_chol_blk(const double* __re
       double piv[16];                            // the pivots, for the conditioning test after
 #pragma unroll
       for (int p = 0; p < 16; ++p) piv[p] = 1.0;
+      // two pivots per step: P = k0 + p and P + 1.  R[P][P+1] and the second pivot come from lane
+      // broadcasts, both rows of R go through LDS together, and the trailing entries take both
+      // updates in pivot order (the same operations as one pivot at a time, so the same bits)
 #pragma unroll
-      for (int p = 0; p < 16; ++p) {
+      for (int p = 0; p < 16; p += 2) {
         const int P = k0 + p;
-        const double d = dpp::lane(col[p], p);   // A[P][P], the same in every lane
-        piv[p] = d;
-        if (P < L && ((force_fail && P == 0) || !(d > 0.0) || !(d < INFINITY))) fl = true;
+        const double d0 = dpp::lane(col[p], p);       // A[P][P], the same in every lane
+        piv[p] = d0;
+        if (P < L && ((force_fail && P == 0) || !(d0 > 0.0) || !(d0 < INFINITY))) fl = true;
         if (fl) break;
-        const double r = rsq_nr(d), rp = d * r;  // refined 1/sqrt(d); R[P][P] = d / sqrt(d)
-        if (lane == 0) { rd[P] = rp; ri[P] = r; }
-        col[p] = (c == p) ? rp : col[p] * r;
-        // row P of R to every lane through LDS (one store per lane, broadcast loads; one wave's
-        // LDS accesses execute in order, so the loads see the stores and the next pivot's stores
-        // follow these loads)
-        if (c < 16) prow[c] = col[p];
+        const double e = dpp::lane(col[p], p + 1);    // A[P][P+1]
+        const double d1 = dpp::lane(col[p + 1], p + 1);
+        const double r0 = rsq_nr(d0), rp0 = d0 * r0;  // refined 1/sqrt(d); R[P][P] = d / sqrt(d)
+        const double r01 = e * r0;                    // R[P][P+1]
+        const double d1u = fma(-r01, r01, d1);        // the second pivot after the first's update
+        piv[p + 1] = d1u;
+        if (P + 1 < L && (!(d1u > 0.0) || !(d1u < INFINITY))) fl = true;
+        if (fl) break;
+        const double r1 = rsq_nr(d1u), rp1 = d1u * r1;
+        if (lane == 0) { rd[P] = rp0; ri[P] = r0; rd[P + 1] = rp1; ri[P + 1] = r1; }
+        col[p] = (c == p) ? rp0 : col[p] * r0;                                   // row P of R
+        col[p + 1] = (c == p + 1) ? rp1 : fma(-r01, col[p], col[p + 1]) * r1;  // row P + 1
+        // both rows to every lane through LDS (one wave's LDS accesses execute in order)
+        if (c < 16) { prow[c] = col[p]; prow[16 + c] = col[p + 1]; }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int i = p + 1; i < 16; ++i) col[i] = fma(-prow[i], col[p], col[i]);   // R[P][k0 + i]
+        for (int i = p + 2; i < 16; ++i)
+          col[i] = fma(-prow[16 + i], col[p + 1], fma(-prow[i], col[p], col[i]));
         __builtin_amdgcn_wave_barrier();
       }
       if (c < 16)
