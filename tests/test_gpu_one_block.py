@@ -97,6 +97,27 @@ def test_one_block_rank_guard(gpu_lib, rank):
     assert oracle.sin_theta_max(V, out["V"][:, :rank]) < 1e-9
 
 
+def test_one_block_rank_guard_cuts_an_accepted_basis(gpu_lib):
+    """The last column of Omega scaled by 1e-11: G's last column is tiny but independent of the
+    others, so Cholesky QR2 accepts G (Cholesky QR is unaffected by column scaling), while the
+    rank guard (R_jj > 1e-10 R_00) drops that column.  The finalize, which went ahead with all l
+    columns before reading R's diagonal, forms the SVD again from the leading l - 1, and must
+    match the reference run with the same Omega (b = l)."""
+    m, n, k, l = 900, 400, 10, 24
+    sig = synth.noisy_spectrum(synth.exp_spectrum(n, 10.0), 1e-6, 31)
+    A, _, s, _ = synth.small_matrix(m, n, sig, 31)
+    Om = synth.gaussian_omega(n, l, 32)
+    Om[:, -1] *= 1e-11
+    out = run_gpu(A, Om, k, l, "f64", [450, 450], src="f64")
+    assert out["paths"][0] == 2                  # the one-block path kept G
+    ref = oracle.single_pass_pca(split_blocks(A, [450, 450]), Om, k, l)
+    assert ref.rank == l - 1
+    assert out["rank"] == ref.rank
+    assert np.max(oracle.rel_sigma_error(out["S"], ref.S)) < 1e-10
+    assert oracle.sin_theta_max(ref.V, out["V"]) < 1e-8
+    assert oracle.sin_theta_max(ref.U, out["U"]) < 1e-8
+
+
 def test_one_block_ill_conditioned_falls_back(gpu_lib):
     """Type 5 spectrum, l = 60: G's Gram matrix is too ill conditioned for unshifted Cholesky QR
     (cond(G) ~ 1e6), so the blocked loop runs, and matches the reference."""
